@@ -1,0 +1,1070 @@
+/*
+ * Plain FP64 CPU oracle for the lattice Boltzmann + Oldroyd-B method of
+ * Kuron, Stewart, de Graaf and Holm, "An extensible lattice Boltzmann method
+ * for viscoelastic flows: complex and moving boundaries in Oldroyd-B fluids"
+ * (arXiv 2009.12279).
+ *
+ * TEST INFRASTRUCTURE ONLY: the slow reference the GPU library is checked
+ * against.  It is deliberately structured unlike the GPU path: raw (not
+ * deviation) populations, push streaming, one whole-lattice sweep per phase,
+ * everything in double precision.
+ *
+ * One time step n -> n+1, phase by phase:
+ *   S0 boundary velocity of every solid node (Section 3.4, surface velocity)
+ *   S1 polymer force from tau^n (Section 3.3, force discretisation with
+ *      constant stress extrapolation at boundaries)
+ *   S2 moments and equilibrium (Section 3.1, macroscopic velocity with half force)
+ *   S3 TRT collision with Guo forcing (Section 3.1)
+ *   S4 push streaming with link bounce-back plus the moving-wall term
+ *      (Section 3.1, velocity boundary condition) and the momentum exchanged
+ *      with every obstacle (Section 3.4)
+ *   S5 finite-volume stress update with tau^n and u^n (Section 3.3: source
+ *      from the Oldroyd-B equation, corner-transport-upwind face fluxes,
+ *      zero flux through boundary faces)
+ *   S6 rigid-body update by symplectic Euler (Section 3.4)
+ *   S7 fluid/solid conversion of cells a moving particle covers or uncovers,
+ *      with momentum and stress bookkeeping (Section 3.4)
+ *
+ * Readings taken where the paper is silent or garbled:
+ *   - equilibrium: the standard second-order form 1 + 3cu + 9/2 (cu)^2 - 3/2 u^2
+ *     (the printed 1/6 coefficients are garbled);
+ *   - omega+ = 1/(3 eta_n + 1/2); omega- from (1/omega+ - 1/2)(1/omega- - 1/2) = magic;
+ *   - Guo forcing: F is a force density (no 1/rho); the symmetric part of the
+ *     source is scaled by (1 - omega+/2) and the antisymmetric part by
+ *     (1 - omega-/2), so a step injects exactly F of momentum;
+ *   - u = (sum f c + F/2)/rho;
+ *   - the density in the moving-wall term is that of the fluid cell;
+ *   - the force on an obstacle is sum over links c_j (f*_j + f_reflected), with
+ *     c_j pointing from fluid into the obstacle; lever arm = solid node - centre;
+ *   - the polymer traction -sum n.tau(x_fluid) over boundary faces acts on the
+ *     obstacle, which balances the boundary terms of the discrete polymer force;
+ *   - the velocity gradient uses the boundary velocity at solid nodes;
+ *   - face flux = tau(donor) * max(u.e,0) * prod_{a perp e}(1-|u_a|) (the exact
+ *     face overlap of the displaced cell; edge and corner overlaps dropped);
+ *   - the tau div(u) source term is omitted;
+ *   - a cell is inside a sphere when |x - R|^2 < r^2 (cell centres at integer
+ *     coordinates, minimum image on periodic axes);
+ *   - conversion: covers before uncovers; the neighbours that take part are the
+ *     D3Q19 neighbours that are fluid both before and after the conversion;
+ *     the refill density is their mean density (1 if none); the momentum of a
+ *     covered cell is that of its populations; covered/uncovered momentum goes
+ *     to the particle in the next step's update.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define Q 19
+#define MAXP 192
+#define PART0 64
+
+static int C[Q][3];
+static double W[Q];
+static int OPP[Q];
+static int REST = -1;
+static int tables_ready = 0;
+
+/* Build the velocity set by enumerating {-1,0,1}^3 and keeping |c|^2 <= 2:
+ * the rest velocity, the 6 face and the 12 edge neighbours (Section 3.1). */
+static void build_tables(void)
+{
+    if (tables_ready)
+        return;
+    int q = 0;
+    for (int cz = -1; cz <= 1; ++cz)
+        for (int cy = -1; cy <= 1; ++cy)
+            for (int cx = -1; cx <= 1; ++cx) {
+                int c2 = cx * cx + cy * cy + cz * cz;
+                if (c2 > 2)
+                    continue;
+                C[q][0] = cx;
+                C[q][1] = cy;
+                C[q][2] = cz;
+                W[q] = (c2 == 0) ? 1.0 / 3.0 : (c2 == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
+                if (c2 == 0)
+                    REST = q;
+                ++q;
+            }
+    for (int i = 0; i < Q; ++i)
+        for (int j = 0; j < Q; ++j)
+            if (C[j][0] == -C[i][0] && C[j][1] == -C[i][1] && C[j][2] == -C[i][2])
+                OPP[i] = j;
+    tables_ready = 1;
+}
+
+int or_velocity(int i, int c[3], double *w)
+{
+    build_tables();
+    if (i >= 0 && i < Q) {
+        if (c) {
+            c[0] = C[i][0];
+            c[1] = C[i][1];
+            c[2] = C[i][2];
+        }
+        if (w)
+            *w = W[i];
+    }
+    return Q;
+}
+
+static int n_threads = 0;
+void or_set_threads(int n) { n_threads = n; }
+int or_get_threads(void)
+{
+#ifdef _OPENMP
+    return n_threads > 0 ? n_threads : omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------ */
+/* Section 3.1: equilibrium, relaxation rates, TRT collision with Guo forcing */
+
+void or_equilibrium(double rho, const double u[3], double feq[19])
+{
+    build_tables();
+    double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    for (int i = 0; i < Q; ++i) {
+        double cu = C[i][0] * u[0] + C[i][1] * u[1] + C[i][2] * u[2];
+        feq[i] = W[i] * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+    }
+}
+
+void or_rates(double eta, double beta, double magic, double *omega_plus, double *omega_minus)
+{
+    double eta_n = (1.0 - beta) * eta;
+    double wp = 1.0 / (3.0 * eta_n + 0.5);
+    double wm = wp;
+    if (magic >= 0.0) {
+        double lam_plus = 1.0 / wp - 0.5;
+        wm = 1.0 / (0.5 + magic / lam_plus);
+    }
+    *omega_plus = wp;
+    *omega_minus = wm;
+}
+
+void or_collide_cell(const double f[19], const double F[3], double omega_plus,
+                     double omega_minus, double fout[19], double *rho_out, double u_out[3])
+{
+    build_tables();
+    double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < Q; ++i) {
+        rho += f[i];
+        for (int a = 0; a < 3; ++a)
+            j[a] += f[i] * C[i][a];
+    }
+    double u[3];
+    for (int a = 0; a < 3; ++a)
+        u[a] = (j[a] + 0.5 * F[a]) / rho;
+    double feq[Q], S[Q];
+    or_equilibrium(rho, u, feq);
+    double uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
+    for (int i = 0; i < Q; ++i) {
+        double cu = C[i][0] * u[0] + C[i][1] * u[1] + C[i][2] * u[2];
+        double cF = C[i][0] * F[0] + C[i][1] * F[1] + C[i][2] * F[2];
+        S[i] = W[i] * (3.0 * cF + 9.0 * cu * cF - 3.0 * uF);
+    }
+    for (int i = 0; i < Q; ++i) {
+        int o = OPP[i];
+        double fp = 0.5 * (f[i] + f[o]), fm = 0.5 * (f[i] - f[o]);
+        double ep = 0.5 * (feq[i] + feq[o]), em = 0.5 * (feq[i] - feq[o]);
+        double sp = 0.5 * (S[i] + S[o]), sm = 0.5 * (S[i] - S[o]);
+        fout[i] = f[i] - omega_plus * (fp - ep) - omega_minus * (fm - em) +
+                  (1.0 - 0.5 * omega_plus) * sp + (1.0 - 0.5 * omega_minus) * sm;
+    }
+    if (rho_out)
+        *rho_out = rho;
+    if (u_out)
+        for (int a = 0; a < 3; ++a)
+            u_out[a] = u[a];
+}
+
+/* ------------------------------------------------------------------ */
+/* Lattice geometry helpers */
+
+static long cell(int nx, int ny, int x, int y, int z) { return x + (long)nx * (y + (long)ny * z); }
+
+static int wrap(int v, int n) { return ((v % n) + n) % n; }
+
+/* Neighbour of (x,y,z) in direction d, always wrapped into the box (the
+ * caller guarantees that non-periodic axes have solid end layers, so fluid
+ * cells never reach across them). */
+static long nbr(int nx, int ny, int nz, int x, int y, int z, const int d[3])
+{
+    return cell(nx, ny, wrap(x + d[0], nx), wrap(y + d[1], ny), wrap(z + d[2], nz));
+}
+
+static const int FACE[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
+
+/* symmetric 3x3 <-> 6 components xx,yy,zz,xy,xz,yz */
+static void tau_get(const double *tau, long N, long n, double t[3][3])
+{
+    t[0][0] = tau[0 * N + n];
+    t[1][1] = tau[1 * N + n];
+    t[2][2] = tau[2 * N + n];
+    t[0][1] = t[1][0] = tau[3 * N + n];
+    t[0][2] = t[2][0] = tau[4 * N + n];
+    t[1][2] = t[2][1] = tau[5 * N + n];
+}
+
+static void tau_put(double *tau, long N, long n, double t[3][3])
+{
+    tau[0 * N + n] = t[0][0];
+    tau[1 * N + n] = t[1][1];
+    tau[2 * N + n] = t[2][2];
+    tau[3 * N + n] = t[0][1];
+    tau[4 * N + n] = t[0][2];
+    tau[5 * N + n] = t[1][2];
+}
+
+/* ------------------------------------------------------------------ */
+/* Section 3.3: polymer force and finite-volume stress update */
+
+void or_polymer_force(int nx, int ny, int nz, const unsigned char *mask, const double *tau,
+                      double *fp)
+{
+    long N = (long)nx * ny * nz;
+#pragma omp parallel for schedule(static) num_threads(or_get_threads())
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                long n = cell(nx, ny, x, y, z);
+                double F[3] = {0.0, 0.0, 0.0};
+                if (mask[n] == 0) {
+                    double t0[3][3];
+                    tau_get(tau, N, n, t0);
+                    /* F_j = sum over faces of tau at the face midpoint times the
+                     * outward normal; the midpoint value is the average of the two
+                     * cells, and a solid neighbour takes this cell's stress. */
+                    for (int k = 0; k < 6; ++k) {
+                        long m = nbr(nx, ny, nz, x, y, z, FACE[k]);
+                        double tn[3][3];
+                        if (mask[m] == 0)
+                            tau_get(tau, N, m, tn);
+                        else
+                            tau_get(tau, N, n, tn);
+                        for (int a = 0; a < 3; ++a) {
+                            if (FACE[k][a] == 0)
+                                continue;
+                            for (int j = 0; j < 3; ++j)
+                                F[j] += FACE[k][a] * 0.5 * (t0[a][j] + tn[a][j]);
+                        }
+                    }
+                }
+                for (int j = 0; j < 3; ++j)
+                    fp[j * N + n] = F[j];
+            }
+}
+
+/* Overlap of a unit cell displaced by u with its face neighbour along e. */
+static double face_overlap(const double u[3], const int e[3])
+{
+    double ue = u[0] * e[0] + u[1] * e[1] + u[2] * e[2];
+    if (ue <= 0.0)
+        return 0.0;
+    double v = ue;
+    for (int a = 0; a < 3; ++a)
+        if (e[a] == 0)
+            v *= (1.0 - fabs(u[a]));
+    return v;
+}
+
+void or_fv_apply(int nx, int ny, int nz, const unsigned char *mask, const double *tau_in,
+                 const double *u, double eta_p, double lambda_p, double *tau_out)
+{
+    long N = (long)nx * ny * nz;
+#pragma omp parallel for schedule(static) num_threads(or_get_threads())
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                long n = cell(nx, ny, x, y, z);
+                double t[3][3];
+                tau_get(tau_in, N, n, t);
+                if (mask[n] != 0) {
+                    tau_put(tau_out, N, n, t);
+                    continue;
+                }
+                double ux[3] = {u[n], u[N + n], u[2 * N + n]};
+                /* velocity gradient G[k][j] = d u_j / d r_k, central difference;
+                 * solid nodes carry their boundary velocity */
+                double G[3][3];
+                for (int k = 0; k < 3; ++k) {
+                    long mp = nbr(nx, ny, nz, x, y, z, FACE[2 * k]);
+                    long mm = nbr(nx, ny, nz, x, y, z, FACE[2 * k + 1]);
+                    for (int j = 0; j < 3; ++j)
+                        G[k][j] = 0.5 * (u[j * N + mp] - u[j * N + mm]);
+                }
+                /* Oldroyd-B source: sum_k tau_ik G_kj + sum_k tau_kj G_ki
+                 * + eta_p/lambda (G_ij + G_ji) - tau_ij/lambda */
+                double S[3][3];
+                for (int i = 0; i < 3; ++i)
+                    for (int j = 0; j < 3; ++j) {
+                        double s = 0.0;
+                        for (int k = 0; k < 3; ++k)
+                            s += t[i][k] * G[k][j] + t[k][j] * G[k][i];
+                        s += eta_p / lambda_p * (G[i][j] + G[j][i]) - t[i][j] / lambda_p;
+                        S[i][j] = s;
+                    }
+                /* face fluxes: what leaves through each fluid face minus what enters */
+                double acc[3][3] = {{0}};
+                for (int k = 0; k < 6; ++k) {
+                    long m = nbr(nx, ny, nz, x, y, z, FACE[k]);
+                    if (mask[m] != 0)
+                        continue;
+                    int back[3] = {-FACE[k][0], -FACE[k][1], -FACE[k][2]};
+                    double um[3] = {u[m], u[N + m], u[2 * N + m]};
+                    double out = face_overlap(ux, FACE[k]);
+                    double in = face_overlap(um, back);
+                    double tm[3][3];
+                    tau_get(tau_in, N, m, tm);
+                    for (int i = 0; i < 3; ++i)
+                        for (int j = 0; j < 3; ++j)
+                            acc[i][j] += in * tm[i][j] - out * t[i][j];
+                }
+                double tn[3][3];
+                for (int i = 0; i < 3; ++i)
+                    for (int j = 0; j < 3; ++j)
+                        tn[i][j] = t[i][j] + acc[i][j] + S[i][j];
+                tau_put(tau_out, N, n, tn);
+            }
+}
+
+/* ------------------------------------------------------------------ */
+/* The lattice */
+
+typedef struct {
+    double R[3], v[3], w[3];
+    double radius, mass, inertia;
+    int movable;
+    double fext[3], text[3];
+    double fconv[3], tconv[3];       /* owed by the last conversion */
+    double fmex[3], tmex[3];         /* last step: momentum exchange */
+    double ftau[3], ttau[3];         /* last step: polymer traction */
+    double fconv_used[3];            /* last step: conversion momentum applied */
+    double ftot[3], ttot[3];         /* last step totals */
+} or_particle;
+
+struct or_lattice {
+    int n[3];
+    int per[3];
+    long N;
+    unsigned char *mask;
+    double *wall_vel;
+    int n_walls;
+    double eta, beta, lambda, magic, g[3];
+    double wp, wm, eta_p;
+    int polymer;
+    double *f, *fnew, *fpost;
+    double *tau, *taunew;
+    double *rho, *u, *fp, *ub;
+    int np;
+    or_particle p[MAXP];
+    double wall_force[3];
+    double dropped[6];
+    double conv_tau_before[6], conv_tau_after[6];
+    int conv_counts[2];
+    long step;
+};
+
+or_lattice *or_create(int nx, int ny, int nz, const int periodic[3], const unsigned char *mask,
+                      const double *wall_vel, int n_walls)
+{
+    build_tables();
+    if (nx < 1 || ny < 1 || nz < 1)
+        return NULL;
+    or_lattice *L = (or_lattice *)calloc(1, sizeof(or_lattice));
+    L->n[0] = nx;
+    L->n[1] = ny;
+    L->n[2] = nz;
+    for (int a = 0; a < 3; ++a)
+        L->per[a] = periodic[a] ? 1 : 0;
+    L->N = (long)nx * ny * nz;
+    long N = L->N;
+    L->mask = (unsigned char *)malloc(N);
+    memcpy(L->mask, mask, N);
+    L->n_walls = n_walls;
+    if (n_walls > 0) {
+        L->wall_vel = (double *)malloc(sizeof(double) * 3 * n_walls);
+        memcpy(L->wall_vel, wall_vel, sizeof(double) * 3 * n_walls);
+    }
+    L->f = (double *)calloc((size_t)Q * N, sizeof(double));
+    L->fnew = (double *)calloc((size_t)Q * N, sizeof(double));
+    L->fpost = (double *)calloc((size_t)Q * N, sizeof(double));
+    L->tau = (double *)calloc((size_t)6 * N, sizeof(double));
+    L->taunew = (double *)calloc((size_t)6 * N, sizeof(double));
+    L->rho = (double *)calloc((size_t)N, sizeof(double));
+    L->u = (double *)calloc((size_t)3 * N, sizeof(double));
+    L->fp = (double *)calloc((size_t)3 * N, sizeof(double));
+    L->ub = (double *)calloc((size_t)3 * N, sizeof(double));
+    double zero[3] = {0, 0, 0};
+    or_set_params(L, 1.0 / 3.0, 0.0, 1.0, 3.0 / 16.0, zero);
+    or_init_equilibrium(L, NULL);
+    return L;
+}
+
+void or_destroy(or_lattice *L)
+{
+    if (!L)
+        return;
+    free(L->mask);
+    free(L->wall_vel);
+    free(L->f);
+    free(L->fnew);
+    free(L->fpost);
+    free(L->tau);
+    free(L->taunew);
+    free(L->rho);
+    free(L->u);
+    free(L->fp);
+    free(L->ub);
+    free(L);
+}
+
+int or_set_params(or_lattice *L, double eta, double beta, double lambda_p, double magic,
+                  const double g[3])
+{
+    if (!(eta > 0.0) || beta < 0.0 || beta >= 1.0)
+        return -1;
+    if (beta > 0.0 && !(lambda_p >= 1.0))
+        return -1;
+    double wp, wm;
+    or_rates(eta, beta, magic, &wp, &wm);
+    if (!(wp > 0.0 && wp < 2.0 && wm > 0.0 && wm < 2.0))
+        return -1;
+    L->eta = eta;
+    L->beta = beta;
+    L->lambda = lambda_p;
+    L->magic = magic;
+    for (int a = 0; a < 3; ++a)
+        L->g[a] = g[a];
+    L->wp = wp;
+    L->wm = wm;
+    L->eta_p = beta * eta;
+    L->polymer = beta > 0.0;
+    return 0;
+}
+
+void or_init_equilibrium(or_lattice *L, const double *u)
+{
+    long N = L->N;
+    for (long n = 0; n < N; ++n) {
+        double feq[Q];
+        double un[3] = {0.0, 0.0, 0.0};
+        if (u && L->mask[n] == 0)
+            for (int a = 0; a < 3; ++a)
+                un[a] = u[a * N + n];
+        or_equilibrium(1.0, un, feq);
+        for (int i = 0; i < Q; ++i)
+            L->f[i * N + n] = (L->mask[n] == 0) ? feq[i] : 0.0;
+    }
+    memset(L->tau, 0, sizeof(double) * 6 * N);
+}
+
+void or_set_populations(or_lattice *L, const double *f)
+{
+    long N = L->N;
+    for (long n = 0; n < N; ++n)
+        for (int i = 0; i < Q; ++i)
+            L->f[i * N + n] = (L->mask[n] == 0) ? f[i * N + n] : 0.0;
+}
+
+void or_set_stress(or_lattice *L, const double *tau)
+{
+    long N = L->N;
+    for (long n = 0; n < N; ++n)
+        for (int c = 0; c < 6; ++c)
+            L->tau[c * N + n] = (L->mask[n] == 0) ? tau[c * N + n] : 0.0;
+}
+
+/* displacement from a to b with the minimum image on periodic axes */
+static void min_image(const or_lattice *L, const double a[3], const double b[3], double d[3])
+{
+    for (int k = 0; k < 3; ++k) {
+        d[k] = b[k] - a[k];
+        if (L->per[k]) {
+            double len = (double)L->n[k];
+            d[k] -= len * floor(d[k] / len + 0.5);
+        }
+    }
+}
+
+static int inside_sphere(const or_lattice *L, const or_particle *P, int x, int y, int z)
+{
+    double pos[3] = {(double)x, (double)y, (double)z};
+    double d[3];
+    min_image(L, P->R, pos, d);
+    double d2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    return d2 < P->radius * P->radius;
+}
+
+int or_add_sphere(or_lattice *L, const double center[3], double radius, double density_ratio,
+                  int movable, const double f_ext[3], const double t_ext[3])
+{
+    if (L->np >= MAXP || !(radius > 0.0))
+        return -1;
+    or_particle P;
+    memset(&P, 0, sizeof(P));
+    for (int a = 0; a < 3; ++a) {
+        P.R[a] = center[a];
+        P.fext[a] = f_ext ? f_ext[a] : 0.0;
+        P.text[a] = t_ext ? t_ext[a] : 0.0;
+    }
+    P.radius = radius;
+    P.mass = density_ratio * 4.0 / 3.0 * M_PI * radius * radius * radius;
+    P.inertia = 0.4 * P.mass * radius * radius;
+    P.movable = movable ? 1 : 0;
+    int nx = L->n[0], ny = L->n[1], nz = L->n[2];
+    /* first pass: refuse overlap with any non-fluid cell */
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x)
+                if (inside_sphere(L, &P, x, y, z) && L->mask[cell(nx, ny, x, y, z)] != 0)
+                    return -1;
+    int id = L->np;
+    long N = L->N;
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                long n = cell(nx, ny, x, y, z);
+                if (inside_sphere(L, &P, x, y, z)) {
+                    L->mask[n] = (unsigned char)(PART0 + id);
+                    for (int i = 0; i < Q; ++i)
+                        L->f[i * N + n] = 0.0;
+                    for (int c = 0; c < 6; ++c)
+                        L->tau[c * N + n] = 0.0;
+                }
+            }
+    L->p[id] = P;
+    L->np = id + 1;
+    return id;
+}
+
+/* Boundary velocity of a solid node (Section 3.4: v + omega x (r_b - R)). */
+static void boundary_velocity(const or_lattice *L, long n, int x, int y, int z, double ub[3])
+{
+    unsigned char m = L->mask[n];
+    ub[0] = ub[1] = ub[2] = 0.0;
+    if (m == 0)
+        return;
+    if (m < PART0) {
+        if (m <= L->n_walls)
+            for (int a = 0; a < 3; ++a)
+                ub[a] = L->wall_vel[3 * (m - 1) + a];
+        return;
+    }
+    const or_particle *P = &L->p[m - PART0];
+    if (!P->movable)
+        return;
+    double pos[3] = {(double)x, (double)y, (double)z}, r[3];
+    min_image(L, P->R, pos, r);
+    ub[0] = P->v[0] + P->w[1] * r[2] - P->w[2] * r[1];
+    ub[1] = P->v[1] + P->w[2] * r[0] - P->w[0] * r[2];
+    ub[2] = P->v[2] + P->w[0] * r[1] - P->w[1] * r[0];
+}
+
+static void cross(const double a[3], const double b[3], double c[3])
+{
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+/* Credit a force dF acting at solid node (x,y,z) to the node's owner. */
+static void credit(or_lattice *L, unsigned char owner, int x, int y, int z, const double dF[3],
+                   int traction)
+{
+    if (owner < PART0) {
+        for (int a = 0; a < 3; ++a)
+            L->wall_force[a] += dF[a];
+        return;
+    }
+    or_particle *P = &L->p[owner - PART0];
+    double pos[3] = {(double)x, (double)y, (double)z}, r[3], t[3];
+    min_image(L, P->R, pos, r);
+    cross(r, dF, t);
+    for (int a = 0; a < 3; ++a) {
+        if (traction) {
+            P->ftau[a] += dF[a];
+            P->ttau[a] += t[a];
+        } else {
+            P->fmex[a] += dF[a];
+            P->tmex[a] += t[a];
+        }
+    }
+}
+
+static void fluid_moments(const or_lattice *L, const double *f, const double *fp, long n,
+                          double *rho, double u[3])
+{
+    long N = L->N;
+    double r = 0.0, j[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < Q; ++i) {
+        double fi = f[i * N + n];
+        r += fi;
+        for (int a = 0; a < 3; ++a)
+            j[a] += fi * C[i][a];
+    }
+    *rho = r;
+    for (int a = 0; a < 3; ++a)
+        u[a] = (j[a] + 0.5 * (L->g[a] + fp[a * N + n])) / r;
+}
+
+static void conversion(or_lattice *L);
+
+void or_step(or_lattice *L, long n_steps)
+{
+    const int nx = L->n[0], ny = L->n[1], nz = L->n[2];
+    const long N = L->N;
+    unsigned char *mask = L->mask;
+    for (long s = 0; s < n_steps; ++s) {
+        /* S0: boundary velocities at solid nodes */
+        for (int z = 0; z < nz; ++z)
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x) {
+                    long n = cell(nx, ny, x, y, z);
+                    double ub[3];
+                    boundary_velocity(L, n, x, y, z, ub);
+                    for (int a = 0; a < 3; ++a)
+                        L->ub[a * N + n] = ub[a];
+                }
+        /* S1: polymer force from tau^n */
+        if (L->polymer)
+            or_polymer_force(nx, ny, nz, mask, L->tau, L->fp);
+        else
+            memset(L->fp, 0, sizeof(double) * 3 * N);
+        /* S2 + S3: moments and collision on every fluid cell */
+#pragma omp parallel for schedule(static) num_threads(or_get_threads())
+        for (long n = 0; n < N; ++n) {
+            if (mask[n] != 0) {
+                L->rho[n] = 0.0;
+                for (int a = 0; a < 3; ++a)
+                    L->u[a * N + n] = L->ub[a * N + n];
+                continue;
+            }
+            double fin[Q], fout[Q], F[3], rho, u[3];
+            for (int i = 0; i < Q; ++i)
+                fin[i] = L->f[i * N + n];
+            for (int a = 0; a < 3; ++a)
+                F[a] = L->g[a] + L->fp[a * N + n];
+            or_collide_cell(fin, F, L->wp, L->wm, fout, &rho, u);
+            for (int i = 0; i < Q; ++i)
+                L->fpost[i * N + n] = fout[i];
+            L->rho[n] = rho;
+            for (int a = 0; a < 3; ++a)
+                L->u[a * N + n] = u[a];
+        }
+        /* S4: push streaming with link bounce-back / moving-wall term */
+        memset(L->fnew, 0, sizeof(double) * Q * N);
+#pragma omp parallel for schedule(static) num_threads(or_get_threads())
+        for (int z = 0; z < nz; ++z)
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x) {
+                    long n = cell(nx, ny, x, y, z);
+                    if (mask[n] != 0)
+                        continue;
+                    for (int j = 0; j < Q; ++j) {
+                        long m = nbr(nx, ny, nz, x, y, z, C[j]);
+                        if (mask[m] == 0) {
+                            L->fnew[j * N + m] = L->fpost[j * N + n];
+                        } else {
+                            int o = OPP[j];
+                            double cub = C[o][0] * L->ub[m] + C[o][1] * L->ub[N + m] +
+                                         C[o][2] * L->ub[2 * N + m];
+                            L->fnew[o * N + n] = L->fpost[j * N + n] + 6.0 * W[o] * L->rho[n] * cub;
+                        }
+                    }
+                }
+        /* momentum exchanged with obstacles over every boundary link, and the
+         * polymer traction over every boundary face (serial, fixed order) */
+        for (int a = 0; a < 3; ++a)
+            L->wall_force[a] = 0.0;
+        for (int k = 0; k < L->np; ++k)
+            for (int a = 0; a < 3; ++a) {
+                L->p[k].fmex[a] = L->p[k].tmex[a] = 0.0;
+                L->p[k].ftau[a] = L->p[k].ttau[a] = 0.0;
+            }
+        for (int z = 0; z < nz; ++z)
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x) {
+                    long n = cell(nx, ny, x, y, z);
+                    if (mask[n] != 0)
+                        continue;
+                    for (int j = 0; j < Q; ++j) {
+                        long m = nbr(nx, ny, nz, x, y, z, C[j]);
+                        if (mask[m] == 0)
+                            continue;
+                        int o = OPP[j];
+                        double sum = L->fpost[j * N + n] + L->fnew[o * N + n];
+                        double dF[3] = {C[j][0] * sum, C[j][1] * sum, C[j][2] * sum};
+                        credit(L, mask[m], wrap(x + C[j][0], nx), wrap(y + C[j][1], ny),
+                               wrap(z + C[j][2], nz), dF, 0);
+                    }
+                    if (L->polymer) {
+                        double t[3][3];
+                        tau_get(L->tau, N, n, t);
+                        for (int k = 0; k < 6; ++k) {
+                            long m = nbr(nx, ny, nz, x, y, z, FACE[k]);
+                            if (mask[m] == 0)
+                                continue;
+                            double dF[3];
+                            for (int jj = 0; jj < 3; ++jj) {
+                                double s = 0.0;
+                                for (int a = 0; a < 3; ++a)
+                                    s += FACE[k][a] * t[a][jj];
+                                dF[jj] = -s;
+                            }
+                            credit(L, mask[m], wrap(x + FACE[k][0], nx), wrap(y + FACE[k][1], ny),
+                                   wrap(z + FACE[k][2], nz), dF, 1);
+                        }
+                    }
+                }
+        /* S5: finite-volume stress update with tau^n and u^n */
+        if (L->polymer)
+            or_fv_apply(nx, ny, nz, mask, L->tau, L->u, L->eta_p, L->lambda, L->taunew);
+        else
+            memset(L->taunew, 0, sizeof(double) * 6 * N);
+        /* S6: particles, symplectic Euler */
+        for (int k = 0; k < L->np; ++k) {
+            or_particle *P = &L->p[k];
+            for (int a = 0; a < 3; ++a) {
+                P->fconv_used[a] = P->fconv[a];
+                P->ftot[a] = P->fmex[a] + P->ftau[a] + P->fconv[a] + P->fext[a];
+                P->ttot[a] = P->tmex[a] + P->ttau[a] + P->tconv[a] + P->text[a];
+                P->fconv[a] = P->tconv[a] = 0.0;
+            }
+            if (!P->movable)
+                continue;
+            for (int a = 0; a < 3; ++a) {
+                P->v[a] += P->ftot[a] / P->mass;
+                P->w[a] += P->ttot[a] / P->inertia;
+            }
+            for (int a = 0; a < 3; ++a) {
+                P->R[a] += P->v[a];
+                if (L->per[a]) {
+                    double len = (double)L->n[a];
+                    P->R[a] -= len * floor(P->R[a] / len);
+                }
+            }
+        }
+        /* swap in the new state */
+        double *t;
+        t = L->f;
+        L->f = L->fnew;
+        L->fnew = t;
+        t = L->tau;
+        L->tau = L->taunew;
+        L->taunew = t;
+        /* S7: cells covered or uncovered by moving particles */
+        conversion(L);
+        L->step += 1;
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* S7: conversion between fluid and solid (Section 3.4) */
+
+static void conversion(or_lattice *L)
+{
+    int any = 0;
+    for (int k = 0; k < L->np; ++k)
+        any |= L->p[k].movable;
+    if (!any)
+        return;
+    const int nx = L->n[0], ny = L->n[1], nz = L->n[2];
+    const long N = L->N;
+    unsigned char *old = L->mask;
+    unsigned char *nw = (unsigned char *)malloc(N);
+    memcpy(nw, old, N);
+    /* the new solid set of each moving particle */
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                long n = cell(nx, ny, x, y, z);
+                unsigned char m = old[n];
+                if (m >= PART0 && L->p[m - PART0].movable &&
+                    !inside_sphere(L, &L->p[m - PART0], x, y, z))
+                    nw[n] = 0;
+                if (m == 0)
+                    for (int k = 0; k < L->np; ++k)
+                        if (L->p[k].movable && inside_sphere(L, &L->p[k], x, y, z)) {
+                            nw[n] = (unsigned char)(PART0 + k);
+                            break;
+                        }
+            }
+#define STAYS_FLUID(mm) (old[mm] == 0 && nw[mm] == 0)
+    double *tau = L->tau;
+    double *f = L->f;
+    L->conv_counts[0] = L->conv_counts[1] = 0;
+    for (int c = 0; c < 6; ++c) {
+        L->conv_tau_before[c] = 0.0;
+        for (long n = 0; n < N; ++n)
+            if (old[n] == 0)
+                L->conv_tau_before[c] += tau[c * N + n];
+    }
+    /* covers: populations deleted, their momentum goes to the particle, the
+     * stress is shared among the neighbours that stay fluid */
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                long n = cell(nx, ny, x, y, z);
+                if (!(old[n] == 0 && nw[n] != 0))
+                    continue;
+                L->conv_counts[0] += 1;
+                or_particle *P = &L->p[nw[n] - PART0];
+                double mom[3] = {0.0, 0.0, 0.0};
+                for (int i = 0; i < Q; ++i)
+                    for (int a = 0; a < 3; ++a)
+                        mom[a] += f[i * N + n] * C[i][a];
+                double pos[3] = {(double)x, (double)y, (double)z}, r[3], t[3];
+                min_image(L, P->R, pos, r);
+                cross(r, mom, t);
+                for (int a = 0; a < 3; ++a) {
+                    P->fconv[a] += mom[a];
+                    P->tconv[a] += t[a];
+                }
+                int nf = 0;
+                for (int j = 0; j < Q; ++j) {
+                    if (j == REST)
+                        continue;
+                    long m = nbr(nx, ny, nz, x, y, z, C[j]);
+                    if (STAYS_FLUID(m))
+                        ++nf;
+                }
+                for (int c = 0; c < 6; ++c) {
+                    double share = tau[c * N + n];
+                    if (nf == 0) {
+                        L->dropped[c] += share;
+                        continue;
+                    }
+                    for (int j = 0; j < Q; ++j) {
+                        if (j == REST)
+                            continue;
+                        long m = nbr(nx, ny, nz, x, y, z, C[j]);
+                        if (STAYS_FLUID(m))
+                            tau[c * N + m] += share / nf;
+                    }
+                }
+                for (int c = 0; c < 6; ++c)
+                    tau[c * N + n] = 0.0;
+                for (int i = 0; i < Q; ++i)
+                    f[i * N + n] = 0.0;
+            }
+    /* uncovers: equilibrium populations at the mean neighbour density and the
+     * surface velocity; stress taken from the neighbours that stay fluid */
+    double *tnew = (double *)calloc((size_t)6 * N, sizeof(double));
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                long n = cell(nx, ny, x, y, z);
+                if (!(old[n] != 0 && nw[n] == 0))
+                    continue;
+                L->conv_counts[1] += 1;
+                int nf = 0;
+                double rsum = 0.0, ts[6] = {0};
+                for (int j = 0; j < Q; ++j) {
+                    if (j == REST)
+                        continue;
+                    long m = nbr(nx, ny, nz, x, y, z, C[j]);
+                    if (!STAYS_FLUID(m))
+                        continue;
+                    ++nf;
+                    double r = 0.0;
+                    for (int i = 0; i < Q; ++i)
+                        r += f[i * N + m];
+                    rsum += r;
+                    for (int c = 0; c < 6; ++c)
+                        ts[c] += tau[c * N + m];
+                }
+                double rho = nf > 0 ? rsum / nf : 1.0;
+                double ub[3];
+                boundary_velocity(L, n, x, y, z, ub); /* old mask: the particle that left */
+                double feq[Q];
+                or_equilibrium(rho, ub, feq);
+                for (int i = 0; i < Q; ++i)
+                    f[i * N + n] = feq[i];
+                or_particle *P = &L->p[old[n] - PART0];
+                double mom[3] = {rho * ub[0], rho * ub[1], rho * ub[2]};
+                double pos[3] = {(double)x, (double)y, (double)z}, r[3], t[3];
+                min_image(L, P->R, pos, r);
+                cross(r, mom, t);
+                for (int a = 0; a < 3; ++a) {
+                    P->fconv[a] -= mom[a];
+                    P->tconv[a] -= t[a];
+                }
+                for (int c = 0; c < 6; ++c)
+                    tnew[c * N + n] = ts[c] / (nf + 1);
+            }
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                long n = cell(nx, ny, x, y, z);
+                if (!(old[n] != 0 && nw[n] == 0))
+                    continue;
+                int nf = 0;
+                for (int j = 0; j < Q; ++j) {
+                    if (j == REST)
+                        continue;
+                    long m = nbr(nx, ny, nz, x, y, z, C[j]);
+                    if (STAYS_FLUID(m))
+                        ++nf;
+                }
+                for (int j = 0; j < Q && nf > 0; ++j) {
+                    if (j == REST)
+                        continue;
+                    long m = nbr(nx, ny, nz, x, y, z, C[j]);
+                    if (STAYS_FLUID(m))
+                        for (int c = 0; c < 6; ++c)
+                            tau[c * N + m] -= tnew[c * N + n] / nf;
+                }
+            }
+    for (long n = 0; n < N; ++n)
+        if (old[n] != 0 && nw[n] == 0)
+            for (int c = 0; c < 6; ++c)
+                tau[c * N + n] = tnew[c * N + n];
+#undef STAYS_FLUID
+    free(tnew);
+    memcpy(L->mask, nw, N);
+    free(nw);
+    for (int c = 0; c < 6; ++c) {
+        L->conv_tau_after[c] = 0.0;
+        for (long n = 0; n < N; ++n)
+            if (L->mask[n] == 0)
+                L->conv_tau_after[c] += tau[c * N + n];
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Readout */
+
+void or_read_populations(const or_lattice *L, double *f) { memcpy(f, L->f, sizeof(double) * Q * L->N); }
+
+void or_read_stress(const or_lattice *L, double *tau) { memcpy(tau, L->tau, sizeof(double) * 6 * L->N); }
+
+void or_read_mask(const or_lattice *L, unsigned char *mask) { memcpy(mask, L->mask, L->N); }
+
+static double *current_force(const or_lattice *L)
+{
+    long N = L->N;
+    double *fp = (double *)calloc((size_t)3 * N, sizeof(double));
+    if (L->polymer)
+        or_polymer_force(L->n[0], L->n[1], L->n[2], L->mask, L->tau, fp);
+    return fp;
+}
+
+void or_read_density(const or_lattice *L, double *rho)
+{
+    long N = L->N;
+    for (long n = 0; n < N; ++n) {
+        double r = 0.0;
+        if (L->mask[n] == 0)
+            for (int i = 0; i < Q; ++i)
+                r += L->f[i * N + n];
+        rho[n] = r;
+    }
+}
+
+void or_read_velocity(const or_lattice *L, double *u)
+{
+    long N = L->N;
+    double *fp = current_force(L);
+    for (long n = 0; n < N; ++n) {
+        double r, un[3] = {0.0, 0.0, 0.0};
+        if (L->mask[n] == 0)
+            fluid_moments(L, L->f, fp, n, &r, un);
+        for (int a = 0; a < 3; ++a)
+            u[a * N + n] = un[a];
+    }
+    free(fp);
+}
+
+void or_read_particle(const or_lattice *L, int id, double pos[3], double vel[3], double omega[3],
+                      double force[3], double torque[3])
+{
+    if (id < 0 || id >= L->np)
+        return;
+    const or_particle *P = &L->p[id];
+    for (int a = 0; a < 3; ++a) {
+        if (pos)
+            pos[a] = P->R[a];
+        if (vel)
+            vel[a] = P->v[a];
+        if (omega)
+            omega[a] = P->w[a];
+        if (force)
+            force[a] = P->ftot[a];
+        if (torque)
+            torque[a] = P->ttot[a];
+    }
+}
+
+void or_read_particle_parts(const or_lattice *L, int id, double f_mex[3], double f_tau[3],
+                            double f_conv[3])
+{
+    if (id < 0 || id >= L->np)
+        return;
+    const or_particle *P = &L->p[id];
+    for (int a = 0; a < 3; ++a) {
+        f_mex[a] = P->fmex[a];
+        f_tau[a] = P->ftau[a];
+        f_conv[a] = P->fconv_used[a];
+    }
+}
+
+void or_read_sums(const or_lattice *L, double *mass, double momentum[3])
+{
+    long N = L->N;
+    double m = 0.0, p[3] = {0.0, 0.0, 0.0};
+    for (long n = 0; n < N; ++n) {
+        if (L->mask[n] != 0)
+            continue;
+        for (int i = 0; i < Q; ++i) {
+            double fi = L->f[i * N + n];
+            m += fi;
+            for (int a = 0; a < 3; ++a)
+                p[a] += fi * C[i][a];
+        }
+    }
+    *mass = m;
+    for (int a = 0; a < 3; ++a)
+        momentum[a] = p[a];
+}
+
+void or_read_wall_force(const or_lattice *L, double force[3])
+{
+    for (int a = 0; a < 3; ++a)
+        force[a] = L->wall_force[a];
+}
+
+void or_read_pending_conversion(const or_lattice *L, double momentum[3])
+{
+    for (int a = 0; a < 3; ++a) {
+        momentum[a] = 0.0;
+        for (int k = 0; k < L->np; ++k)
+            momentum[a] += L->p[k].fconv[a];
+    }
+}
+
+void or_read_dropped_stress(const or_lattice *L, double tau[6])
+{
+    for (int c = 0; c < 6; ++c)
+        tau[c] = L->dropped[c];
+}
+
+long or_step_count(const or_lattice *L) { return L->step; }
+
+void or_read_conversion_stats(const or_lattice *L, int counts[2], double tau_before[6],
+                              double tau_after[6])
+{
+    counts[0] = L->conv_counts[0];
+    counts[1] = L->conv_counts[1];
+    for (int c = 0; c < 6; ++c) {
+        tau_before[c] = L->conv_tau_before[c];
+        tau_after[c] = L->conv_tau_after[c];
+    }
+}

@@ -1,0 +1,217 @@
+"""Whole-step pins of the oracle (Sections 3.1-3.4, 4.1, 4.2): exact TRT
+Poiseuille, the steady Oldroyd-B Poiseuille closed forms of the channel
+workload, the paper's Couette and Poiseuille numbers, exact mass and
+momentum balances, mirror symmetry around a fixed sphere, and the momentum
+and stress bookkeeping of a moving sphere."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2009_12279_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def channel(orc, shape, beta, lam, g=(0, 0, 0), magic=3 / 16, eta=1 / 3, wall_velocity=None,
+            top_id=None):
+    mask = inputs.channel_mask(shape, wall_axes=(1,), top_id=top_id)
+    L = orc.Lattice(shape, mask, periodic=(1, 0, 1), wall_velocity=wall_velocity)
+    L.set_params(eta=eta, beta=beta, lambda_p=lam, magic=magic, body_force=g)
+    return L, mask
+
+
+def test_newtonian_trt_poiseuille_is_an_exact_parabola(orc):
+    """Textbook TRT property (magic 3/16, halfway bounce-back): the steady
+    profile is g/(2 eta) (y - 1/2)(ny - 3/2 - y) to machine precision."""
+    shape = (4, 18, 4)
+    g, eta = 1e-6, 1 / 3
+    L, mask = channel(orc, shape, 0.0, 1.0, g=(g, 0, 0), eta=eta)
+    L.init_equilibrium()
+    L.step(3000)
+    ux = L.velocity()[0, 0, :, 0]
+    y = np.arange(shape[1])
+    ex = g / (2 * eta) * (y - 0.5) * (shape[1] - 1.5 - y)
+    np.testing.assert_allclose(ux[1:-1], ex[1:-1], rtol=1e-10)
+
+
+def test_channel_workload_steady_oldroyd_b_closed_forms(orc):
+    """The 4x64x4 plane Poiseuille workload (BGK tau = 1, beta = 0.5,
+    lambda = 1000, g = 1e-6, 20000 steps from rest with 1e-8 noise): at a
+    discrete steady state tau_yy = 0, tau_xy = eta_p D_y u_x and
+    tau_xx = 2 lambda eta_p (D_y u_x)^2 with D_y the scheme's central
+    difference, and the bulk curvature of u_x is -g/eta."""
+    shape = (4, 64, 4)
+    g, eta, beta, lam = 1e-6, 1 / 3, 0.5, 1000.0
+    L, mask = channel(orc, shape, beta, lam, g=(g, 0, 0), magic=-1.0, eta=eta)
+    u0 = inputs.noise_field(1, 0, shape, 1e-8)
+    u0[:, mask != 0] = 0
+    L.init_equilibrium(u0)
+    L.step(20000)
+    u = L.velocity()
+    tau = L.stress()
+    ux = u[0].mean(axis=(0, 2))
+    ub = ux.copy()
+    ub[0] = ub[-1] = 0.0
+    D = 0.5 * (ub[2:] - ub[:-2])
+    eta_p = beta * eta
+    txy = tau[3].mean(axis=(0, 2))[1:-1]
+    txx = tau[0].mean(axis=(0, 2))[1:-1]
+    tyy = tau[1].mean(axis=(0, 2))[1:-1]
+    assert np.max(np.abs(txy - eta_p * D)) < 1e-5 * np.max(np.abs(eta_p * D))
+    assert np.max(np.abs(txx - 2 * lam * eta_p * D ** 2)) < 1e-5 * np.max(2 * lam * eta_p * D ** 2)
+    assert np.max(np.abs(tyy)) < 1e-8 * np.max(np.abs(txy))
+    curv = ux[2:] - 2 * ux[1:-1] + ux[:-2]
+    bulk = curv[9:-9]
+    np.testing.assert_allclose(bulk, -g / eta, rtol=1e-5)
+    # velocity is uniform along x and z and the cross-flow has died out
+    assert np.max(np.abs(u[1:])) < 1e-6 * ux.max()
+
+
+def test_paper_poiseuille_reynolds_number(orc):
+    gold = json.load(open(os.path.join(GOLDEN, "poiseuille_startup.json")))
+    Lw, F, eta = gold["L"], gold["F"], gold["eta"]
+    shape = (4, Lw + 2, 4)
+    L, mask = channel(orc, shape, 0.0, 1.0, g=(F, 0, 0), eta=eta)
+    L.init_equilibrium()
+    L.step(6000)
+    ux = L.velocity()[0, 0, :, 0]
+    centre = 0.5 * (ux[Lw // 2] + ux[Lw // 2 + 1])
+    Re = centre * Lw / eta
+    assert abs(Re - gold["Re_quoted"]) < gold["Re_rounding"]
+    # and the closed form rho F L^3 / (8 eta^2) it is quoted from, to 1/L^2
+    assert abs(Re - F * Lw ** 3 / (8 * eta ** 2)) < 1e-3 * Re + F * Lw / (8 * eta ** 2) * 2
+
+
+@pytest.mark.parametrize("case", [0, 1])
+def test_paper_couette_first_normal_stress_difference(orc, case):
+    gold = json.load(open(os.path.join(GOLDEN, "couette_steady_shear.json")))
+    c = gold["cases"][case]
+    Lw, u0, eta = gold["L"], gold["u0"], gold["eta"]
+    beta, lam = c["beta"], float(c["lambda_p"])
+    shape = (4, Lw + 2, 4)
+    L, mask = channel(orc, shape, beta, lam, eta=eta, wall_velocity=[[0, 0, 0], [u0, 0, 0]],
+                      top_id=2)
+    L.init_equilibrium()
+    L.step(int(gold["run_lambdas"] * lam))
+    u = L.velocity()
+    tau = L.stress()
+    ux = u[0].mean(axis=(0, 2))[1:-1]
+    txx, tyy, txy = (tau[k].mean(axis=(0, 2))[1:-1] for k in (0, 1, 3))
+    eta_p = beta * eta
+    # per cell at the discrete steady state: tau_yy = 0, N1 = 2 lam tau_xy^2 / eta_p
+    assert np.max(np.abs(tyy)) < 1e-10 * np.max(np.abs(txx))
+    np.testing.assert_allclose(txx - tyy, 2 * lam * txy ** 2 / eta_p, rtol=2e-3)
+    # bulk: the paper's N1 = 2 eta_p lam (u0/L)^2 with the effective width
+    # from the bulk shear rate (the wall position is not exactly halfway)
+    bulk = slice(6, -6)
+    slope = np.polyfit(np.arange(Lw)[bulk], ux[bulk], 1)[0]
+    L_eff = u0 / slope
+    assert abs(L_eff - Lw) < 0.6  # the paper's +-0.3 cells per wall
+    N1 = (txx - tyy)[bulk]
+    np.testing.assert_allclose(N1, 2 * eta_p * lam * (u0 / L_eff) ** 2,
+                               rtol=gold["N1_rel_tol_bulk"])
+
+
+def _fixed_geometry(orc, seed):
+    """A small lattice with y walls (the top one a tangentially moving lid), a
+    fixed sphere, random body force, random near-equilibrium populations and
+    random stress."""
+    rng = np.random.default_rng(seed)
+    shape = (10, 9, 8)
+    nx, ny, nz = shape
+    mask = inputs.channel_mask(shape, wall_axes=(1,), top_id=2)
+    L = orc.Lattice(shape, mask, periodic=(1, 0, 1), wall_velocity=[[0, 0, 0], [2e-3, 0, 3e-3]])
+    g = 1e-5 * rng.standard_normal(3)
+    L.set_params(eta=0.25, beta=0.4, lambda_p=30.0, magic=3 / 16, body_force=g)
+    L.add_sphere([4.5, 4.2, 3.7], 2.2)
+    m = L.mask()
+    c, w = orc.velocities()
+    f = np.zeros((19, nz, ny, nx))
+    u = 1e-3 * rng.standard_normal((3, nz, ny, nx))
+    for i in range(19):
+        cu = sum(c[i, a] * u[a] for a in range(3))
+        f[i] = w[i] * (1 + 3 * cu) + 1e-5 * w[i] * rng.standard_normal((nz, ny, nx))
+    L.set_populations(f)
+    tau = 1e-4 * rng.standard_normal((6, nz, ny, nx))
+    L.set_stress(tau)
+    return L, m, g
+
+
+def test_mass_is_conserved_with_fixed_and_tangentially_moving_walls(orc):
+    L, m, g = _fixed_geometry(orc, 1)
+    m0, _ = L.sums()
+    for _ in range(10):
+        L.step(20)
+        mass, _ = L.sums()
+        assert abs(mass - m0) < 1e-13 * m0
+
+
+def test_momentum_balance_every_step(orc):
+    """P^{n+1} - P^n = N_f g + sum F^p - (momentum exchange) and the polymer
+    force sums to minus the traction on obstacles, so
+    P^{n+1} - P^n + (force on walls + spheres) = N_f g exactly."""
+    L, m, g = _fixed_geometry(orc, 2)
+    Nf = int((m == 0).sum())
+    _, p0 = L.sums()
+    for _ in range(15):
+        L.step(1)
+        _, p1 = L.sums()
+        part = L.particle(0)["force"]
+        obstacles = L.wall_force() + part
+        np.testing.assert_allclose(p1 - p0 + obstacles, Nf * g, rtol=0, atol=1e-13)
+        p0 = p1
+
+
+def test_fixed_sphere_in_duct_mirror_symmetry(orc):
+    """A fixed sphere at the centre of a square duct with x-flow: transverse
+    force and all torque vanish by symmetry; the drag points downstream."""
+    shape = (24, 16, 16)
+    mask = inputs.channel_mask(shape, wall_axes=(1, 2))
+    L = orc.Lattice(shape, mask, periodic=(1, 0, 0))
+    L.set_params(eta=1 / 3, beta=0.5, lambda_p=100.0, magic=3 / 16, body_force=(1e-5, 0, 0))
+    L.add_sphere([11.5, 7.5, 7.5], 3.0)
+    L.init_equilibrium()
+    L.step(200)
+    p = L.particle(0)
+    F, T = p["force"], p["torque"]
+    assert F[0] > 1e-6
+    assert abs(F[1]) < 1e-12 * F[0] and abs(F[2]) < 1e-12 * F[0]
+    assert np.max(np.abs(T)) < 1e-11 * F[0]
+
+
+def test_moving_sphere_momentum_ledger_and_stress_conservation(orc):
+    """Periodic box, no body force, one moving sphere pushed by an external
+    force.  Fluid momentum + particle momentum + momentum owed by the last
+    conversion grows by exactly F_ext per step; conversions neither create
+    nor destroy stress."""
+    shape = (16, 16, 16)
+    L = orc.Lattice(shape)
+    L.set_params(eta=1 / 6, beta=0.5, lambda_p=50.0, magic=3 / 16, body_force=(0, 0, 0))
+    fext = np.array([2e-3, -1e-3, 3e-3])
+    pid = L.add_sphere([7.5, 7.3, 7.6], 3.1, density_ratio=1.2, movable=True, f_ext=fext)
+    L.init_equilibrium()
+    M = 1.2 * 4 / 3 * np.pi * 3.1 ** 3
+
+    def ledger():
+        _, pf = L.sums()
+        return pf + M * L.particle(pid)["vel"] + L.pending_conversion()
+
+    led0 = ledger()
+    n_cover = n_uncover = 0
+    pos_prev = L.particle(pid)["pos"]
+    for n in range(1, 301):
+        L.step(1)
+        np.testing.assert_allclose(ledger() - led0, n * fext, rtol=0, atol=1e-12)
+        (c, u), before, after = L.conversion_stats()
+        n_cover += c
+        n_uncover += u
+        np.testing.assert_allclose(after + L.dropped_stress() * 0, before, rtol=0,
+                                   atol=1e-15 + 1e-12 * np.abs(before).max())
+        p = L.particle(pid)
+        # symplectic Euler: the position advances by the new velocity
+        np.testing.assert_allclose(p["pos"] - pos_prev, p["vel"], atol=1e-14)
+        pos_prev = p["pos"]
+    assert n_cover > 0 and n_uncover > 0
+    assert np.all(L.dropped_stress() == 0)
