@@ -1,0 +1,199 @@
+/*
+ * vlb.h -- C ABI of the MI355X (gfx950) lattice Boltzmann library for
+ * Oldroyd-B fluids with complex and moving boundaries, after Kuron, Stewart,
+ * de Graaf and Holm, "An extensible lattice Boltzmann method for viscoelastic
+ * flows: complex and moving boundaries in Oldroyd-B fluids" (arXiv 2009.12279).
+ *
+ * One time step is the coupled per-cell update of Section 3:
+ *   - D3Q19 TRT stream-collide with Guo forcing whose force is the body force
+ *     plus the divergence of the polymer stress (Section 3.1, Section 2.1
+ *     polymer force, Section 3.3 force discretisation);
+ *   - explicit finite-volume update of the Oldroyd-B stress with
+ *     corner-transport-upwind face fluxes (Section 2.2, Section 3.3);
+ *   - link bounce-back with the moving-wall term for walls and particle
+ *     surfaces, momentum exchange force and torque on particles, symplectic
+ *     Euler particle motion, and refill / deletion of cells a moving particle
+ *     uncovers / covers (Section 3.1 velocity boundary condition, Section 3.4).
+ *
+ * Conventions (all functions):
+ *   - Lattice units: grid spacing = time step = 1, reference density 1.
+ *   - Cell index n = x + nx*(y + ny*z).  A field with k components is passed
+ *     as k consecutive planes of N = nx*ny*nz values (structure of arrays).
+ *   - Stress components are ordered xx, yy, zz, xy, xz, yz.
+ *   - Populations use the direction order of vlb_velocity().
+ *   - Mask byte per cell: 0 = fluid; 1..63 = wall id w, moving with
+ *     wall_velocity[w-1] (at rest when w > n_walls); 64..255 are reserved for
+ *     particles and set only by vlb_add_sphere (particle k has byte 64+k).
+ *     Every non-periodic axis must have solid cells in its first and last
+ *     layer.
+ *   - All host pointers are copied at the call (inputs) or filled before the
+ *     call returns (outputs); the caller owns them.  The library owns all
+ *     device memory it allocates.
+ *   - Every call returns a vlb_status; no exception or abort crosses the ABI.
+ *     On failure the lattice keeps its previous state and vlb_last_error()
+ *     describes the cause.  VLB_EUNSTABLE is sticky: once a health check
+ *     found a non-finite value or a speed above the limit, vlb_step returns
+ *     it without stepping; reads still work.
+ *   - vlb_step is asynchronous on the lattice's HIP stream; every read
+ *     synchronises that stream.
+ */
+#ifndef VLB_H
+#define VLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VLB_Q 19
+#define VLB_MAX_WALL_ID 63
+#define VLB_MAX_PARTICLES 192
+
+typedef enum vlb_status {
+    VLB_OK = 0,
+    VLB_EINVAL = 1,    /* invalid argument or parameter                     */
+    VLB_ENOMEM = 2,    /* device or host allocation failed                  */
+    VLB_EDEVICE = 3,   /* HIP runtime error or no usable device             */
+    VLB_EUNSTABLE = 4, /* non-finite field or speed above the health limit  */
+    VLB_ESTATE = 5,    /* call not allowed in the current state             */
+    VLB_EBUSY = 6,     /* no free slot / memory budget (serving)            */
+    VLB_ENOTFOUND = 7  /* unknown particle id or ticket                     */
+} vlb_status;
+
+/* Population storage: deviations h_i = s * (f_i - w_i) from the lattice
+ * weights w_i, with a power-of-two scale s (1 for FP32, 2^10 for FP16, 1 for
+ * BF16).  The per-cell arithmetic runs in FP64 registers for FP32 storage and
+ * in FP32 for FP16/BF16 storage; particle sums are FP64. */
+typedef enum vlb_storage { VLB_STORE_F32 = 0, VLB_STORE_F16 = 1, VLB_STORE_BF16 = 2 } vlb_storage;
+
+/* How stored values (populations and stress) are rounded to their storage
+ * precision after each step.  Stochastic rounding picks the neighbouring
+ * representable value above or below with probability proportional to the
+ * distance, from a counter-based hash of (cell, step, seed); it is unbiased,
+ * so a slowly relaxing steady state does not drift the way repeated
+ * round-to-nearest does.  Results are deterministic for a given seed. */
+typedef enum vlb_rounding { VLB_ROUND_NEAREST = 0, VLB_ROUND_STOCHASTIC = 1 } vlb_rounding;
+
+typedef struct vlb_dims {
+    int32_t nx, ny, nz;
+    uint8_t periodic[3]; /* 1 = periodic along x, y, z */
+    uint8_t reserved;
+} vlb_dims;
+
+/* Physical parameters (Section 2, Section 3.1).  Defaults: eta = 1/3,
+ * beta = 0, lambda_p = 1, magic = 3/16, no body force. */
+typedef struct vlb_params {
+    double eta;           /* total dynamic viscosity eta = eta_n + eta_p            */
+    double beta;          /* polymer fraction eta_p/eta in [0,1); 0 = Newtonian     */
+    double lambda_p;      /* polymer relaxation time in steps (>= 1 when beta > 0) */
+    double magic;         /* TRT (1/w+ - 1/2)(1/w- - 1/2); < 0 selects BGK (w- = w+) */
+    double body_force[3]; /* force density g applied to every fluid cell            */
+} vlb_params;
+
+typedef struct vlb_lattice vlb_lattice;
+
+/* Direction i (0..18) of the D3Q19 set: velocity c[3] and weight *w (either
+ * may be NULL).  Returns VLB_Q.  Order: rest, +x, -x, +y, -y, +z, -z, then
+ * the 12 edge directions in opposite pairs (+x+y, -x-y, +x-y, -x+y, +x+z,
+ * -x-z, +x-z, -x+z, +y+z, -y-z, +y-z, -y+z). */
+int32_t vlb_velocity(int32_t i, int32_t c[3], double *w);
+
+/* Bytes of device memory a lattice of these dimensions holds (admission). */
+size_t vlb_required_bytes(const vlb_dims *dims, vlb_storage storage, int32_t n_particles);
+
+/* Create a lattice on the current HIP device.  mask: N bytes (see above).
+ * wall_velocity: n_walls x 3 doubles or NULL.  stream: a hipStream_t to
+ * enqueue all work on, or NULL for a stream the library creates.  The state
+ * starts at rest (f = w, tau = 0) with the default parameters.
+ * Errors: VLB_EINVAL (bad dims, mask values >= 64, a non-periodic axis
+ * without solid end layers, n_walls > 63), VLB_ENOMEM, VLB_EDEVICE. */
+vlb_status vlb_create(const vlb_dims *dims, const uint8_t *mask, const double *wall_velocity,
+                      int32_t n_walls, vlb_storage storage, void *stream, vlb_lattice **out);
+
+/* Set eta, beta, lambda_p, magic and the body force (Section 2.3, 3.1):
+ * omega+ = 1/(3 (1-beta) eta + 1/2); omega- from magic.  VLB_EINVAL when
+ * eta <= 0, beta outside [0,1), lambda_p < 1 with beta > 0, or a rate
+ * outside (0,2). */
+vlb_status vlb_set_params(vlb_lattice *lat, const vlb_params *params);
+
+/* f = f^eq(rho = 1, u) on fluid cells (u: 3*N doubles, or NULL for rest),
+ * tau = 0.  Resets the step count. */
+vlb_status vlb_init_equilibrium(vlb_lattice *lat, const double *u);
+
+/* Overwrite the populations (19*N doubles, raw f, vlb_velocity order) or the
+ * stress (6*N doubles) of every fluid cell; solid cells are ignored. */
+vlb_status vlb_set_populations(vlb_lattice *lat, const double *f);
+vlb_status vlb_set_stress(vlb_lattice *lat, const double *tau);
+
+/* Add a sphere of radius r centred at c (cells with |x - c|^2 < r^2, minimum
+ * image on periodic axes) as particle *id_out.  Mass = density_ratio *
+ * 4/3 pi r^3, moment of inertia 2/5 M r^2.  A movable sphere follows
+ * symplectic Euler under momentum exchange, polymer traction, conversion
+ * momentum and the external force/torque (Section 3.4); a fixed one only
+ * records its force.  VLB_EINVAL if it overlaps a non-fluid cell or the
+ * particle table is full. */
+vlb_status vlb_add_sphere(vlb_lattice *lat, const double center[3], double radius,
+                          double density_ratio, int32_t movable, const double f_ext[3],
+                          const double t_ext[3], int32_t *id_out);
+
+/* Advance n_steps time steps (asynchronous). */
+vlb_status vlb_step(vlb_lattice *lat, int64_t n_steps);
+vlb_status vlb_sync(vlb_lattice *lat);
+int64_t vlb_step_count(const vlb_lattice *lat);
+
+/* Reads of the current state (FP64 host arrays of N, 3*N, 6*N, 19*N values;
+ * solid cells read 0).  Density rho = sum f; velocity u = (sum f c + F/2)/rho
+ * with F = g + polymer force of the current stress (Section 3.1). */
+vlb_status vlb_read_density(vlb_lattice *lat, double *rho);
+vlb_status vlb_read_velocity(vlb_lattice *lat, double *u);
+vlb_status vlb_read_stress(vlb_lattice *lat, double *tau);
+vlb_status vlb_read_populations(vlb_lattice *lat, double *f);
+vlb_status vlb_read_mask(vlb_lattice *lat, uint8_t *mask);
+
+/* Particle state after the last step and the total force / torque that step
+ * applied to it (momentum exchange + polymer traction + conversion
+ * momentum + external), FP64.  Any output may be NULL. */
+vlb_status vlb_read_particle(vlb_lattice *lat, int32_t id, double pos[3], double vel[3],
+                             double omega[3], double force[3], double torque[3]);
+
+/* FP64 population mass and momentum summed over fluid cells. */
+vlb_status vlb_read_sums(vlb_lattice *lat, double *mass, double momentum[3]);
+
+/* Momentum exchange + polymer traction of the last step summed over all wall
+ * links (FP64), a diagnostic. */
+vlb_status vlb_read_wall_force(vlb_lattice *lat, double force[3]);
+
+/* Health check of the current state: largest |sum f c / rho| and number of
+ * non-finite populations.  Sets the sticky VLB_EUNSTABLE state (and returns
+ * it) when either exceeds the limits (speed 0.3 or any non-finite value).
+ * vlb_step also runs it every check_interval steps (default 1000; 0 = off). */
+vlb_status vlb_check_health(vlb_lattice *lat, double *max_speed, int64_t *non_finite);
+vlb_status vlb_set_check_interval(vlb_lattice *lat, int64_t steps);
+
+/* Checkpoint: parameters, mask, walls, particles, step count and the state in
+ * its storage precision.  vlb_load creates a new lattice. */
+vlb_status vlb_save(vlb_lattice *lat, const char *path);
+vlb_status vlb_load(const char *path, void *stream, vlb_lattice **out);
+
+/* Destroy the lattice and free its device memory (synchronises first). */
+void vlb_destroy(vlb_lattice *lat);
+
+/* Message of the last failed call on this lattice (or of the last failed
+ * create/load when lat is NULL).  Never NULL. */
+const char *vlb_last_error(const vlb_lattice *lat);
+
+/* Average device time of the last vlb_step call per kernel family, measured
+ * with HIP events on the lattice's stream when timing is on (ms; -1 when not
+ * measured).  which: 0 = stream-collide, 1 = stress update, 2 = particles. */
+vlb_status vlb_set_timing(vlb_lattice *lat, int32_t on);
+
+/* Rounding of stored values (default VLB_ROUND_STOCHASTIC, seed 0x2009). */
+vlb_status vlb_set_rounding(vlb_lattice *lat, vlb_rounding mode, uint32_t seed);
+double vlb_kernel_time_ms(const vlb_lattice *lat, int32_t which);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

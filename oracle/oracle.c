@@ -190,7 +190,8 @@ void or_collide_cell(const double f[19], const double F[3], double omega_plus,
 
 static long cell(int nx, int ny, int x, int y, int z) { return x + (long)nx * (y + (long)ny * z); }
 
-static int wrap(int v, int n) { return ((v % n) + n) % n; }
+/* wrap a coordinate that is at most one cell outside [0, n) */
+static int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
 /* Neighbour of (x,y,z) in direction d, always wrapped into the box (the
  * caller guarantees that non-periodic axes have solid end layers, so fluid

@@ -1,0 +1,1061 @@
+// Host runtime of libvlb: the C ABI of include/vlb.h over the gfx950 kernels.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "vlb.h"
+#include "vlb_internal.h"
+
+using vlb::Particle;
+
+namespace {
+
+thread_local std::string g_create_error = "no error";
+
+constexpr uint64_t kPlaneAlign = 256;  // elements; keeps every plane 512 B+ aligned
+
+size_t storage_bytes(int storage) { return storage == vlb::ST_F32 ? 4 : 2; }
+
+float default_scale(int storage) { return storage == vlb::ST_F16 ? 1024.f : 1.f; }
+
+}  // namespace
+
+struct vlb_lattice {
+    vlb::Geom g{};
+    int storage = 0;
+    float scale = 1.f, inv_scale = 1.f;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int device = 0;
+    uint8_t *d_mask = nullptr;
+    void *d_f[2] = {nullptr, nullptr};
+    float *d_tau[2] = {nullptr, nullptr};
+    float *d_u = nullptr;
+    double *d_wall = nullptr;
+    Particle *d_parts = nullptr;
+    double *d_partials = nullptr;
+    double *d_out = nullptr;
+    int32_t *d_counters = nullptr;
+    int n_walls = 0;
+    std::vector<double> wall_h;
+    std::vector<Particle> parts_h;  // host copy of static particle data
+    bool any_movable = false;
+    bool moving_walls = false;
+    std::vector<uint8_t> mask_h;
+    bool mask_h_valid = true;
+    vlb_params params{};
+    double wp = 1.0, wm = 1.0;
+    int rounding = VLB_ROUND_STOCHASTIC;
+    uint32_t seed = 0x2009u;
+    int polymer = 0;
+    int cur = 0;
+    int64_t step = 0;
+    int64_t check_interval = 1000;
+    bool unstable = false;
+    bool timing = false;
+    double ktime[3] = {-1.0, -1.0, -1.0};
+    std::vector<hipEvent_t> events;
+    std::string err = "no error";
+
+    vlb::Bound bound() const
+    {
+        vlb::Bound b;
+        b.wall_vel = d_wall;
+        b.n_walls = n_walls;
+        b.parts = d_parts;
+        b.n_parts = static_cast<int32_t>(parts_h.size());
+        b.moving = (any_movable || moving_walls) ? 1 : 0;
+        return b;
+    }
+};
+
+namespace {
+
+vlb_status fail(vlb_lattice *lat, vlb_status st, const std::string &msg)
+{
+    if (lat)
+        lat->err = msg;
+    else
+        g_create_error = msg;
+    return st;
+}
+
+vlb_status hip_fail(vlb_lattice *lat, hipError_t e, const char *what)
+{
+    return fail(lat, e == hipErrorOutOfMemory ? VLB_ENOMEM : VLB_EDEVICE,
+                std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(lat, expr, what)                      \
+    do {                                             \
+        hipError_t e_ = (expr);                      \
+        if (e_ != hipSuccess)                        \
+            return hip_fail((lat), e_, (what));      \
+    } while (0)
+
+uint64_t round_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
+
+bool rates(const vlb_params &p, double &wp, double &wm)
+{
+    const double eta_n = (1.0 - p.beta) * p.eta;
+    const double dwp = 1.0 / (3.0 * eta_n + 0.5);
+    double dwm = dwp;
+    if (p.magic >= 0.0)
+        dwm = 1.0 / (0.5 + p.magic / (1.0 / dwp - 0.5));
+    if (!(dwp > 0.0 && dwp < 2.0 && dwm > 0.0 && dwm < 2.0))
+        return false;
+    wp = dwp;
+    wm = dwm;
+    return true;
+}
+
+vlb_status check_dims(const vlb_dims *d)
+{
+    if (!d || d->nx < 1 || d->ny < 1 || d->nz < 1)
+        return VLB_EINVAL;
+    const uint64_t N = static_cast<uint64_t>(d->nx) * d->ny * d->nz;
+    if (N >= (1ull << 31))
+        return VLB_EINVAL;
+    return VLB_OK;
+}
+
+// every non-periodic axis needs solid first and last layers
+bool end_layers_solid(const vlb_dims *d, const uint8_t *mask)
+{
+    const int n[3] = {d->nx, d->ny, d->nz};
+    for (int ax = 0; ax < 3; ++ax) {
+        if (d->periodic[ax])
+            continue;
+        for (int z = 0; z < n[2]; ++z)
+            for (int y = 0; y < n[1]; ++y)
+                for (int x = 0; x < n[0]; ++x) {
+                    const int c[3] = {x, y, z};
+                    if (c[ax] != 0 && c[ax] != n[ax] - 1)
+                        continue;
+                    if (mask[x + static_cast<size_t>(n[0]) * (y + static_cast<size_t>(n[1]) * z)] == 0)
+                        return false;
+                }
+    }
+    return true;
+}
+
+vlb_status sync_mask_host(vlb_lattice *lat)
+{
+    if (lat->mask_h_valid)
+        return VLB_OK;
+    HIPCHK(lat, hipMemcpyAsync(lat->mask_h.data(), lat->d_mask, lat->g.N, hipMemcpyDeviceToHost,
+                               lat->stream),
+           "mask download");
+    HIPCHK(lat, hipStreamSynchronize(lat->stream), "mask download");
+    lat->mask_h_valid = true;
+    return VLB_OK;
+}
+
+vlb_status upload_particles(vlb_lattice *lat)
+{
+    if (lat->parts_h.empty())
+        return VLB_OK;
+    HIPCHK(lat, hipMemcpyAsync(lat->d_parts, lat->parts_h.data(),
+                               sizeof(Particle) * lat->parts_h.size(), hipMemcpyHostToDevice,
+                               lat->stream),
+           "particle upload");
+    HIPCHK(lat, hipStreamSynchronize(lat->stream), "particle upload");
+    return VLB_OK;
+}
+
+vlb_status download_particles(vlb_lattice *lat, std::vector<Particle> &out)
+{
+    out.resize(lat->parts_h.size());
+    if (out.empty())
+        return VLB_OK;
+    HIPCHK(lat, hipMemcpyAsync(out.data(), lat->d_parts, sizeof(Particle) * out.size(),
+                               hipMemcpyDeviceToHost, lat->stream),
+           "particle download");
+    HIPCHK(lat, hipStreamSynchronize(lat->stream), "particle download");
+    return VLB_OK;
+}
+
+void free_all(vlb_lattice *lat)
+{
+    if (lat->stream)
+        (void)hipStreamSynchronize(lat->stream);
+    void *ptrs[] = {lat->d_mask,  lat->d_f[0],     lat->d_f[1],   lat->d_tau[0],     lat->d_tau[1],
+                    lat->d_u,     lat->d_wall,     lat->d_parts,  lat->d_partials,   lat->d_out,
+                    lat->d_counters};
+    for (void *p : ptrs)
+        if (p)
+            (void)hipFree(p);
+    for (hipEvent_t e : lat->events)
+        (void)hipEventDestroy(e);
+    if (lat->own_stream && lat->stream)
+        (void)hipStreamDestroy(lat->stream);
+}
+
+// run `fn(device_scratch)` with a temporary device buffer and copy it to host
+template <class Fn>
+vlb_status read_via_scratch(vlb_lattice *lat, size_t bytes, void *host, Fn fn, const char *what)
+{
+    void *d = nullptr;
+    HIPCHK(lat, hipMalloc(&d, bytes), what);
+    hipError_t e = fn(static_cast<double *>(d));
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(host, d, bytes, hipMemcpyDeviceToHost, lat->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(lat->stream);
+    (void)hipFree(d);
+    if (e != hipSuccess)
+        return hip_fail(lat, e, what);
+    return VLB_OK;
+}
+
+template <class Fn>
+vlb_status write_via_scratch(vlb_lattice *lat, size_t bytes, const void *host, Fn fn,
+                             const char *what)
+{
+    void *d = nullptr;
+    HIPCHK(lat, hipMalloc(&d, bytes), what);
+    hipError_t e = hipMemcpyAsync(d, host, bytes, hipMemcpyHostToDevice, lat->stream);
+    if (e == hipSuccess)
+        e = fn(static_cast<const double *>(d));
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(lat->stream);
+    (void)hipFree(d);
+    if (e != hipSuccess)
+        return hip_fail(lat, e, what);
+    return VLB_OK;
+}
+
+// FP64 sums of the current state into out[8]
+vlb_status run_sums(vlb_lattice *lat, double out[8])
+{
+    HIPCHK(lat, vlb::launch_sums(lat->storage, lat->g, lat->d_mask, lat->d_f[lat->cur],
+                                 lat->inv_scale, lat->d_partials, lat->d_out, lat->stream),
+           "sums");
+    HIPCHK(lat, hipMemcpyAsync(out, lat->d_out, 8 * sizeof(double), hipMemcpyDeviceToHost,
+                               lat->stream),
+           "sums");
+    HIPCHK(lat, hipStreamSynchronize(lat->stream), "sums");
+    return VLB_OK;
+}
+
+constexpr double kMaxSpeed = 0.3;
+
+// |d|^2 evaluated left to right without fused multiply-add, the same way the
+// device-side coverage test does
+double sq_norm(const double d[3])
+{
+#pragma clang fp contract(off)
+    return d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t vlb_velocity(int32_t i, int32_t c[3], double *w)
+{
+    if (i >= 0 && i < vlb::Q) {
+        if (c) {
+            c[0] = vlb::CX[i];
+            c[1] = vlb::CY[i];
+            c[2] = vlb::CZ[i];
+        }
+        if (w)
+            *w = vlb::WD[i];
+    }
+    return vlb::Q;
+}
+
+size_t vlb_required_bytes(const vlb_dims *dims, vlb_storage storage, int32_t n_particles)
+{
+    if (check_dims(dims) != VLB_OK)
+        return 0;
+    const uint64_t N = static_cast<uint64_t>(dims->nx) * dims->ny * dims->nz;
+    const uint64_t P = round_up(N, kPlaneAlign);
+    const uint64_t pops = 2ull * vlb::Q * P * storage_bytes(storage);
+    const uint64_t tau = 2ull * 6 * P * sizeof(float);
+    const uint64_t u = 3ull * P * sizeof(float);
+    const uint64_t mask = round_up(N, 256);
+    const uint64_t small = sizeof(Particle) * vlb::MAX_PARTICLES + 64 * 3 * sizeof(double) +
+                           2048 * 8 * sizeof(double) + 4096;
+    (void)n_particles;
+    return static_cast<size_t>(pops + tau + u + mask + small);
+}
+
+vlb_status vlb_create(const vlb_dims *dims, const uint8_t *mask, const double *wall_velocity,
+                      int32_t n_walls, vlb_storage storage, void *stream, vlb_lattice **out)
+{
+    if (!out)
+        return fail(nullptr, VLB_EINVAL, "vlb_create: out is NULL");
+    *out = nullptr;
+    if (check_dims(dims) != VLB_OK)
+        return fail(nullptr, VLB_EINVAL, "vlb_create: invalid dimensions");
+    if (!mask)
+        return fail(nullptr, VLB_EINVAL, "vlb_create: mask is NULL");
+    if (storage != VLB_STORE_F32 && storage != VLB_STORE_F16 && storage != VLB_STORE_BF16)
+        return fail(nullptr, VLB_EINVAL, "vlb_create: unknown storage");
+    if (n_walls < 0 || n_walls > VLB_MAX_WALL_ID || (n_walls > 0 && !wall_velocity))
+        return fail(nullptr, VLB_EINVAL, "vlb_create: invalid wall table");
+    const uint64_t N = static_cast<uint64_t>(dims->nx) * dims->ny * dims->nz;
+    for (uint64_t n = 0; n < N; ++n)
+        if (mask[n] >= vlb::PART0)
+            return fail(nullptr, VLB_EINVAL, "vlb_create: mask values >= 64 are reserved");
+    if (!end_layers_solid(dims, mask))
+        return fail(nullptr, VLB_EINVAL,
+                    "vlb_create: a non-periodic axis needs solid first and last layers");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+        return fail(nullptr, VLB_EDEVICE, "vlb_create: no HIP device");
+
+    vlb_lattice *lat = new vlb_lattice();
+    (void)hipGetDevice(&lat->device);
+    lat->g.nx = dims->nx;
+    lat->g.ny = dims->ny;
+    lat->g.nz = dims->nz;
+    for (int a = 0; a < 3; ++a)
+        lat->g.per[a] = dims->periodic[a] ? 1 : 0;
+    lat->g.N = static_cast<uint32_t>(N);
+    lat->g.plane = round_up(N, kPlaneAlign);
+    lat->storage = storage;
+    lat->scale = default_scale(storage);
+    lat->inv_scale = 1.f / lat->scale;
+    lat->mask_h.assign(mask, mask + N);
+    lat->n_walls = n_walls;
+    lat->wall_h.assign(64 * 3, 0.0);
+    for (int w = 0; w < n_walls; ++w)
+        for (int a = 0; a < 3; ++a) {
+            lat->wall_h[3 * w + a] = wall_velocity[3 * w + a];
+            if (wall_velocity[3 * w + a] != 0.0)
+                lat->moving_walls = true;
+        }
+
+    auto bail = [&](hipError_t e, const char *what) {
+        std::string msg = std::string(what) + ": " + hipGetErrorString(e);
+        free_all(lat);
+        delete lat;
+        return fail(nullptr, e == hipErrorOutOfMemory ? VLB_ENOMEM : VLB_EDEVICE, msg);
+    };
+    hipError_t e;
+    if (stream) {
+        lat->stream = static_cast<hipStream_t>(stream);
+    } else {
+        if ((e = hipStreamCreate(&lat->stream)) != hipSuccess)
+            return bail(e, "stream");
+        lat->own_stream = true;
+    }
+    const uint64_t P = lat->g.plane;
+    const size_t es = storage_bytes(storage);
+    if ((e = hipMalloc(&lat->d_mask, round_up(N, 256))) != hipSuccess)
+        return bail(e, "mask");
+    for (int b = 0; b < 2; ++b) {
+        if ((e = hipMalloc(&lat->d_f[b], vlb::Q * P * es)) != hipSuccess)
+            return bail(e, "populations");
+        if ((e = hipMalloc(&lat->d_tau[b], 6 * P * sizeof(float))) != hipSuccess)
+            return bail(e, "stress");
+        if ((e = hipMemsetAsync(lat->d_tau[b], 0, 6 * P * sizeof(float), lat->stream)) != hipSuccess)
+            return bail(e, "stress");
+        if ((e = hipMemsetAsync(lat->d_f[b], 0, vlb::Q * P * es, lat->stream)) != hipSuccess)
+            return bail(e, "populations");
+    }
+    if ((e = hipMalloc(&lat->d_u, 3 * P * sizeof(float))) != hipSuccess)
+        return bail(e, "velocity");
+    if ((e = hipMemsetAsync(lat->d_u, 0, 3 * P * sizeof(float), lat->stream)) != hipSuccess)
+        return bail(e, "velocity");
+    if ((e = hipMalloc(&lat->d_wall, 64 * 3 * sizeof(double))) != hipSuccess)
+        return bail(e, "walls");
+    if ((e = hipMalloc(&lat->d_parts, vlb::MAX_PARTICLES * sizeof(Particle))) != hipSuccess)
+        return bail(e, "particles");
+    if ((e = hipMalloc(&lat->d_partials, static_cast<size_t>(vlb::sums_blocks(lat->g)) * 8 *
+                                             sizeof(double))) != hipSuccess)
+        return bail(e, "partials");
+    if ((e = hipMalloc(&lat->d_out, 16 * sizeof(double))) != hipSuccess)
+        return bail(e, "out");
+    if ((e = hipMalloc(&lat->d_counters, 4 * sizeof(int32_t))) != hipSuccess)
+        return bail(e, "counters");
+    if ((e = hipMemsetAsync(lat->d_counters, 0, 4 * sizeof(int32_t), lat->stream)) != hipSuccess)
+        return bail(e, "counters");
+    if ((e = hipMemcpyAsync(lat->d_mask, mask, N, hipMemcpyHostToDevice, lat->stream)) != hipSuccess)
+        return bail(e, "mask upload");
+    if ((e = hipMemcpyAsync(lat->d_wall, lat->wall_h.data(), 64 * 3 * sizeof(double),
+                            hipMemcpyHostToDevice, lat->stream)) != hipSuccess)
+        return bail(e, "wall upload");
+    if ((e = hipStreamSynchronize(lat->stream)) != hipSuccess)
+        return bail(e, "create");
+
+    vlb_params p{};
+    p.eta = 1.0 / 3.0;
+    p.beta = 0.0;
+    p.lambda_p = 1.0;
+    p.magic = 3.0 / 16.0;
+    if (vlb_set_params(lat, &p) != VLB_OK || vlb_init_equilibrium(lat, nullptr) != VLB_OK) {
+        std::string msg = lat->err;
+        free_all(lat);
+        delete lat;
+        return fail(nullptr, VLB_EDEVICE, "vlb_create: " + msg);
+    }
+    *out = lat;
+    return VLB_OK;
+}
+
+vlb_status vlb_set_params(vlb_lattice *lat, const vlb_params *p)
+{
+    if (!lat)
+        return VLB_EINVAL;
+    if (!p)
+        return fail(lat, VLB_EINVAL, "vlb_set_params: params is NULL");
+    if (!(p->eta > 0.0) || !(p->beta >= 0.0 && p->beta < 1.0))
+        return fail(lat, VLB_EINVAL, "vlb_set_params: need eta > 0 and 0 <= beta < 1");
+    if (p->beta > 0.0 && !(p->lambda_p >= 1.0))
+        return fail(lat, VLB_EINVAL, "vlb_set_params: lambda_p must be >= 1 when beta > 0");
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(p->body_force[a]))
+            return fail(lat, VLB_EINVAL, "vlb_set_params: non-finite body force");
+    double wp, wm;
+    if (!rates(*p, wp, wm))
+        return fail(lat, VLB_EINVAL, "vlb_set_params: relaxation rate outside (0, 2)");
+    lat->params = *p;
+    lat->wp = wp;
+    lat->wm = wm;
+    const int was = lat->polymer;
+    lat->polymer = p->beta > 0.0 ? 1 : 0;
+    if (was && !lat->polymer)
+        for (int b = 0; b < 2; ++b)
+            HIPCHK(lat, hipMemsetAsync(lat->d_tau[b], 0, 6 * lat->g.plane * sizeof(float),
+                                       lat->stream),
+                   "stress reset");
+    return VLB_OK;
+}
+
+vlb_status vlb_init_equilibrium(vlb_lattice *lat, const double *u)
+{
+    if (!lat)
+        return VLB_EINVAL;
+    vlb_status st = sync_mask_host(lat);
+    if (st != VLB_OK)
+        return st;
+    const size_t N = lat->g.N;
+    auto run = [&](const double *du) {
+        hipError_t e = vlb::launch_init_equilibrium(lat->storage, lat->g, lat->d_mask, du,
+                                                    lat->d_f[lat->cur], lat->scale, lat->stream);
+        if (e == hipSuccess)
+            e = hipMemsetAsync(lat->d_tau[lat->cur], 0, 6 * lat->g.plane * sizeof(float),
+                               lat->stream);
+        return e;
+    };
+    if (u) {
+        st = write_via_scratch(lat, 3 * N * sizeof(double), u, run, "vlb_init_equilibrium");
+    } else {
+        hipError_t e = run(nullptr);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(lat->stream);
+        if (e != hipSuccess)
+            return hip_fail(lat, e, "vlb_init_equilibrium");
+    }
+    if (st == VLB_OK) {
+        lat->step = 0;
+        lat->unstable = false;
+    }
+    return st;
+}
+
+vlb_status vlb_set_populations(vlb_lattice *lat, const double *f)
+{
+    if (!lat)
+        return VLB_EINVAL;
+    if (!f)
+        return fail(lat, VLB_EINVAL, "vlb_set_populations: f is NULL");
+    return write_via_scratch(
+        lat, static_cast<size_t>(vlb::Q) * lat->g.N * sizeof(double), f,
+        [&](const double *d) {
+            return vlb::launch_set_populations(lat->storage, lat->g, lat->d_mask, d,
+                                               lat->d_f[lat->cur], lat->scale, lat->stream);
+        },
+        "vlb_set_populations");
+}
+
+vlb_status vlb_set_stress(vlb_lattice *lat, const double *tau)
+{
+    if (!lat)
+        return VLB_EINVAL;
+    if (!tau)
+        return fail(lat, VLB_EINVAL, "vlb_set_stress: tau is NULL");
+    return write_via_scratch(
+        lat, 6 * static_cast<size_t>(lat->g.N) * sizeof(double), tau,
+        [&](const double *d) {
+            return vlb::launch_set_stress(lat->g, lat->d_mask, d, lat->d_tau[lat->cur],
+                                          lat->stream);
+        },
+        "vlb_set_stress");
+}
+
+vlb_status vlb_add_sphere(vlb_lattice *lat, const double center[3], double radius,
+                          double density_ratio, int32_t movable, const double f_ext[3],
+                          const double t_ext[3], int32_t *id_out)
+{
+    if (!lat)
+        return VLB_EINVAL;
+    if (!center || !(radius > 0.0) || !(density_ratio > 0.0))
+        return fail(lat, VLB_EINVAL, "vlb_add_sphere: invalid centre, radius or density");
+    if (lat->parts_h.size() >= static_cast<size_t>(vlb::MAX_PARTICLES))
+        return fail(lat, VLB_EINVAL, "vlb_add_sphere: particle table full");
+    vlb_status st = sync_mask_host(lat);
+    if (st != VLB_OK)
+        return st;
+    // current dynamic state of existing particles must be kept
+    std::vector<Particle> cur;
+    if ((st = download_particles(lat, cur)) != VLB_OK)
+        return st;
+    Particle P;
+    std::memset(&P, 0, sizeof(P));
+    for (int a = 0; a < 3; ++a) {
+        P.R[a] = center[a];
+        P.fext[a] = f_ext ? f_ext[a] : 0.0;
+        P.text[a] = t_ext ? t_ext[a] : 0.0;
+    }
+    P.radius = radius;
+    P.mass = density_ratio * 4.0 / 3.0 * M_PI * radius * radius * radius;
+    P.inertia = 0.4 * P.mass * radius * radius;
+    P.movable = movable ? 1 : 0;
+    const int id = static_cast<int>(cur.size());
+    const int n[3] = {lat->g.nx, lat->g.ny, lat->g.nz};
+    std::vector<uint32_t> cells;
+    for (int z = 0; z < n[2]; ++z)
+        for (int y = 0; y < n[1]; ++y)
+            for (int x = 0; x < n[0]; ++x) {
+                const int c[3] = {x, y, z};
+                double d[3];
+                for (int k = 0; k < 3; ++k) {
+                    d[k] = static_cast<double>(c[k]) - P.R[k];
+                    if (lat->g.per[k]) {
+                        const double L = static_cast<double>(n[k]);
+                        d[k] -= L * std::floor(d[k] / L + 0.5);
+                    }
+                }
+                if (sq_norm(d) < radius * radius) {
+                    const uint32_t idx = x + static_cast<uint32_t>(n[0]) * (y + static_cast<uint32_t>(n[1]) * z);
+                    if (lat->mask_h[idx] != 0)
+                        return fail(lat, VLB_EINVAL, "vlb_add_sphere: overlaps a non-fluid cell");
+                    cells.push_back(idx);
+                }
+            }
+    for (uint32_t idx : cells)
+        lat->mask_h[idx] = static_cast<uint8_t>(vlb::PART0 + id);
+    cur.push_back(P);
+    lat->parts_h = cur;
+    if (movable)
+        lat->any_movable = true;
+    HIPCHK(lat, hipMemcpyAsync(lat->d_mask, lat->mask_h.data(), lat->g.N, hipMemcpyHostToDevice,
+                               lat->stream),
+           "mask upload");
+    if ((st = upload_particles(lat)) != VLB_OK)
+        return st;
+    if (id_out)
+        *id_out = id;
+    return VLB_OK;
+}
+
+vlb_status vlb_step(vlb_lattice *lat, int64_t n_steps)
+{
+    if (!lat)
+        return VLB_EINVAL;
+    if (n_steps < 0)
+        return fail(lat, VLB_EINVAL, "vlb_step: negative step count");
+    if (lat->unstable)
+        return fail(lat, VLB_EUNSTABLE, "vlb_step: lattice is unstable (sticky)");
+    vlb::StepArgs a{};
+    a.g = lat->g;
+    a.b = lat->bound();
+    a.mask = lat->d_mask;
+    a.u = lat->d_u;
+    a.wp = lat->wp;
+    a.wm = lat->wm;
+    for (int k = 0; k < 3; ++k)
+        a.g3[k] = lat->params.body_force[k];
+    a.polymer = lat->polymer;
+    if (lat->polymer) {
+        a.eta_p_lam = lat->params.beta * lat->params.eta / lat->params.lambda_p;
+        a.inv_lam = 1.0 / lat->params.lambda_p;
+    }
+    a.stochastic = lat->rounding == VLB_ROUND_STOCHASTIC ? 1 : 0;
+    a.seed = lat->seed;
+    a.scale = lat->scale;
+    a.inv_scale = lat->inv_scale;
+    a.remap = 1;
+    const int nev = lat->timing ? 6 : 0;
+    if (lat->timing && lat->events.size() < static_cast<size_t>(nev * n_steps)) {
+        while (lat->events.size() < static_cast<size_t>(nev * n_steps)) {
+            hipEvent_t e;
+            HIPCHK(lat, hipEventCreate(&e), "timing events");
+            lat->events.push_back(e);
+        }
+    }
+    for (int64_t s = 0; s < n_steps; ++s) {
+        a.fin = lat->d_f[lat->cur];
+        a.fout = lat->d_f[lat->cur ^ 1];
+        a.tin = lat->d_tau[lat->cur];
+        a.tout = lat->d_tau[lat->cur ^ 1];
+        a.step = static_cast<uint32_t>(lat->step);
+        hipEvent_t *ev = lat->timing ? &lat->events[nev * s] : nullptr;
+        if (ev)
+            HIPCHK(lat, hipEventRecord(ev[0], lat->stream), "event");
+        HIPCHK(lat, vlb::launch_lb_step(lat->storage, a, lat->stream), "stream-collide launch");
+        if (ev)
+            HIPCHK(lat, hipEventRecord(ev[1], lat->stream), "event");
+        if (lat->polymer)
+            HIPCHK(lat, vlb::launch_fv_step(lat->storage, a, lat->stream), "stress update launch");
+        if (ev)
+            HIPCHK(lat, hipEventRecord(ev[2], lat->stream), "event");
+        if (lat->any_movable) {
+            const int np = static_cast<int>(lat->parts_h.size());
+            HIPCHK(lat, vlb::launch_particle_forces(lat->storage, lat->g, lat->d_mask, a.fout, a.tin,
+                                                    lat->polymer, lat->inv_scale, lat->d_parts, np,
+                                                    lat->stream),
+                   "particle forces");
+            HIPCHK(lat, vlb::launch_particle_update(lat->g, lat->d_parts, np, lat->stream),
+                   "particle update");
+            HIPCHK(lat, vlb::launch_conversion(lat->storage, lat->g, a.b, lat->d_mask, a.fout,
+                                               a.tout, lat->scale, lat->inv_scale,
+                                               lat->d_counters, lat->stream),
+                   "conversion");
+            lat->mask_h_valid = false;
+        }
+        if (ev)
+            HIPCHK(lat, hipEventRecord(ev[3], lat->stream), "event");
+        lat->cur ^= 1;
+        lat->step += 1;
+        if (lat->check_interval > 0 && lat->step % lat->check_interval == 0) {
+            double max_speed;
+            int64_t bad;
+            vlb_status st = vlb_check_health(lat, &max_speed, &bad);
+            if (st != VLB_OK)
+                return st;
+        }
+    }
+    if (lat->timing && n_steps > 0) {
+        HIPCHK(lat, hipStreamSynchronize(lat->stream), "timing");
+        double acc[3] = {0, 0, 0};
+        for (int64_t s = 0; s < n_steps; ++s) {
+            hipEvent_t *ev = &lat->events[nev * s];
+            for (int k = 0; k < 3; ++k) {
+                float ms = 0.f;
+                HIPCHK(lat, hipEventElapsedTime(&ms, ev[k], ev[k + 1]), "timing");
+                acc[k] += ms;
+            }
+        }
+        for (int k = 0; k < 3; ++k)
+            lat->ktime[k] = acc[k] / static_cast<double>(n_steps);
+    }
+    return VLB_OK;
+}
+
+vlb_status vlb_sync(vlb_lattice *lat)
+{
+    if (!lat)
+        return VLB_EINVAL;
+    HIPCHK(lat, hipStreamSynchronize(lat->stream), "vlb_sync");
+    return VLB_OK;
+}
+
+int64_t vlb_step_count(const vlb_lattice *lat) { return lat ? lat->step : -1; }
+
+vlb_status vlb_read_density(vlb_lattice *lat, double *rho)
+{
+    if (!lat)
+        return VLB_EINVAL;
+    if (!rho)
+        return fail(lat, VLB_EINVAL, "vlb_read_density: NULL output");
+    const float gv[3] = {static_cast<float>(lat->params.body_force[0]),
+                         static_cast<float>(lat->params.body_force[1]),
+                         static_cast<float>(lat->params.body_force[2])};
+    return read_via_scratch(
+        lat, static_cast<size_t>(lat->g.N) * sizeof(double), rho,
+        [&](double *d) {
+            return vlb::launch_read_moments(lat->storage, lat->g, lat->bound(), lat->d_mask,
+                                            lat->d_f[lat->cur], lat->d_tau[lat->cur], lat->polymer,
+                                            gv, lat->inv_scale, d, nullptr, lat->stream);
+        },
+        "vlb_read_density");
+}
+
+vlb_status vlb_read_velocity(vlb_lattice *lat, double *u)
+{
+    if (!lat)
+        return VLB_EINVAL;
+    if (!u)
+        return fail(lat, VLB_EINVAL, "vlb_read_velocity: NULL output");
+    const float gv[3] = {static_cast<float>(lat->params.body_force[0]),
+                         static_cast<float>(lat->params.body_force[1]),
+                         static_cast<float>(lat->params.body_force[2])};
+    return read_via_scratch(
+        lat, 3 * static_cast<size_t>(lat->g.N) * sizeof(double), u,
+        [&](double *d) {
+            return vlb::launch_read_moments(lat->storage, lat->g, lat->bound(), lat->d_mask,
+                                            lat->d_f[lat->cur], lat->d_tau[lat->cur], lat->polymer,
+                                            gv, lat->inv_scale, nullptr, d, lat->stream);
+        },
+        "vlb_read_velocity");
+}
+
+vlb_status vlb_read_stress(vlb_lattice *lat, double *tau)
+{
+    if (!lat)
+        return VLB_EINVAL;
+    if (!tau)
+        return fail(lat, VLB_EINVAL, "vlb_read_stress: NULL output");
+    return read_via_scratch(
+        lat, 6 * static_cast<size_t>(lat->g.N) * sizeof(double), tau,
+        [&](double *d) {
+            return vlb::launch_read_stress(lat->g, lat->d_mask, lat->d_tau[lat->cur], d,
+                                           lat->stream);
+        },
+        "vlb_read_stress");
+}
+
+vlb_status vlb_read_populations(vlb_lattice *lat, double *f)
+{
+    if (!lat)
+        return VLB_EINVAL;
+    if (!f)
+        return fail(lat, VLB_EINVAL, "vlb_read_populations: NULL output");
+    return read_via_scratch(
+        lat, static_cast<size_t>(vlb::Q) * lat->g.N * sizeof(double), f,
+        [&](double *d) {
+            return vlb::launch_read_populations(lat->storage, lat->g, lat->d_mask,
+                                                lat->d_f[lat->cur], lat->inv_scale, d, lat->stream);
+        },
+        "vlb_read_populations");
+}
+
+vlb_status vlb_read_mask(vlb_lattice *lat, uint8_t *mask)
+{
+    if (!lat)
+        return VLB_EINVAL;
+    if (!mask)
+        return fail(lat, VLB_EINVAL, "vlb_read_mask: NULL output");
+    vlb_status st = sync_mask_host(lat);
+    if (st != VLB_OK)
+        return st;
+    std::memcpy(mask, lat->mask_h.data(), lat->g.N);
+    return VLB_OK;
+}
+
+vlb_status vlb_read_particle(vlb_lattice *lat, int32_t id, double pos[3], double vel[3],
+                             double omega[3], double force[3], double torque[3])
+{
+    if (!lat)
+        return VLB_EINVAL;
+    if (id < 0 || id >= static_cast<int32_t>(lat->parts_h.size()))
+        return fail(lat, VLB_ENOTFOUND, "vlb_read_particle: unknown particle id");
+    const int np = static_cast<int>(lat->parts_h.size());
+    if (!lat->any_movable && lat->step > 0) {
+        // fixed geometry: the last step's exchange is recomputed from the
+        // state it left (its output populations and its input stress)
+        HIPCHK(lat, vlb::launch_particle_forces(lat->storage, lat->g, lat->d_mask,
+                                                lat->d_f[lat->cur], lat->d_tau[lat->cur ^ 1],
+                                                lat->polymer, lat->inv_scale, lat->d_parts, np,
+                                                lat->stream),
+               "particle forces");
+        HIPCHK(lat, vlb::launch_particle_update(lat->g, lat->d_parts, np, lat->stream),
+               "particle totals");
+    }
+    std::vector<Particle> cur;
+    vlb_status st = download_particles(lat, cur);
+    if (st != VLB_OK)
+        return st;
+    const Particle &P = cur[id];
+    for (int a = 0; a < 3; ++a) {
+        if (pos)
+            pos[a] = P.R[a];
+        if (vel)
+            vel[a] = P.v[a];
+        if (omega)
+            omega[a] = P.w[a];
+        if (force)
+            force[a] = lat->step > 0 ? P.ftot[a] : 0.0;
+        if (torque)
+            torque[a] = lat->step > 0 ? P.ttot[a] : 0.0;
+    }
+    return VLB_OK;
+}
+
+vlb_status vlb_read_sums(vlb_lattice *lat, double *mass, double momentum[3])
+{
+    if (!lat)
+        return VLB_EINVAL;
+    double out[8];
+    vlb_status st = run_sums(lat, out);
+    if (st != VLB_OK)
+        return st;
+    if (mass)
+        *mass = out[6] + out[0];
+    if (momentum)
+        for (int a = 0; a < 3; ++a)
+            momentum[a] = out[1 + a];
+    return VLB_OK;
+}
+
+vlb_status vlb_read_wall_force(vlb_lattice *lat, double force[3])
+{
+    if (!lat)
+        return VLB_EINVAL;
+    if (!force)
+        return fail(lat, VLB_EINVAL, "vlb_read_wall_force: NULL output");
+    if (lat->step == 0) {
+        force[0] = force[1] = force[2] = 0.0;
+        return VLB_OK;
+    }
+    HIPCHK(lat, vlb::launch_wall_force(lat->storage, lat->g, lat->d_mask, lat->d_f[lat->cur],
+                                       lat->d_tau[lat->cur ^ 1], lat->polymer, lat->inv_scale,
+                                       lat->d_partials, lat->d_out, lat->stream),
+           "wall force");
+    HIPCHK(lat, hipMemcpyAsync(force, lat->d_out, 3 * sizeof(double), hipMemcpyDeviceToHost,
+                               lat->stream),
+           "wall force");
+    HIPCHK(lat, hipStreamSynchronize(lat->stream), "wall force");
+    return VLB_OK;
+}
+
+vlb_status vlb_check_health(vlb_lattice *lat, double *max_speed, int64_t *non_finite)
+{
+    if (!lat)
+        return VLB_EINVAL;
+    double out[8];
+    vlb_status st = run_sums(lat, out);
+    if (st != VLB_OK)
+        return st;
+    if (max_speed)
+        *max_speed = out[4];
+    if (non_finite)
+        *non_finite = static_cast<int64_t>(out[5]);
+    if (out[5] > 0.0 || !(out[4] <= kMaxSpeed)) {
+        lat->unstable = true;
+        char buf[160];
+        std::snprintf(buf, sizeof buf, "unstable at step %lld: max speed %.3g, %lld non-finite cells",
+                      static_cast<long long>(lat->step), out[4], static_cast<long long>(out[5]));
+        return fail(lat, VLB_EUNSTABLE, buf);
+    }
+    return VLB_OK;
+}
+
+vlb_status vlb_set_check_interval(vlb_lattice *lat, int64_t steps)
+{
+    if (!lat)
+        return VLB_EINVAL;
+    if (steps < 0)
+        return fail(lat, VLB_EINVAL, "vlb_set_check_interval: negative interval");
+    lat->check_interval = steps;
+    return VLB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// checkpoint
+
+namespace {
+constexpr uint64_t kMagic = 0x31304B434C424C56ull;  // "VLBLCK01"
+
+struct FileHeader {
+    uint64_t magic;
+    int32_t nx, ny, nz, per[3];
+    int32_t storage, n_walls, n_parts, polymer;
+    int64_t step;
+    vlb_params params;
+    float scale;
+    int32_t any_movable;
+};
+}  // namespace
+
+vlb_status vlb_save(vlb_lattice *lat, const char *path)
+{
+    if (!lat)
+        return VLB_EINVAL;
+    if (!path)
+        return fail(lat, VLB_EINVAL, "vlb_save: path is NULL");
+    vlb_status st = sync_mask_host(lat);
+    if (st != VLB_OK)
+        return st;
+    std::vector<Particle> parts;
+    if ((st = download_particles(lat, parts)) != VLB_OK)
+        return st;
+    const uint64_t N = lat->g.N;
+    const size_t es = storage_bytes(lat->storage);
+    std::vector<char> f(vlb::Q * N * es);
+    std::vector<float> tau(6 * N), tau_prev(6 * N);
+    for (int i = 0; i < vlb::Q; ++i)
+        HIPCHK(lat, hipMemcpyAsync(f.data() + i * N * es,
+                                   static_cast<char *>(lat->d_f[lat->cur]) + i * lat->g.plane * es,
+                                   N * es, hipMemcpyDeviceToHost, lat->stream),
+               "vlb_save");
+    for (int c = 0; c < 6; ++c) {
+        HIPCHK(lat, hipMemcpyAsync(tau.data() + c * N, lat->d_tau[lat->cur] + c * lat->g.plane,
+                                   N * sizeof(float), hipMemcpyDeviceToHost, lat->stream),
+               "vlb_save");
+        HIPCHK(lat, hipMemcpyAsync(tau_prev.data() + c * N,
+                                   lat->d_tau[lat->cur ^ 1] + c * lat->g.plane, N * sizeof(float),
+                                   hipMemcpyDeviceToHost, lat->stream),
+               "vlb_save");
+    }
+    HIPCHK(lat, hipStreamSynchronize(lat->stream), "vlb_save");
+    FILE *fp = std::fopen(path, "wb");
+    if (!fp)
+        return fail(lat, VLB_EINVAL, std::string("vlb_save: cannot open ") + path);
+    FileHeader h{};
+    h.magic = kMagic;
+    h.nx = lat->g.nx;
+    h.ny = lat->g.ny;
+    h.nz = lat->g.nz;
+    for (int a = 0; a < 3; ++a)
+        h.per[a] = lat->g.per[a];
+    h.storage = lat->storage;
+    h.n_walls = lat->n_walls;
+    h.n_parts = static_cast<int32_t>(parts.size());
+    h.polymer = lat->polymer;
+    h.step = lat->step;
+    h.params = lat->params;
+    h.scale = lat->scale;
+    h.any_movable = lat->any_movable;
+    bool ok = std::fwrite(&h, sizeof h, 1, fp) == 1;
+    ok = ok && std::fwrite(lat->wall_h.data(), sizeof(double), 64 * 3, fp) == 64 * 3;
+    ok = ok && (parts.empty() || std::fwrite(parts.data(), sizeof(Particle), parts.size(), fp) ==
+                                     parts.size());
+    ok = ok && std::fwrite(lat->mask_h.data(), 1, N, fp) == N;
+    ok = ok && std::fwrite(f.data(), 1, f.size(), fp) == f.size();
+    ok = ok && std::fwrite(tau.data(), sizeof(float), tau.size(), fp) == tau.size();
+    ok = ok && std::fwrite(tau_prev.data(), sizeof(float), tau_prev.size(), fp) == tau_prev.size();
+    ok = (std::fclose(fp) == 0) && ok;
+    if (!ok)
+        return fail(lat, VLB_EINVAL, std::string("vlb_save: write failed for ") + path);
+    return VLB_OK;
+}
+
+vlb_status vlb_load(const char *path, void *stream, vlb_lattice **out)
+{
+    if (!path || !out)
+        return fail(nullptr, VLB_EINVAL, "vlb_load: NULL argument");
+    *out = nullptr;
+    FILE *fp = std::fopen(path, "rb");
+    if (!fp)
+        return fail(nullptr, VLB_EINVAL, std::string("vlb_load: cannot open ") + path);
+    FileHeader h{};
+    if (std::fread(&h, sizeof h, 1, fp) != 1 || h.magic != kMagic || h.n_parts < 0 ||
+        h.n_parts > vlb::MAX_PARTICLES) {
+        std::fclose(fp);
+        return fail(nullptr, VLB_EINVAL, "vlb_load: not a lattice checkpoint");
+    }
+    vlb_dims d{};
+    d.nx = h.nx;
+    d.ny = h.ny;
+    d.nz = h.nz;
+    for (int a = 0; a < 3; ++a)
+        d.periodic[a] = static_cast<uint8_t>(h.per[a]);
+    if (check_dims(&d) != VLB_OK) {
+        std::fclose(fp);
+        return fail(nullptr, VLB_EINVAL, "vlb_load: invalid dimensions");
+    }
+    const uint64_t N = static_cast<uint64_t>(h.nx) * h.ny * h.nz;
+    const size_t es = storage_bytes(h.storage);
+    std::vector<double> walls(64 * 3);
+    std::vector<Particle> parts(h.n_parts);
+    std::vector<uint8_t> mask(N);
+    std::vector<char> f(vlb::Q * N * es);
+    std::vector<float> tau(6 * N), tau_prev(6 * N);
+    bool ok = std::fread(walls.data(), sizeof(double), walls.size(), fp) == walls.size();
+    ok = ok && (parts.empty() || std::fread(parts.data(), sizeof(Particle), parts.size(), fp) ==
+                                     parts.size());
+    ok = ok && std::fread(mask.data(), 1, N, fp) == N;
+    ok = ok && std::fread(f.data(), 1, f.size(), fp) == f.size();
+    ok = ok && std::fread(tau.data(), sizeof(float), tau.size(), fp) == tau.size();
+    ok = ok && std::fread(tau_prev.data(), sizeof(float), tau_prev.size(), fp) == tau_prev.size();
+    std::fclose(fp);
+    if (!ok)
+        return fail(nullptr, VLB_EINVAL, "vlb_load: truncated checkpoint");
+    // create on a particle-free mask, then restore the saved mask verbatim
+    std::vector<uint8_t> base(mask);
+    for (auto &m : base)
+        if (m >= vlb::PART0)
+            m = 0;
+    vlb_lattice *lat = nullptr;
+    vlb_status st = vlb_create(&d, base.data(), walls.data(), h.n_walls,
+                               static_cast<vlb_storage>(h.storage), stream, &lat);
+    if (st != VLB_OK)
+        return st;
+    auto bail = [&](vlb_status s2) {
+        g_create_error = lat->err;
+        vlb_destroy(lat);
+        return s2;
+    };
+    if ((st = vlb_set_params(lat, &h.params)) != VLB_OK)
+        return bail(st);
+    lat->mask_h = mask;
+    lat->parts_h = parts;
+    lat->any_movable = h.any_movable != 0;
+    lat->step = h.step;
+    lat->scale = h.scale;
+    lat->inv_scale = 1.f / h.scale;
+    hipError_t e = hipMemcpyAsync(lat->d_mask, mask.data(), N, hipMemcpyHostToDevice, lat->stream);
+    for (int i = 0; e == hipSuccess && i < vlb::Q; ++i)
+        e = hipMemcpyAsync(static_cast<char *>(lat->d_f[lat->cur]) + i * lat->g.plane * es,
+                           f.data() + i * N * es, N * es, hipMemcpyHostToDevice, lat->stream);
+    for (int c = 0; e == hipSuccess && c < 6; ++c) {
+        e = hipMemcpyAsync(lat->d_tau[lat->cur] + c * lat->g.plane, tau.data() + c * N,
+                           N * sizeof(float), hipMemcpyHostToDevice, lat->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(lat->d_tau[lat->cur ^ 1] + c * lat->g.plane, tau_prev.data() + c * N,
+                               N * sizeof(float), hipMemcpyHostToDevice, lat->stream);
+    }
+    if (e == hipSuccess && !parts.empty())
+        e = hipMemcpyAsync(lat->d_parts, parts.data(), sizeof(Particle) * parts.size(),
+                           hipMemcpyHostToDevice, lat->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(lat->stream);
+    if (e != hipSuccess) {
+        hip_fail(lat, e, "vlb_load");
+        return bail(VLB_EDEVICE);
+    }
+    *out = lat;
+    return VLB_OK;
+}
+
+void vlb_destroy(vlb_lattice *lat)
+{
+    if (!lat)
+        return;
+    free_all(lat);
+    delete lat;
+}
+
+const char *vlb_last_error(const vlb_lattice *lat)
+{
+    return lat ? lat->err.c_str() : g_create_error.c_str();
+}
+
+vlb_status vlb_set_rounding(vlb_lattice *lat, vlb_rounding mode, uint32_t seed)
+{
+    if (!lat)
+        return VLB_EINVAL;
+    if (mode != VLB_ROUND_NEAREST && mode != VLB_ROUND_STOCHASTIC)
+        return fail(lat, VLB_EINVAL, "vlb_set_rounding: unknown mode");
+    lat->rounding = mode;
+    lat->seed = seed;
+    return VLB_OK;
+}
+
+vlb_status vlb_set_timing(vlb_lattice *lat, int32_t on)
+{
+    if (!lat)
+        return VLB_EINVAL;
+    lat->timing = on != 0;
+    return VLB_OK;
+}
+
+double vlb_kernel_time_ms(const vlb_lattice *lat, int32_t which)
+{
+    if (!lat || which < 0 || which > 2)
+        return -1.0;
+    return lat->ktime[which];
+}
+
+}  // extern "C"

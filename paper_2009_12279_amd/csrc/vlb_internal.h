@@ -1,0 +1,124 @@
+// Internal declarations shared by the host runtime and the gfx950 kernels of
+// libvlb.  Not part of the public ABI (include/vlb.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace vlb {
+
+constexpr int Q = 19;
+constexpr int PART0 = 64;          // mask byte of particle 0
+constexpr int MAX_PARTICLES = 192;
+constexpr int BLOCK = 256;         // threads per block of the per-cell kernels
+
+// D3Q19 in the public order: rest, 6 faces, 12 edges, opposite directions
+// adjacent (i odd, i+1 is its opposite).
+constexpr int CX[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+constexpr int CY[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+constexpr int CZ[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+constexpr int OPP[Q] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+constexpr float WF[Q] = {1.f / 3.f,   1.f / 18.f, 1.f / 18.f, 1.f / 18.f, 1.f / 18.f,
+                         1.f / 18.f,  1.f / 18.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f,
+                         1.f / 36.f,  1.f / 36.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f,
+                         1.f / 36.f,  1.f / 36.f, 1.f / 36.f, 1.f / 36.f};
+constexpr double WD[Q] = {1.0 / 3.0,  1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0,
+                          1.0 / 18.0, 1.0 / 18.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
+                          1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
+                          1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+
+// Stress components xx, yy, zz, xy, xz, yz.  TROW[k][j] is the component index
+// of tau_kj.
+constexpr int TROW[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
+
+enum Storage : int { ST_F32 = 0, ST_F16 = 1, ST_BF16 = 2 };
+
+// Particle record, device resident, FP64 (Section 3.4).
+struct Particle {
+    double R[3], v[3], w[3];
+    double radius, mass, inertia;
+    int32_t movable, pad;
+    double fext[3], text[3];
+    double fconv[3], tconv[3];  // momentum owed by the last conversion
+    double fmex[3], tmex[3];    // last step: momentum exchange
+    double ftau[3], ttau[3];    // last step: polymer traction
+    double ftot[3], ttot[3];    // last step: total applied
+};
+
+// Geometry common to every kernel.
+struct Geom {
+    int32_t nx, ny, nz;
+    int32_t per[3];
+    uint32_t N;        // cells
+    uint64_t plane;    // elements between consecutive planes of a field
+};
+
+struct Bound {
+    const double *wall_vel;  // [n_walls][3]
+    int32_t n_walls;
+    const Particle *parts;
+    int32_t n_parts;
+    int32_t moving;          // any moving wall or movable particle
+};
+
+struct StepArgs {
+    Geom g;
+    Bound b;
+    const uint8_t *mask;
+    const void *fin;
+    void *fout;
+    const float *tin;
+    float *tout;
+    float *u;                // 3 planes, u^n for the stress update
+    double wp, wm;           // omega+, omega-
+    double g3[3];            // body force density
+    double eta_p_lam, inv_lam;
+    float scale, inv_scale;  // storage scale s and 1/s
+    int32_t polymer;
+    int32_t remap;           // XCD-aware block order
+    int32_t stochastic;      // stochastic rounding of stored values
+    uint32_t step;           // step index (random stream of the rounding)
+    uint32_t seed;
+};
+
+// Host-side launchers (vlb_kernels.hip).
+hipError_t launch_lb_step(int storage, const StepArgs &a, hipStream_t s);
+hipError_t launch_fv_step(int storage, const StepArgs &a, hipStream_t s);
+hipError_t launch_init_equilibrium(int storage, const Geom &g, const uint8_t *mask,
+                                   const double *u, void *f, float scale, hipStream_t s);
+hipError_t launch_set_populations(int storage, const Geom &g, const uint8_t *mask,
+                                  const double *f_in, void *f, float scale, hipStream_t s);
+hipError_t launch_set_stress(const Geom &g, const uint8_t *mask, const double *tau_in,
+                             float *tau, hipStream_t s);
+hipError_t launch_read_moments(int storage, const Geom &g, const Bound &b, const uint8_t *mask,
+                               const void *f, const float *tau, int polymer, const float gvec[3],
+                               float inv_scale, double *rho_out, double *u_out, hipStream_t s);
+hipError_t launch_read_populations(int storage, const Geom &g, const uint8_t *mask, const void *f,
+                                   float inv_scale, double *out, hipStream_t s);
+hipError_t launch_read_stress(const Geom &g, const uint8_t *mask, const float *tau, double *out,
+                              hipStream_t s);
+// FP64 population mass/momentum + health (max speed, non-finite count):
+// partial sums per block into `partials` (nblocks x 6), then a final pass
+// into out[6] = {mass_dev, px, py, pz, max_speed, non_finite}.
+int sums_blocks(const Geom &g);
+hipError_t launch_sums(int storage, const Geom &g, const uint8_t *mask, const void *f,
+                       float inv_scale, double *partials, double *out, hipStream_t s);
+// Per-particle momentum exchange + polymer traction over each particle's
+// bounding box (one block per particle, deterministic FP64 reduction).
+hipError_t launch_particle_forces(int storage, const Geom &g, const uint8_t *mask, const void *f,
+                                  const float *tau_n, int polymer, float inv_scale,
+                                  Particle *parts, int n_parts, hipStream_t s);
+// Same over wall links of the whole lattice into out[3] (two-stage).
+hipError_t launch_wall_force(int storage, const Geom &g, const uint8_t *mask, const void *f,
+                             const float *tau_n, int polymer, float inv_scale, double *partials,
+                             double *out, hipStream_t s);
+// Totals, symplectic Euler for movable particles.
+hipError_t launch_particle_update(const Geom &g, Particle *parts, int n_parts, hipStream_t s);
+// Fluid/solid conversion around every movable particle.
+hipError_t launch_conversion(int storage, const Geom &g, const Bound &b, uint8_t *mask, void *f,
+                             float *tau, float scale, float inv_scale, int32_t *counters,
+                             hipStream_t s);
+
+}  // namespace vlb

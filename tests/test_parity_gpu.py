@@ -1,0 +1,178 @@
+"""GPU (libvlb, gfx950) against the FP64 oracle on identical seeded inputs.
+
+FP32 storage must stay within the stated tolerance (1e-5 relative on velocity
+and stress for the workloads; tighter on single steps).  Every case prints
+its name before touching the GPU."""
+import numpy as np
+import pytest
+
+from paper_2009_12279_amd import inputs
+from parity import Case, build, compare, log
+
+pytestmark = pytest.mark.gpu
+
+
+def random_case(seed, shape, periodic, walls_moving=False, sphere=None, beta=0.4,
+                solid_frac=0.12, magic=3 / 16):
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = shape
+    mask = (rng.uniform(size=(nz, ny, nx)) < solid_frac).astype(np.uint8)
+    wall_velocity = None
+    if walls_moving:
+        wall_velocity = [[0.0, 0.0, 0.0], [3e-3, -1e-3, 2e-3]]
+        mask[mask == 1] = rng.integers(1, 3, size=int((mask == 1).sum())).astype(np.uint8)
+    for ax in range(3):
+        if not periodic[ax]:
+            sl0 = [slice(None)] * 3
+            sl1 = [slice(None)] * 3
+            sl0[2 - ax] = 0
+            sl1[2 - ax] = shape[ax] - 1
+            mask[tuple(sl0)] = 1
+            mask[tuple(sl1)] = 2 if walls_moving else 1
+    spheres = []
+    if sphere is not None:
+        c, r = sphere
+        # clear the sphere's neighbourhood so it can be placed
+        z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+        d2 = (x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2]) ** 2
+        inner = (d2 < (r + 0.01) ** 2)
+        mask[inner] = 0
+        spheres.append(dict(center=c, radius=r))
+    c, w = zip(*[__import__("paper_2009_12279_amd").vlb.vlb_velocity(i) for i in range(19)])
+    c = np.array(c)
+    w = np.array(w)
+    u = 2e-3 * rng.standard_normal((3, nz, ny, nx))
+    f0 = np.zeros((19, nz, ny, nx))
+    for i in range(19):
+        cu = c[i, 0] * u[0] + c[i, 1] * u[1] + c[i, 2] * u[2]
+        f0[i] = w[i] * (1 + 3 * cu + 4.5 * cu ** 2) + 2e-4 * w[i] * rng.standard_normal((nz, ny, nx))
+    tau0 = 1e-4 * rng.standard_normal((6, nz, ny, nx))
+    params = dict(eta=0.2, beta=beta, lambda_p=25.0, magic=magic,
+                  body_force=tuple(1e-5 * rng.standard_normal(3)))
+    return Case(f"random{seed}", shape, mask, periodic, wall_velocity, params, spheres,
+                f0=f0, tau0=tau0)
+
+
+BRUTE = [
+    (1, (5, 6, 7), (1, 1, 1), False, None),
+    (2, (8, 5, 6), (1, 0, 1), True, None),
+    (3, (9, 9, 9), (0, 0, 0), True, ((4.3, 4.6, 4.4), 1.8)),
+    (4, (7, 4, 3), (1, 1, 0), False, None),
+    (5, (12, 10, 11), (1, 0, 0), True, ((6.2, 4.9, 5.1), 2.5)),
+]
+
+
+@pytest.mark.parametrize("seed,shape,periodic,moving,sphere", BRUTE)
+@pytest.mark.parametrize("steps", [1, 30])
+def test_brute_force_tiny_lattices(seed, shape, periodic, moving, sphere, steps):
+    case = random_case(seed, shape, periodic, moving, sphere)
+    log(f"[parity] brute seed={seed} shape={shape} per={periodic} steps={steps}")
+    g, o = build(case)
+    g.step(steps)
+    o.step(steps)
+    e = compare(g, o, case)
+    log(f"[parity]   errors {e}")
+    assert e["mask_equal"]
+    tol = 2e-6 if steps == 1 else 1e-5
+    for k in ("f", "u", "tau", "rho"):
+        assert e[k][0] < tol, (k, e[k])
+    wo = o.wall_force()
+    np.testing.assert_allclose(g.wall_force(), wo, rtol=0, atol=1e-5 * np.abs(wo).max() + 1e-12)
+    if sphere is not None:
+        pg, po = g.particle(0), o.particle(0)
+        for k in ("force", "torque"):
+            np.testing.assert_allclose(pg[k], po[k], rtol=0, atol=1e-5 * np.abs(po[k]).max())
+    m_g, p_g = g.sums()
+    m_o, p_o = o.sums()
+    assert abs(m_g - m_o) < 1e-6 * m_o
+    np.testing.assert_allclose(p_g, p_o, rtol=1e-4, atol=1e-9)
+
+
+def test_single_link_bounce_back_by_hand():
+    """One fluid cell between two solid layers, at rest except one population:
+    after a step the reflected population sits where the oracle says."""
+    shape = (1, 3, 1)
+    mask = np.array([1, 0, 1], np.uint8).reshape(1, 3, 1)
+    c, w = zip(*[__import__("paper_2009_12279_amd").vlb.vlb_velocity(i) for i in range(19)])
+    f0 = np.zeros((19, 1, 3, 1))
+    for i in range(19):
+        f0[i] = w[i]
+    f0[3, 0, 1, 0] += 1e-3  # +y population
+    case = Case("single-link", shape, mask, (1, 0, 1), None,
+                dict(eta=1 / 6, beta=0.0, lambda_p=1.0, magic=-1.0), f0=f0)
+    log("[parity] single link")
+    g, o = build(case)
+    g.step(1)
+    o.step(1)
+    e = compare(g, o, case, what=("f",))
+    assert e["f"][0] < 1e-6
+
+
+def test_channel_workload_fp32_matches_fp64_oracle():
+    """The 4x64x4 Oldroyd-B Poiseuille workload, 20000 steps: FP32 GPU vs FP64
+    oracle within 1e-5 relative on velocity and stress."""
+    shape = (4, 64, 4)
+    mask = inputs.channel_mask(shape, wall_axes=(1,))
+    u0 = inputs.noise_field(1, 0, shape, 1e-8)
+    u0[:, mask != 0] = 0
+    case = Case("channel", shape, mask, (1, 0, 1), None,
+                dict(eta=1 / 3, beta=0.5, lambda_p=1000.0, magic=-1.0, body_force=(1e-6, 0, 0)),
+                u0=u0)
+    log("[parity] channel 4x64x4 20000 steps")
+    g, o = build(case)
+    g.step(20000)
+    o.step(20000)
+    e = compare(g, o, case, what=("u", "tau"))
+    log(f"[parity]   errors {e}")
+    assert e["u"][1] < 1e-5 and e["tau"][1] < 1e-5
+    assert e["u"][0] < 1e-5 and e["tau"][0] < 1e-5
+
+
+def test_fixed_sphere_duct_short():
+    """Duct with a fixed sphere (walls in y and z), 64x32x32, 300 steps."""
+    shape = (64, 32, 32)
+    mask = inputs.channel_mask(shape, wall_axes=(1, 2))
+    case = Case("duct", shape, mask, (1, 0, 0), None,
+                dict(eta=1 / 3, beta=0.5, lambda_p=100.0, magic=3 / 16, body_force=(1e-5, 0, 0)),
+                spheres=[dict(center=(31.5, 15.5, 15.5), radius=4.0)])
+    log("[parity] duct 64x32x32 sphere r=4, 300 steps")
+    g, o = build(case, threads=8)
+    g.step(300)
+    o.step(300)
+    e = compare(g, o, case, what=("u", "tau", "rho"))
+    log(f"[parity]   errors {e}")
+    for k in ("u", "tau"):
+        assert e[k][0] < 1e-5, (k, e[k])
+    pg, po = g.particle(0), o.particle(0)
+    np.testing.assert_allclose(pg["force"], po["force"], rtol=0,
+                               atol=1e-5 * np.abs(po["force"]).max())
+    wg, wo = g.wall_force(), o.wall_force()
+    np.testing.assert_allclose(wg, wo, rtol=0, atol=1e-5 * np.abs(wo).max())
+
+
+def test_moving_sphere_conversion_short():
+    """A movable sphere pushed through a closed box: conversions, momentum
+    exchange and symplectic Euler agree with the oracle."""
+    shape = (20, 20, 28)
+    mask = inputs.channel_mask(shape, wall_axes=(0, 1, 2))
+    case = Case("moving", shape, mask, (0, 0, 0), None,
+                dict(eta=1 / 6, beta=0.5, lambda_p=60.0, magic=3 / 16),
+                spheres=[dict(center=(9.5, 9.7, 14.2), radius=3.6, density_ratio=1.5,
+                              movable=True, f_ext=(1e-3, 0.0, -6e-3))])
+    log("[parity] moving sphere 20x20x28, 400 steps")
+    g, o = build(case, threads=8)
+    traj_g, traj_o = [], []
+    for _ in range(8):
+        g.step(50)
+        o.step(50)
+        traj_g.append(g.particle(0)["pos"])
+        traj_o.append(o.particle(0)["pos"])
+    e = compare(g, o, case, what=("u", "tau"))
+    log(f"[parity]   errors {e}")
+    assert e["mask_equal"]
+    pg, po = g.particle(0), o.particle(0)
+    log(f"[parity]   vel gpu {pg['vel']} oracle {po['vel']}")
+    np.testing.assert_allclose(np.array(traj_g), np.array(traj_o), rtol=0, atol=1e-8)
+    np.testing.assert_allclose(pg["vel"], po["vel"], rtol=1e-5, atol=1e-12)
+    for k in ("u", "tau"):
+        assert e[k][0] < 1e-5, (k, e[k])
