@@ -3,6 +3,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -17,6 +18,44 @@ namespace {
 thread_local std::string g_create_error = "no error";
 
 constexpr uint64_t kPlaneAlign = 256;  // elements; keeps every plane 512 B+ aligned
+
+// Extra elements between consecutive planes of a field.  Planes of a
+// power-of-two size would start on the same HBM channel; an odd multiple of
+// the alignment staggers them.  VLB_PLANE_PAD (elements, multiple of 256)
+// overrides it for tuning.
+uint64_t plane_pad()
+{
+    static uint64_t pad = [] {
+        const char *e = std::getenv("VLB_PLANE_PAD");
+        if (e) {
+            const long long v = std::atoll(e);
+            if (v >= 0)
+                return static_cast<uint64_t>(v) / kPlaneAlign * kPlaneAlign;
+        }
+        return static_cast<uint64_t>(5 * kPlaneAlign);
+    }();
+    return pad;
+}
+
+// Block order of the per-cell kernels: y-slabs per XCD when a z-plane
+// splits into 8 equal runs of whole 256-cell blocks, else one contiguous
+// block range per XCD.  VLB_XCD_REMAP (0, 1, 2) overrides it for tuning.
+int remap_blocks(const vlb::Geom &g, uint32_t &slab_blocks)
+{
+    static int forced = [] {
+        const char *e = std::getenv("VLB_XCD_REMAP");
+        return e ? std::atoi(e) : -1;
+    }();
+    const uint64_t nxy = static_cast<uint64_t>(g.nx) * g.ny;
+    const bool slabs_fit = nxy % (8ull * vlb::BLOCK) == 0;
+    slab_blocks = slabs_fit ? static_cast<uint32_t>(nxy / (8ull * vlb::BLOCK)) : 0;
+    int mode = slabs_fit ? 2 : 1;
+    if (forced >= 0)
+        mode = forced;
+    if (mode == 2 && !slabs_fit)
+        mode = 1;
+    return mode;
+}
 
 size_t storage_bytes(int storage) { return storage == vlb::ST_F32 ? 4 : 2; }
 
@@ -117,8 +156,10 @@ vlb_status check_dims(const vlb_dims *d)
 {
     if (!d || d->nx < 1 || d->ny < 1 || d->nz < 1)
         return VLB_EINVAL;
+    // kernels address every field plane with 32-bit byte offsets: a plane of
+    // FP32 values must stay below 4 GiB
     const uint64_t N = static_cast<uint64_t>(d->nx) * d->ny * d->nz;
-    if (N >= (1ull << 31))
+    if (N + kPlaneAlign + plane_pad() >= (1ull << 30))
         return VLB_EINVAL;
     return VLB_OK;
 }
@@ -275,7 +316,7 @@ size_t vlb_required_bytes(const vlb_dims *dims, vlb_storage storage, int32_t n_p
     if (check_dims(dims) != VLB_OK)
         return 0;
     const uint64_t N = static_cast<uint64_t>(dims->nx) * dims->ny * dims->nz;
-    const uint64_t P = round_up(N, kPlaneAlign);
+    const uint64_t P = round_up(N, kPlaneAlign) + plane_pad();
     const uint64_t pops = 2ull * vlb::Q * P * storage_bytes(storage);
     const uint64_t tau = 2ull * 6 * P * sizeof(float);
     const uint64_t u = 3ull * P * sizeof(float);
@@ -319,7 +360,7 @@ vlb_status vlb_create(const vlb_dims *dims, const uint8_t *mask, const double *w
     for (int a = 0; a < 3; ++a)
         lat->g.per[a] = dims->periodic[a] ? 1 : 0;
     lat->g.N = static_cast<uint32_t>(N);
-    lat->g.plane = round_up(N, kPlaneAlign);
+    lat->g.plane = round_up(N, kPlaneAlign) + plane_pad();
     lat->storage = storage;
     lat->scale = default_scale(storage);
     lat->inv_scale = 1.f / lat->scale;
@@ -584,7 +625,7 @@ vlb_status vlb_step(vlb_lattice *lat, int64_t n_steps)
     a.seed = lat->seed;
     a.scale = lat->scale;
     a.inv_scale = lat->inv_scale;
-    a.remap = 1;
+    a.remap = remap_blocks(lat->g, a.slab_blocks);
     const int nev = lat->timing ? 6 : 0;
     if (lat->timing && lat->events.size() < static_cast<size_t>(nev * n_steps)) {
         while (lat->events.size() < static_cast<size_t>(nev * n_steps)) {
@@ -598,6 +639,17 @@ vlb_status vlb_step(vlb_lattice *lat, int64_t n_steps)
         a.fout = lat->d_f[lat->cur ^ 1];
         a.tin = lat->d_tau[lat->cur];
         a.tout = lat->d_tau[lat->cur ^ 1];
+        const size_t pb = lat->g.plane * storage_bytes(lat->storage);
+        for (int i = 0; i < vlb::Q; ++i) {
+            a.fin_p[i] = static_cast<const char *>(a.fin) + i * pb;
+            a.fout_p[i] = static_cast<char *>(a.fout) + i * pb;
+        }
+        for (int c = 0; c < 6; ++c) {
+            a.tin_p[c] = a.tin + c * lat->g.plane;
+            a.tout_p[c] = a.tout + c * lat->g.plane;
+        }
+        for (int c = 0; c < 3; ++c)
+            a.u_p[c] = a.u + c * lat->g.plane;
         a.step = static_cast<uint32_t>(lat->step);
         hipEvent_t *ev = lat->timing ? &lat->events[nev * s] : nullptr;
         if (ev)

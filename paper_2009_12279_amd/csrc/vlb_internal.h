@@ -72,12 +72,21 @@ struct StepArgs {
     const float *tin;
     float *tout;
     float *u;                // 3 planes, u^n for the stress update
+    // The same fields as one base pointer per plane (kernel arguments the
+    // compiler keeps in scalar registers, so every access is scalar base +
+    // 32-bit vector offset).
+    const void *fin_p[Q];
+    void *fout_p[Q];
+    const float *tin_p[6];
+    float *tout_p[6];
+    float *u_p[3];
     double wp, wm;           // omega+, omega-
     double g3[3];            // body force density
     double eta_p_lam, inv_lam;
     float scale, inv_scale;  // storage scale s and 1/s
     int32_t polymer;
-    int32_t remap;           // XCD-aware block order
+    int32_t remap;           // XCD-aware block order (0 off, 1 ranges, 2 y-slabs)
+    uint32_t slab_blocks;    // remap 2: blocks per XCD per z-plane
     int32_t stochastic;      // stochastic rounding of stored values
     uint32_t step;           // step index (random stream of the rounding)
     uint32_t seed;

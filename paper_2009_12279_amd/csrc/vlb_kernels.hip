@@ -19,8 +19,9 @@ namespace vlb {
 namespace {
 
 // ---------------------------------------------------------------------------
-// counter-based random bits for stochastic rounding (a 32-bit integer hash of
-// (cell, step, seed), then a linear congruential sequence per cell)
+// Random bits for stochastic rounding: a 32-bit integer hash of (cell, step,
+// seed) seeds a per-thread xorshift32 sequence; every call yields two signed
+// 16-bit uniforms.
 
 __device__ __forceinline__ uint32_t hash32(uint32_t x)
 {
@@ -35,22 +36,47 @@ __device__ __forceinline__ uint32_t hash32(uint32_t x)
 struct Rng {
     uint32_t s;
     __device__ __forceinline__ Rng(uint32_t cell, uint32_t step, uint32_t seed)
-        : s(hash32(cell * 0x9e3779b1u ^ hash32(step * 0x85ebca77u + seed)))
+        : s(hash32(cell * 0x9e3779b1u ^ hash32(step * 0x85ebca77u + seed)) | 1u)
     {
     }
-    // 16 uniform bits
-    __device__ __forceinline__ uint32_t next16()
+    __device__ __forceinline__ uint32_t next32()
     {
-        s = s * 1664525u + 1013904223u;
-        return s >> 16;
+        s ^= s << 13;
+        s ^= s >> 17;
+        s ^= s << 5;
+        return s;
     }
 };
 
+// the two signed 16-bit halves of a 32-bit random word, each in [-2^15, 2^15)
+__device__ __forceinline__ int32_t rhi(uint32_t r) { return static_cast<int32_t>(r) >> 16; }
+__device__ __forceinline__ int32_t rlo(uint32_t r) { return static_cast<int32_t>(r << 16) >> 16; }
+
+// Stochastic rounding as dither-then-round-to-nearest: adding a uniform
+// offset in [-1/2, 1/2) of the target format's spacing at x and rounding to
+// nearest selects the upper neighbour with probability equal to the distance
+// from the lower one.
+__device__ __forceinline__ float sr_f32(double x, int32_t r16)
+{
+    uint32_t e = (static_cast<uint32_t>(__double2hiint(x)) >> 20) & 0x7ffu;
+    e = e < 897u ? 897u : e;  // below 2^-126 the FP32 spacing is 2^-149
+    const double scale = __hiloint2double(static_cast<int>((e - 39u) << 20), 0);  // spacing * 2^-16
+    return static_cast<float>(fma(static_cast<double>(r16), scale, x));
+}
+
+__device__ __forceinline__ float sr_f16_dither(float x, int32_t r16)
+{
+    uint32_t e = (__float_as_uint(x) >> 23) & 0xffu;
+    e = e < 113u ? 113u : e;  // below 2^-14 the FP16 spacing is 2^-24
+    const float scale = __uint_as_float((e - 26u) << 23);  // spacing * 2^-16
+    return fmaf(static_cast<float>(r16), scale, x);
+}
+
 // ---------------------------------------------------------------------------
 // storage codecs: deviation h = s * (f - w) in FP32, FP16 or BF16.
-// st() rounds to nearest; st_sr() rounds stochastically (up or down with
-// probability proportional to the distance), which removes the systematic
-// bias round-to-nearest leaves in a slowly relaxing steady state.
+// st() rounds to nearest; st_sr() rounds stochastically with the 16-bit
+// uniform r16, which removes the systematic bias round-to-nearest leaves in
+// a slowly relaxing steady state.
 
 template <int S>
 struct Store;
@@ -69,20 +95,12 @@ struct Store<ST_F32> {
         p[i] = static_cast<float>(v * s);
     }
     template <class V>
-    static __device__ __forceinline__ void st_sr(T *p, uint64_t i, V v, float s, Rng &rng)
+    static __device__ __forceinline__ void st_sr(T *p, uint64_t i, V v, float s, int32_t r16)
     {
-        if constexpr (sizeof(V) == 8) {
-            const double x = v * static_cast<double>(s);
-            float f0 = __double2float_rz(x);
-            const double rem = x - static_cast<double>(f0);  // exact, |rem| < one float step
-            const float f1 = __uint_as_float(__float_as_uint(f0) + 1u);  // next away from zero
-            const double step = fabs(static_cast<double>(f1) - static_cast<double>(f0));
-            if (static_cast<double>(rng.next16()) * (1.0 / 65536.0) * step < fabs(rem))
-                f0 = f1;
-            p[i] = f0;
-        } else {
+        if constexpr (sizeof(V) == 8)
+            p[i] = sr_f32(v * static_cast<double>(s), r16);
+        else
             p[i] = v * s;
-        }
     }
 };
 
@@ -100,17 +118,9 @@ struct Store<ST_F16> {
         p[i] = __float2half_rn(static_cast<float>(v) * s);
     }
     template <class V>
-    static __device__ __forceinline__ void st_sr(T *p, uint64_t i, V v, float s, Rng &rng)
+    static __device__ __forceinline__ void st_sr(T *p, uint64_t i, V v, float s, int32_t r16)
     {
-        const float x = static_cast<float>(v) * s;
-        __half h0 = __float2half_rz(x);
-        const float f0 = __half2float(h0);
-        const float rem = x - f0;  // exact
-        const __half h1 = __ushort_as_half(static_cast<unsigned short>(__half_as_ushort(h0) + 1u));
-        const float step = fabsf(__half2float(h1) - f0);
-        if (static_cast<float>(rng.next16()) * (1.f / 65536.f) * step < fabsf(rem))
-            h0 = h1;
-        p[i] = h0;
+        p[i] = __float2half_rn(sr_f16_dither(static_cast<float>(v) * s, r16));
     }
 };
 
@@ -131,33 +141,72 @@ struct Store<ST_BF16> {
         p[i] = static_cast<uint16_t>(b >> 16);
     }
     template <class V>
-    static __device__ __forceinline__ void st_sr(T *p, uint64_t i, V v, float s, Rng &rng)
+    static __device__ __forceinline__ void st_sr(T *p, uint64_t i, V v, float s, int32_t r16)
     {
         // uniform bits added below the kept 16 bits, then truncation
-        const uint32_t b = __float_as_uint(static_cast<float>(v) * s) + rng.next16();
+        const uint32_t b = __float_as_uint(static_cast<float>(v) * s) +
+                           static_cast<uint32_t>(r16 + 32768);
         p[i] = static_cast<uint16_t>(b >> 16);
     }
 };
 
-template <int S, class V>
-__device__ __forceinline__ void store(typename Store<S>::T *p, uint64_t i, V v, float s,
-                                      bool stochastic, Rng &rng)
+template <int S, bool SR, class V>
+__device__ __forceinline__ void store(typename Store<S>::T *p, uint64_t i, V v, float s, int32_t r16)
 {
-    if (stochastic)
-        Store<S>::st_sr(p, i, v, s, rng);
+    if constexpr (SR)
+        Store<S>::st_sr(p, i, v, s, r16);
     else
         Store<S>::st(p, i, v, s);
+}
+
+// Element `idx` of one plane addressed as (uniform plane base) + (32-bit byte
+// offset), which maps to the scalar-base / vector-offset addressing form and
+// keeps one VGPR per access instead of a 64-bit address.  The host
+// guarantees every field plane is below 4 GiB.
+template <class T>
+__device__ __forceinline__ const T *elem(const T *plane, uint32_t idx)
+{
+    return reinterpret_cast<const T *>(reinterpret_cast<const char *>(plane) +
+                                       idx * static_cast<uint32_t>(sizeof(T)));
+}
+template <class T>
+__device__ __forceinline__ T *elem(T *plane, uint32_t idx)
+{
+    return reinterpret_cast<T *>(reinterpret_cast<char *>(plane) +
+                                 idx * static_cast<uint32_t>(sizeof(T)));
+}
+
+// plane-addressed loads/stores of populations (deviation h = s (f - w))
+template <int S>
+__device__ __forceinline__ float ldp(const typename Store<S>::T *plane, uint32_t idx, float inv)
+{
+    return Store<S>::ld(elem(plane, idx), 0, inv);
+}
+template <int S, bool SR, class V>
+__device__ __forceinline__ void stp(typename Store<S>::T *plane, uint32_t idx, V v, float s,
+                                   int32_t r16)
+{
+    store<S, SR>(elem(plane, idx), 0, v, s, r16);
 }
 
 // ---------------------------------------------------------------------------
 // indexing
 
-// The hardware hands block b to XCD b % 8; give each XCD one contiguous slab
-// of blocks so that the neighbour planes a block reads sit in its own L2.
-__device__ __forceinline__ uint32_t block_id(int remap)
+// Block order.  The hardware hands block b to XCD b % 8, each XCD with its
+// own L2.  remap 1: each XCD takes one contiguous range of blocks.  remap 2
+// (used when a z-plane splits into 8 equal runs of whole blocks): XCD k
+// takes the k-th y-slab of every plane and sweeps it plane by plane, so the
+// three planes a stencil touches (z-1, z, z+1) of one slab stay in that
+// XCD's L2 while they are reused.
+__device__ __forceinline__ uint32_t block_id(int remap, uint32_t slab_blocks)
 {
     const uint32_t b = blockIdx.x, G = gridDim.x;
-    if (!remap)
+    if (remap == 2) {
+        const uint32_t k = b & 7u, q = b >> 3;
+        const uint32_t z = q / slab_blocks, j = q - z * slab_blocks;
+        return z * (8u * slab_blocks) + k * slab_blocks + j;
+    }
+    if (remap != 1)
         return b;
     const uint32_t per = G >> 3;
     if (b >= per * 8u)
@@ -295,214 +344,331 @@ __device__ double block_max(double v, double *sh)
 
 // ---------------------------------------------------------------------------
 // Stream-collide (Section 3.1) with the polymer force of Section 3.3.
-// Arithmetic in R (FP64 for FP32 storage, FP32 for half storage).
+// Arithmetic in R (FP64 for FP32 storage, FP32 for half storage); the pulled
+// populations stay in FP32 registers (exact) to keep occupancy up.
 
-template <int S>
+// Index deltas to the six face neighbours with periodic wrap, so that the
+// neighbour along (cx, cy, cz) is n + dx[cx+1] + dy[cy+1] + dz[cz+1].
+struct Delta {
+    int32_t dx[3], dy[3], dz[3];
+    __device__ __forceinline__ Delta(const Geom &g, int x, int y, int z)
+    {
+        const int32_t nx = g.nx, nxy = g.nx * g.ny, nxyz = nxy * g.nz;
+        dx[0] = x == 0 ? nx - 1 : -1;
+        dx[1] = 0;
+        dx[2] = x == g.nx - 1 ? 1 - nx : 1;
+        dy[0] = y == 0 ? nxy - nx : -nx;
+        dy[1] = 0;
+        dy[2] = y == g.ny - 1 ? nx - nxy : nx;
+        dz[0] = z == 0 ? nxyz - nxy : -nxy;
+        dz[1] = 0;
+        dz[2] = z == g.nz - 1 ? nxy - nxyz : nxy;
+    }
+    __device__ __forceinline__ uint32_t at(uint32_t n, int cx, int cy, int cz) const
+    {
+        return static_cast<uint32_t>(static_cast<int32_t>(n) + dx[cx + 1] + dy[cy + 1] + dz[cz + 1]);
+    }
+    // same for offsets only known at run time (selects, no indexed arrays)
+    __device__ __forceinline__ uint32_t at_rt(uint32_t n, int cx, int cy, int cz) const
+    {
+        const int32_t ox = cx < 0 ? dx[0] : (cx > 0 ? dx[2] : 0);
+        const int32_t oy = cy < 0 ? dy[0] : (cy > 0 ? dy[2] : 0);
+        const int32_t oz = cz < 0 ? dz[0] : (cz > 0 ? dz[2] : 0);
+        return static_cast<uint32_t>(static_cast<int32_t>(n) + ox + oy + oz);
+    }
+};
+
+// Runtime-indexed copies of the velocity set for the rare boundary path.
+__constant__ int8_t kCX[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+__constant__ int8_t kCY[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+__constant__ int8_t kCZ[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+
+// Bounce-back for every link of cell n into a solid cell (Section 3.1
+// velocity boundary condition): the post-collision population just stored
+// for direction j is reflected, with the moving-wall term, into the slot of
+// the solid cell that the next pull of this cell reads.  `links` has bit j
+// set for each solid neighbour along c_j.
+template <int S, bool SR, class R>
+__device__ void reflect_links(const StepArgs &a, typename Store<S>::T *fout, uint32_t n,
+                              const Delta &d, uint32_t links, R rho, Rng &rng)
+{
+    const uint64_t P = a.g.plane;
+    while (links) {
+        const int j = __builtin_ctz(links);
+        links &= links - 1;
+        const int cx = kCX[j], cy = kCY[j], cz = kCZ[j];
+        const uint32_t m = d.at_rt(n, cx, cy, cz);
+        R val = static_cast<R>(ldp<S>(fout + j * P, n, a.inv_scale));
+        if (a.b.moving) {
+            int x, y, z;
+            coords(a.g, m, x, y, z);
+            double ub[3];
+            boundary_velocity_d(a.g, a.b, a.mask[m], x, y, z, ub);
+            const double w = (cx * cx + cy * cy + cz * cz == 1) ? 1.0 / 18.0 : 1.0 / 36.0;
+            val -= R(6) * static_cast<R>(w) * rho * static_cast<R>(cx * ub[0] + cy * ub[1] + cz * ub[2]);
+        }
+        const int o = (j & 1) ? j + 1 : j - 1;  // opposite direction (pairs are adjacent)
+        stp<S, SR>(fout + o * P, m, val, a.scale, rhi(rng.next32()));
+    }
+}
+
+template <int S, bool SR>
 __global__ __launch_bounds__(BLOCK) void lb_step_kernel(StepArgs a)
 {
     using St = Store<S>;
     using T = typename St::T;
     using R = typename St::R;
-    const uint32_t n = block_id(a.remap) * BLOCK + threadIdx.x;
+    const uint32_t n = block_id(a.remap, a.slab_blocks) * BLOCK + threadIdx.x;
     if (n >= a.g.N)
         return;
     const uint8_t *__restrict__ mask = a.mask;
-    if (mask[n] != 0)
-        return;
     int x, y, z;
     coords(a.g, n, x, y, z);
-    const Nbr nb(a.g, x, y, z);
-    const uint64_t P = a.g.plane;
-    const T *__restrict__ fin = static_cast<const T *>(a.fin);
-    T *__restrict__ fout = static_cast<T *>(a.fout);
+    const Delta d(a.g, x, y, z);
 
+    // Every load is issued before any result is used (all addresses are in
+    // bounds, also for solid cells), so a wave has all its memory requests
+    // in flight at once.
     // pull: f_i(x) sits in plane i at x - c_i
-    R f[Q];
+    float f[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i)
-        f[i] = static_cast<R>(St::ld(fin, i * P + nb.at(-CX[i], -CY[i], -CZ[i]), a.inv_scale));
-
-    // force density: body force + polymer force, the face average of the
-    // stress with a solid face neighbour taking this cell's stress
-    R F[3] = {static_cast<R>(a.g3[0]), static_cast<R>(a.g3[1]), static_cast<R>(a.g3[2])};
+        f[i] = ldp<S>(static_cast<const T *>(a.fin_p[i]), d.at(n, -CX[i], -CY[i], -CZ[i]),
+                      a.inv_scale);
+    // solid neighbours along every direction
+    uint32_t links = 0;
+#pragma unroll
+    for (int j = 1; j < Q; ++j)
+        links |= (mask[d.at(n, CX[j], CY[j], CZ[j])] != 0 ? 1u : 0u) << j;
+    // stress of the face neighbours and of the cell itself (for the
+    // constant extrapolation into solid neighbours)
+    float tn[3][2][3], town[6];
     if (a.polymer) {
-        const float *__restrict__ tin = a.tin;
+#pragma unroll
+        for (int c = 0; c < 6; ++c)
+            town[c] = *elem(a.tin_p[c], n);
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                const int sg = side == 0 ? 1 : -1;
+                const uint32_t m = d.at(n, sg * (k == 0), sg * (k == 1), sg * (k == 2));
+#pragma unroll
+                for (int j = 0; j < 3; ++j)
+                    tn[k][side][j] = *elem(a.tin_p[TROW[k][j]], m);
+            }
+    }
+    if (mask[n] != 0)
+        return;
+
+    // polymer force: sum over faces of the face-averaged stress times the
+    // outward normal, a solid face neighbour taking this cell's stress; in
+    // FP32 (a difference of stresses, small next to the populations)
+    float Fp[3] = {0.f, 0.f, 0.f};
+    if (a.polymer) {
+        // face bits of `links`: +x 1, -x 2, +y 3, -y 4, +z 5, -z 6
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const uint32_t ip = nb.at(k == 0, k == 1, k == 2);
-            const uint32_t im = nb.at(-(k == 0), -(k == 1), -(k == 2));
-            const uint32_t sp = mask[ip] != 0 ? n : ip;
-            const uint32_t sm = mask[im] != 0 ? n : im;
+            const bool sp = (links >> (2 * k + 1)) & 1u, sm = (links >> (2 * k + 2)) & 1u;
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
-                const uint64_t c = static_cast<uint64_t>(TROW[k][j]) * P;
-                F[j] += R(0.5) * (static_cast<R>(tin[c + sp]) - static_cast<R>(tin[c + sm]));
+                const float own = town[TROW[k][j]];
+                Fp[j] += 0.5f * ((sp ? own : tn[k][0][j]) - (sm ? own : tn[k][1][j]));
             }
         }
     }
+    const R Fx = static_cast<R>(a.g3[0]) + static_cast<R>(Fp[0]);
+    const R Fy = static_cast<R>(a.g3[1]) + static_cast<R>(Fp[1]);
+    const R Fz = static_cast<R>(a.g3[2]) + static_cast<R>(Fp[2]);
 
-    // moments in deviation form: rho = 1 + sum h, rho u = sum h c + F/2
-    R drho = 0, jx = 0, jy = 0, jz = 0;
+    // moments in deviation form from opposite-pair sums and differences:
+    // rho = 1 + h_0 + sum (h_i + h_o), rho u = sum c_i (h_i - h_o) + F/2
+    R drho = static_cast<R>(f[0]), jx = 0, jy = 0, jz = 0;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        drho += f[i];
+    for (int k = 0; k < Q / 2; ++k) {
+        const int i = 2 * k + 1;
+        const R a_ = static_cast<R>(f[i]), b_ = static_cast<R>(f[i + 1]);
+        drho += a_ + b_;
+        const R df = a_ - b_;
         if (CX[i])
-            jx += CX[i] * f[i];
+            jx += CX[i] * df;
         if (CY[i])
-            jy += CY[i] * f[i];
+            jy += CY[i] * df;
         if (CZ[i])
-            jz += CZ[i] * f[i];
+            jz += CZ[i] * df;
     }
     const R rho = R(1) + drho;
     const R inv_rho = R(1) / rho;
-    const R ux = (jx + R(0.5) * F[0]) * inv_rho;
-    const R uy = (jy + R(0.5) * F[1]) * inv_rho;
-    const R uz = (jz + R(0.5) * F[2]) * inv_rho;
+    const R ux = (jx + R(0.5) * Fx) * inv_rho;
+    const R uy = (jy + R(0.5) * Fy) * inv_rho;
+    const R uz = (jz + R(0.5) * Fz) * inv_rho;
     const R uu = ux * ux + uy * uy + uz * uz;
-    const R uF = ux * F[0] + uy * F[1] + uz * F[2];
+    const R uF = ux * Fx + uy * Fy + uz * Fz;
     const R wp = static_cast<R>(a.wp), wm = static_cast<R>(a.wm);
     const R cp = R(1) - R(0.5) * wp, cm = R(1) - R(0.5) * wm;
 
-    // TRT collision on opposite pairs, Guo source split into its symmetric
-    // part (second order, scaled by 1 - w+/2) and antisymmetric part (first
-    // order, scaled by 1 - w-/2)
-    R fo[Q];
-    {
-        const R eq0 = static_cast<R>(WD[0]) * (drho - R(1.5) * rho * uu);
-        const R s0 = static_cast<R>(WD[0]) * (R(-3) * uF);
-        fo[0] = f[0] - wp * (f[0] - eq0) + cp * s0;
-    }
-#pragma unroll
-    for (int i = 1; i < Q; i += 2) {
-        const int o = i + 1;
-        const R cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
-        const R cF = CX[i] * F[0] + CY[i] * F[1] + CZ[i] * F[2];
-        const R w = static_cast<R>(WD[i]);
-        const R eqp = w * (drho + rho * (R(4.5) * cu * cu - R(1.5) * uu));
-        const R eqm = w * rho * R(3) * cu;
-        const R sp = w * (R(9) * cu * cF - R(3) * uF);
-        const R sm = w * R(3) * cF;
-        const R hp = R(0.5) * (f[i] + f[o]);
-        const R hm = R(0.5) * (f[i] - f[o]);
-        const R np = hp - wp * (hp - eqp) + cp * sp;
-        const R nm = hm - wm * (hm - eqm) + cm * sm;
-        fo[i] = np + nm;
-        fo[o] = np - nm;
-    }
+    // TRT with Guo forcing, written per opposite pair (i, o) with s = h_i + h_o
+    // and d = h_i - h_o as
+    //   f*+ = (1-w+) s/2 + w+ f^eq+ + (1-w+/2) S+,  f*- = (1-w-) d/2 + w- f^eq- + (1-w-/2) S-
+    // with f^eq+ = w (drho + rho (9/2 (c.u)^2 - 3/2 u.u)),  f^eq- = 3 w rho c.u,
+    //      S+ = w (9 (c.u)(c.F) - 3 u.F),                    S- = 3 w c.F,
+    // i.e. f*+ = a1 s + w (P1 + c.u (Q1 c.u + C9 c.F)),  f*- = b1 d + w (M3 c.u + C3 c.F).
+    const R a1 = R(0.5) * (R(1) - wp), b1 = R(0.5) * (R(1) - wm);
+    const R P1 = wp * (drho - R(1.5) * rho * uu) - R(3) * cp * uF;
+    const R Q1 = R(4.5) * wp * rho, C9 = R(9) * cp;
+    const R M3 = R(3) * wm * rho, C3 = R(3) * cm;
     Rng rng(n, a.step, a.seed);
-    const bool sr = a.stochastic != 0;
+    uint32_t r = rng.next32();
+    stp<S, SR>(static_cast<T *>(a.fout_p[0]), n,
+               R(2) * a1 * static_cast<R>(f[0]) + static_cast<R>(WD[0]) * P1, a.scale, rhi(r));
 #pragma unroll
-    for (int i = 0; i < Q; ++i)
-        store<S>(fout, i * P + n, fo[i], a.scale, sr, rng);
-
-    // links into solid cells: reflect into the solid slot the next pull reads
-#pragma unroll
-    for (int j = 1; j < Q; ++j) {
-        const uint32_t m = nb.at(CX[j], CY[j], CZ[j]);
-        const uint8_t mb = mask[m];
-        if (mb != 0) {
-            R val = fo[j];
-            if (a.b.moving) {
-                double ub[3];
-                boundary_velocity_d(a.g, a.b, mb, nb.xc[CX[j] + 1], nb.yc[CY[j] + 1],
-                                    nb.zc[CZ[j] + 1], ub);
-                val -= R(6) * static_cast<R>(WD[j]) * rho *
-                       static_cast<R>(CX[j] * ub[0] + CY[j] * ub[1] + CZ[j] * ub[2]);
-            }
-            store<S>(fout, OPP[j] * P + m, val, a.scale, sr, rng);
+    for (int k = 0; k < Q / 2; ++k) {
+        const int i = 2 * k + 1, o = i + 1;
+        const R w = static_cast<R>(WD[i]);
+        const R a_ = static_cast<R>(f[i]), b_ = static_cast<R>(f[o]);
+        const R cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
+        const R cF = CX[i] * Fx + CY[i] * Fy + CZ[i] * Fz;
+        const R np = a1 * (a_ + b_) + w * (P1 + cu * (Q1 * cu + C9 * cF));
+        const R nm = b1 * (a_ - b_) + w * (M3 * cu + C3 * cF);
+        T *pi = static_cast<T *>(a.fout_p[i]);
+        T *po = static_cast<T *>(a.fout_p[o]);
+        if (k & 1) {
+            stp<S, SR>(pi, n, np + nm, a.scale, rlo(r));
+            r = rng.next32();
+            stp<S, SR>(po, n, np - nm, a.scale, rhi(r));
+        } else {
+            r = rng.next32();
+            stp<S, SR>(pi, n, np + nm, a.scale, rhi(r));
+            stp<S, SR>(po, n, np - nm, a.scale, rlo(r));
         }
     }
 
+    if (links)
+        reflect_links<S, SR>(a, static_cast<T *>(a.fout), n, d, links, rho, rng);
+
     if (a.polymer) {
-        a.u[n] = static_cast<float>(ux);
-        a.u[P + n] = static_cast<float>(uy);
-        a.u[2 * P + n] = static_cast<float>(uz);
+        *elem(a.u_p[0], n) = static_cast<float>(ux);
+        *elem(a.u_p[1], n) = static_cast<float>(uy);
+        *elem(a.u_p[2], n) = static_cast<float>(uz);
     }
 }
 
 // ---------------------------------------------------------------------------
-// Finite-volume Oldroyd-B stress update (Section 2.2 source, Section 3.3),
-// arithmetic in R.
+// Finite-volume Oldroyd-B stress update (Section 2.2 source, Section 3.3).
+// The increment (fluxes + source, products of small quantities) is formed in
+// FP32; it is added to the stored stress in FP64 and rounded once.
 
-template <class R>
-__device__ __forceinline__ R face_overlap(const R u[3], int k, int s)
+__device__ __forceinline__ float face_overlap(const float u[3], int k, int s)
 {
-    const R ue = s * u[k];
-    if (ue <= R(0))
-        return R(0);
+    const float ue = s * u[k];
+    if (ue <= 0.f)
+        return 0.f;
     const int a1 = k == 0 ? 1 : 0, a2 = k == 2 ? 1 : 2;
-    return ue * (R(1) - fabs(u[a1])) * (R(1) - fabs(u[a2]));
+    return ue * (1.f - fabsf(u[a1])) * (1.f - fabsf(u[a2]));
 }
 
-template <class R>
+template <bool SR>
 __global__ __launch_bounds__(BLOCK) void fv_step_kernel(StepArgs a)
 {
-    const uint32_t n = block_id(a.remap) * BLOCK + threadIdx.x;
+    const uint32_t n = block_id(a.remap, a.slab_blocks) * BLOCK + threadIdx.x;
     if (n >= a.g.N)
         return;
     const uint8_t *__restrict__ mask = a.mask;
-    if (mask[n] != 0)
-        return;
     int x, y, z;
     coords(a.g, n, x, y, z);
-    const Nbr nb(a.g, x, y, z);
-    const uint64_t P = a.g.plane;
-    const float *__restrict__ u = a.u;
-    const float *__restrict__ tin = a.tin;
-    const R u0[3] = {u[n], u[P + n], u[2 * P + n]};
-    R t0[6];
+    const Delta d(a.g, x, y, z);
+    // all loads first (in bounds for every cell), selection afterwards
+    const float u0[3] = {*elem(a.u_p[0], n), *elem(a.u_p[1], n), *elem(a.u_p[2], n)};
+    float t0[6];
 #pragma unroll
     for (int c = 0; c < 6; ++c)
-        t0[c] = tin[c * P + n];
-    R G[3][3];
-    R acc[6] = {0, 0, 0, 0, 0, 0};
+        t0[c] = *elem(a.tin_p[c], n);
+    float un[3][2][3], tn[3][2][6];
+    uint32_t solid = 0;  // bit 2k+side: face neighbour along +/- e_k is solid
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        R us[2][3];
+    for (int k = 0; k < 3; ++k)
 #pragma unroll
         for (int side = 0; side < 2; ++side) {
             const int s = side == 0 ? 1 : -1;
-            const int cx = s * (k == 0), cy = s * (k == 1), cz = s * (k == 2);
-            const uint32_t m = nb.at(cx, cy, cz);
-            const uint8_t mb = mask[m];
-            if (mb == 0) {
-                us[side][0] = u[m];
-                us[side][1] = u[P + m];
-                us[side][2] = u[2 * P + m];
-                const R out = face_overlap(u0, k, s);
-                const R in = face_overlap(us[side], k, -s);
+            const uint32_t m = d.at(n, s * (k == 0), s * (k == 1), s * (k == 2));
+            solid |= (mask[m] != 0 ? 1u : 0u) << (2 * k + side);
 #pragma unroll
-                for (int c = 0; c < 6; ++c)
-                    acc[c] += in * static_cast<R>(tin[c * P + m]) - out * t0[c];
-            } else {
-                double ub[3];
-                boundary_velocity_d(a.g, a.b, mb, nb.xc[cx + 1], nb.yc[cy + 1], nb.zc[cz + 1], ub);
-                us[side][0] = static_cast<R>(ub[0]);
-                us[side][1] = static_cast<R>(ub[1]);
-                us[side][2] = static_cast<R>(ub[2]);
-            }
+            for (int j = 0; j < 3; ++j)
+                un[k][side][j] = *elem(a.u_p[j], m);
+#pragma unroll
+            for (int c = 0; c < 6; ++c)
+                tn[k][side][c] = *elem(a.tin_p[c], m);
+        }
+    if (mask[n] != 0)
+        return;
+
+    float G[3][3];
+    float in_sum[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float out_tot = 0.f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const int s = side == 0 ? 1 : -1;
+            const bool sol = (solid >> (2 * k + side)) & 1u;
+            // no flux through a solid face; its velocity (zero for walls at
+            // rest) enters the gradient below
+            const float out = sol ? 0.f : face_overlap(u0, k, s);
+            const float in = sol ? 0.f : face_overlap(un[k][side], k, -s);
+            out_tot += out;
+#pragma unroll
+            for (int c = 0; c < 6; ++c)
+                in_sum[c] += in * tn[k][side][c];
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                un[k][side][j] = sol ? 0.f : un[k][side][j];
         }
 #pragma unroll
         for (int j = 0; j < 3; ++j)
-            G[k][j] = R(0.5) * (us[0][j] - us[1][j]);
+            G[k][j] = 0.5f * (un[k][0][j] - un[k][1][j]);
+    }
+    if (solid && a.b.moving) {
+        // velocity gradient with the boundary velocity at solid face neighbours
+        while (solid) {
+            const int b = __builtin_ctz(solid);
+            solid &= solid - 1;
+            const int k = b >> 1, s = (b & 1) ? -1 : 1;
+            const uint32_t m = d.at_rt(n, s * (k == 0), s * (k == 1), s * (k == 2));
+            int mx, my, mz;
+            coords(a.g, m, mx, my, mz);
+            double ub[3];
+            boundary_velocity_d(a.g, a.b, mask[m], mx, my, mz, ub);
+            const float hs = 0.5f * s;
+            for (int j = 0; j < 3; ++j) {
+                const float gj = hs * static_cast<float>(ub[j]);
+                if (k == 0)
+                    G[0][j] += gj;
+                else if (k == 1)
+                    G[1][j] += gj;
+                else
+                    G[2][j] += gj;
+            }
+        }
     }
     // source: sum_k tau_ik G_kj + sum_k tau_kj G_ki + eta_p/lam (G_ij + G_ji) - tau_ij/lam
-    const R T3[3][3] = {{t0[0], t0[3], t0[4]}, {t0[3], t0[1], t0[5]}, {t0[4], t0[5], t0[2]}};
+    const float T3[3][3] = {{t0[0], t0[3], t0[4]}, {t0[3], t0[1], t0[5]}, {t0[4], t0[5], t0[2]}};
     const int PI[6] = {0, 1, 2, 0, 0, 1};
     const int PJ[6] = {0, 1, 2, 1, 2, 2};
-    const R epl = static_cast<R>(a.eta_p_lam), il = static_cast<R>(a.inv_lam);
-    float *__restrict__ tout = a.tout;
+    const float epl = static_cast<float>(a.eta_p_lam), il = static_cast<float>(a.inv_lam);
     Rng rng(n, a.step, a.seed ^ 0x5bd1e995u);
-    const bool sr = a.stochastic != 0;
+    uint32_t r = 0;
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
         const int i = PI[c], j = PJ[c];
-        R s = 0;
+        float sdot = 0.f;
 #pragma unroll
         for (int k = 0; k < 3; ++k)
-            s += T3[i][k] * G[k][j] + T3[k][j] * G[k][i];
-        s += epl * (G[i][j] + G[j][i]) - t0[c] * il;
-        store<ST_F32>(tout, c * P + n, t0[c] + (acc[c] + s), 1.f, sr, rng);
+            sdot += T3[i][k] * G[k][j] + T3[k][j] * G[k][i];
+        const float inc = in_sum[c] - out_tot * t0[c] + sdot + epl * (G[i][j] + G[j][i]) - t0[c] * il;
+        const double v = static_cast<double>(t0[c]) + static_cast<double>(inc);
+        if (!(c & 1))
+            r = rng.next32();
+        stp<ST_F32, SR>(a.tout_p[c], n, v, 1.f, (c & 1) ? rlo(r) : rhi(r));
     }
 }
 
@@ -1257,18 +1423,22 @@ hipError_t dispatch(int storage, Fn fn)
 hipError_t launch_lb_step(int storage, const StepArgs &a, hipStream_t s)
 {
     return dispatch(storage, [&](auto st) {
-        hipLaunchKernelGGL(lb_step_kernel<decltype(st)::value>, dim3(blocks_for(a.g.N)), dim3(BLOCK),
-                           0, s, a);
+        constexpr int S = decltype(st)::value;
+        if (a.stochastic)
+            hipLaunchKernelGGL((lb_step_kernel<S, true>), dim3(blocks_for(a.g.N)), dim3(BLOCK), 0, s, a);
+        else
+            hipLaunchKernelGGL((lb_step_kernel<S, false>), dim3(blocks_for(a.g.N)), dim3(BLOCK), 0, s, a);
         return hipGetLastError();
     });
 }
 
 hipError_t launch_fv_step(int storage, const StepArgs &a, hipStream_t s)
 {
-    if (storage == ST_F32)
-        hipLaunchKernelGGL(fv_step_kernel<double>, dim3(blocks_for(a.g.N)), dim3(BLOCK), 0, s, a);
+    (void)storage;
+    if (a.stochastic)
+        hipLaunchKernelGGL(fv_step_kernel<true>, dim3(blocks_for(a.g.N)), dim3(BLOCK), 0, s, a);
     else
-        hipLaunchKernelGGL(fv_step_kernel<float>, dim3(blocks_for(a.g.N)), dim3(BLOCK), 0, s, a);
+        hipLaunchKernelGGL(fv_step_kernel<false>, dim3(blocks_for(a.g.N)), dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
 
