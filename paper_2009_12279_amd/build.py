@@ -24,14 +24,15 @@ def flags():
     ]
 
 
-def build(verbose: bool = False) -> str:
-    tmp = SO + ".tmp"
-    cmd = [HIPCC] + flags() + [os.path.join(HERE, s) for s in SOURCES] + ["-o", tmp]
+def build(verbose: bool = False, out: str = SO, defines=()) -> str:
+    tmp = out + ".tmp"
+    cmd = [HIPCC] + flags() + [f"-D{d}" for d in defines] + \
+        [os.path.join(HERE, s) for s in SOURCES] + ["-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd, cwd=HERE)
-    os.replace(tmp, SO)
-    return SO
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

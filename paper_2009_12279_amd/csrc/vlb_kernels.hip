@@ -39,11 +39,10 @@ struct Rng {
         : s(hash32(cell * 0x9e3779b1u ^ hash32(step * 0x85ebca77u + seed)) | 1u)
     {
     }
+    // next state of the hardware pseudo-random sequence (one instruction)
     __device__ __forceinline__ uint32_t next32()
     {
-        s ^= s << 13;
-        s ^= s >> 17;
-        s ^= s << 5;
+        s = __builtin_amdgcn_prng_b32(s);
         return s;
     }
 };
@@ -58,10 +57,13 @@ __device__ __forceinline__ int32_t rlo(uint32_t r) { return static_cast<int32_t>
 // from the lower one.
 __device__ __forceinline__ float sr_f32(double x, int32_t r16)
 {
-    uint32_t e = (static_cast<uint32_t>(__double2hiint(x)) >> 20) & 0x7ffu;
-    e = e < 897u ? 897u : e;  // below 2^-126 the FP32 spacing is 2^-149
-    const double scale = __hiloint2double(static_cast<int>((e - 39u) << 20), 0);  // spacing * 2^-16
-    return static_cast<float>(fma(static_cast<double>(r16), scale, x));
+    // One FP32 spacing is 2^29 units in the last place of an FP64 value of
+    // the same binade, so adding r16 * 2^13 to the bit pattern dithers x by
+    // [-1/2, 1/2) of an FP32 spacing; the conversion then rounds to nearest.
+    // |x| below 1e-300 (only ever exact zeros here) is passed through.
+    const int64_t dither = static_cast<int64_t>(r16) * (int64_t(1) << 13);
+    const double xd = __longlong_as_double(__double_as_longlong(x) + dither);
+    return fabs(x) < 1e-300 ? static_cast<float>(x) : static_cast<float>(xd);
 }
 
 __device__ __forceinline__ float sr_f16_dither(float x, int32_t r16)
@@ -70,6 +72,14 @@ __device__ __forceinline__ float sr_f16_dither(float x, int32_t r16)
     e = e < 113u ? 113u : e;  // below 2^-14 the FP16 spacing is 2^-24
     const float scale = __uint_as_float((e - 26u) << 23);  // spacing * 2^-16
     return fmaf(static_cast<float>(r16), scale, x);
+}
+
+// Streaming store: every population is written once per step and read once
+// in the next step, long after it would have left the caches.
+template <class T>
+__device__ __forceinline__ void st_stream(T *p, T v)
+{
+    __builtin_nontemporal_store(v, p);
 }
 
 // ---------------------------------------------------------------------------
@@ -92,15 +102,15 @@ struct Store<ST_F32> {
     template <class V>
     static __device__ __forceinline__ void st(T *p, uint64_t i, V v, float s)
     {
-        p[i] = static_cast<float>(v * s);
+        st_stream(p + i, static_cast<float>(v * s));
     }
     template <class V>
     static __device__ __forceinline__ void st_sr(T *p, uint64_t i, V v, float s, int32_t r16)
     {
         if constexpr (sizeof(V) == 8)
-            p[i] = sr_f32(v * static_cast<double>(s), r16);
+            st_stream(p + i, sr_f32(v * static_cast<double>(s), r16));
         else
-            p[i] = v * s;
+            st_stream(p + i, static_cast<float>(v * s));
     }
 };
 
@@ -412,8 +422,21 @@ __device__ void reflect_links(const StepArgs &a, typename Store<S>::T *fout, uin
     }
 }
 
+// Optional occupancy targets for the step kernels (waves per SIMD); the
+// default leaves register allocation to the compiler.
+#ifdef VLB_LB_WAVES
+#define LB_OCCUPANCY __attribute__((amdgpu_waves_per_eu(VLB_LB_WAVES)))
+#else
+#define LB_OCCUPANCY
+#endif
+#ifdef VLB_FV_WAVES
+#define FV_OCCUPANCY __attribute__((amdgpu_waves_per_eu(VLB_FV_WAVES)))
+#else
+#define FV_OCCUPANCY
+#endif
+
 template <int S, bool SR>
-__global__ __launch_bounds__(BLOCK) void lb_step_kernel(StepArgs a)
+__global__ __launch_bounds__(BLOCK) LB_OCCUPANCY void lb_step_kernel(StepArgs a)
 {
     using St = Store<S>;
     using T = typename St::T;
@@ -458,6 +481,7 @@ __global__ __launch_bounds__(BLOCK) void lb_step_kernel(StepArgs a)
                     tn[k][side][j] = *elem(a.tin_p[TROW[k][j]], m);
             }
     }
+    auto pop = [&](int i) -> float { return f[i]; };
     if (mask[n] != 0)
         return;
 
@@ -483,11 +507,11 @@ __global__ __launch_bounds__(BLOCK) void lb_step_kernel(StepArgs a)
 
     // moments in deviation form from opposite-pair sums and differences:
     // rho = 1 + h_0 + sum (h_i + h_o), rho u = sum c_i (h_i - h_o) + F/2
-    R drho = static_cast<R>(f[0]), jx = 0, jy = 0, jz = 0;
+    R drho = static_cast<R>(pop(0)), jx = 0, jy = 0, jz = 0;
 #pragma unroll
     for (int k = 0; k < Q / 2; ++k) {
         const int i = 2 * k + 1;
-        const R a_ = static_cast<R>(f[i]), b_ = static_cast<R>(f[i + 1]);
+        const R a_ = static_cast<R>(pop(i)), b_ = static_cast<R>(pop(i + 1));
         drho += a_ + b_;
         const R df = a_ - b_;
         if (CX[i])
@@ -520,12 +544,12 @@ __global__ __launch_bounds__(BLOCK) void lb_step_kernel(StepArgs a)
     Rng rng(n, a.step, a.seed);
     uint32_t r = rng.next32();
     stp<S, SR>(static_cast<T *>(a.fout_p[0]), n,
-               R(2) * a1 * static_cast<R>(f[0]) + static_cast<R>(WD[0]) * P1, a.scale, rhi(r));
+               R(2) * a1 * static_cast<R>(pop(0)) + static_cast<R>(WD[0]) * P1, a.scale, rhi(r));
 #pragma unroll
     for (int k = 0; k < Q / 2; ++k) {
         const int i = 2 * k + 1, o = i + 1;
         const R w = static_cast<R>(WD[i]);
-        const R a_ = static_cast<R>(f[i]), b_ = static_cast<R>(f[o]);
+        const R a_ = static_cast<R>(pop(i)), b_ = static_cast<R>(pop(o));
         const R cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
         const R cF = CX[i] * Fx + CY[i] * Fy + CZ[i] * Fz;
         const R np = a1 * (a_ + b_) + w * (P1 + cu * (Q1 * cu + C9 * cF));
@@ -568,7 +592,7 @@ __device__ __forceinline__ float face_overlap(const float u[3], int k, int s)
 }
 
 template <bool SR>
-__global__ __launch_bounds__(BLOCK) void fv_step_kernel(StepArgs a)
+__global__ __launch_bounds__(BLOCK) FV_OCCUPANCY void fv_step_kernel(StepArgs a)
 {
     const uint32_t n = block_id(a.remap, a.slab_blocks) * BLOCK + threadIdx.x;
     if (n >= a.g.N)

@@ -16,7 +16,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libvlb.so")
+# VLB_LIBRARY selects another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("VLB_LIBRARY") or os.path.join(_HERE, "libvlb.so")
 Q = 19
 
 VLB_OK, VLB_EINVAL, VLB_ENOMEM, VLB_EDEVICE, VLB_EUNSTABLE, VLB_ESTATE, VLB_EBUSY, \
