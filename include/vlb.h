@@ -193,6 +193,71 @@ vlb_status vlb_set_timing(vlb_lattice *lat, int32_t on);
 vlb_status vlb_set_rounding(vlb_lattice *lat, vlb_rounding mode, uint32_t seed);
 double vlb_kernel_time_ms(const vlb_lattice *lat, int32_t which);
 
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of independent solves (FP32 storage).
+ *
+ * A server owns a FIFO queue of requests and a set of slots.  vlb_server_pump
+ * retires finished solves (their velocity and stress are copied to the host
+ * and their device memory freed), admits queued requests in order while a
+ * slot is free and the request's device footprint fits the HBM budget, and
+ * launches steps_per_launch batched steps that advance every admitted solve
+ * together (a replayed hipGraph).  Requests submitted while others run join
+ * at the next pump.  Each solve computes exactly what a lone vlb_lattice with
+ * the same mask, parameters and rounding seed computes: results do not
+ * depend on what else is in the batch.  Walls in a request mask are at rest;
+ * moving particles are not served.
+ */
+typedef enum vlb_request_state {
+    VLB_REQ_QUEUED = 0,
+    VLB_REQ_RUNNING = 1,
+    VLB_REQ_DONE = 2,
+    VLB_REQ_CANCELLED = 3,
+    VLB_REQ_FAILED = 4
+} vlb_request_state;
+
+typedef struct vlb_request {
+    vlb_dims dims;
+    const uint8_t *mask;    /* N bytes: 0 fluid, 1..63 solid at rest; copied        */
+    vlb_params params;
+    int32_t n_spheres;
+    const double *spheres;  /* n_spheres x {cx, cy, cz, r}: fixed spheres, copied     */
+    int64_t n_steps;
+    uint32_t seed;          /* stochastic-rounding seed (vlb_set_rounding)           */
+} vlb_request;
+
+typedef struct vlb_server_stats {
+    int64_t submitted, completed, queued, running, launches, graph_captures;
+    uint64_t bytes_in_use, cell_steps_launched;
+} vlb_server_stats;
+
+typedef struct vlb_server vlb_server;
+
+/* hbm_budget_bytes bounds the summed footprint of admitted solves;
+ * max_slots bounds their number (<= 4096); steps_per_launch is the number
+ * of batched steps per pump (1..4096).  stream as for vlb_create. */
+vlb_status vlb_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t steps_per_launch,
+                             void *stream, vlb_server **out);
+/* Device bytes a request of these dimensions holds while admitted. */
+size_t vlb_server_request_bytes(const vlb_dims *dims);
+/* Rounding of stored values for every solve (only while idle). */
+vlb_status vlb_server_set_rounding(vlb_server *srv, vlb_rounding mode);
+/* Queue a request (inputs copied).  VLB_EBUSY if it can never fit the budget,
+ * VLB_EINVAL for invalid dimensions, mask or parameters. */
+vlb_status vlb_server_submit(vlb_server *srv, const vlb_request *req, uint64_t *ticket);
+/* One scheduling round (retire, admit, launch).  wait = 0 returns at once if
+ * the previous launch is still running; wait = 1 waits for it. */
+vlb_status vlb_server_pump(vlb_server *srv, int32_t wait);
+vlb_status vlb_server_poll(vlb_server *srv, uint64_t ticket, int32_t *state);
+/* Copy the result of a finished request (u: 3*N, tau: 6*N doubles, either
+ * may be NULL) and its latency from submission to completion, then forget
+ * the request.  VLB_ESTATE if it has not finished. */
+vlb_status vlb_server_result(vlb_server *srv, uint64_t ticket, double *u, double *tau,
+                             double *latency_ms);
+vlb_status vlb_server_cancel(vlb_server *srv, uint64_t ticket);
+vlb_status vlb_server_stats_get(vlb_server *srv, vlb_server_stats *out);
+const char *vlb_server_last_error(const vlb_server *srv);
+void vlb_server_destroy(vlb_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

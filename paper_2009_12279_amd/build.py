@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SO = os.path.join(HERE, "libvlb.so")
-SOURCES = ["csrc/vlb_kernels.hip", "csrc/vlb_api.hip"]
+SOURCES = ["csrc/vlb_kernels.hip", "csrc/vlb_api.hip", "csrc/vlb_server.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -92,8 +92,30 @@ struct StepArgs {
     uint32_t seed;
 };
 
+// One solve of the batched (serving) step: step arguments for both buffer
+// parities (index = step & 1), its block range and its step target.
+struct BatchSolve {
+    StepArgs args[2];
+    uint32_t first_block;
+    uint32_t nblocks;
+    uint32_t target;
+    uint32_t pad;
+};
+
+struct BatchTable {
+    uint32_t n_solves;
+    uint32_t total_blocks;
+    const BatchSolve *solves;     // [n_solves]
+    const uint16_t *block_solve;  // [total_blocks]
+    uint32_t *steps;              // [n_solves], advanced on the device
+};
+
 // Host-side launchers (vlb_kernels.hip).
 hipError_t launch_lb_step(int storage, const StepArgs &a, hipStream_t s);
+// n_steps batched steps (stream-collide, stress update, counter advance per
+// step) over every solve of the table; grid of max_blocks blocks.
+hipError_t launch_batch_step(const BatchTable *t, uint32_t max_blocks, int stochastic, int n_steps,
+                             hipStream_t s);
 hipError_t launch_fv_step(int storage, const StepArgs &a, hipStream_t s);
 hipError_t launch_init_equilibrium(int storage, const Geom &g, const uint8_t *mask,
                                    const double *u, void *f, float scale, hipStream_t s);

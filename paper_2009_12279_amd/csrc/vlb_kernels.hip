@@ -435,15 +435,14 @@ __device__ void reflect_links(const StepArgs &a, typename Store<S>::T *fout, uin
 #define FV_OCCUPANCY
 #endif
 
+// Stream-collide of cell n of the lattice described by `a`, at step `step`
+// (the step only seeds the rounding stream).
 template <int S, bool SR>
-__global__ __launch_bounds__(BLOCK) LB_OCCUPANCY void lb_step_kernel(StepArgs a)
+__device__ __forceinline__ void lb_cell(const StepArgs &a, uint32_t n, uint32_t step)
 {
     using St = Store<S>;
     using T = typename St::T;
     using R = typename St::R;
-    const uint32_t n = block_id(a.remap, a.slab_blocks) * BLOCK + threadIdx.x;
-    if (n >= a.g.N)
-        return;
     const uint8_t *__restrict__ mask = a.mask;
     int x, y, z;
     coords(a.g, n, x, y, z);
@@ -541,7 +540,7 @@ __global__ __launch_bounds__(BLOCK) LB_OCCUPANCY void lb_step_kernel(StepArgs a)
     const R P1 = wp * (drho - R(1.5) * rho * uu) - R(3) * cp * uF;
     const R Q1 = R(4.5) * wp * rho, C9 = R(9) * cp;
     const R M3 = R(3) * wm * rho, C3 = R(3) * cm;
-    Rng rng(n, a.step, a.seed);
+    Rng rng(n, step, a.seed);
     uint32_t r = rng.next32();
     stp<S, SR>(static_cast<T *>(a.fout_p[0]), n,
                R(2) * a1 * static_cast<R>(pop(0)) + static_cast<R>(WD[0]) * P1, a.scale, rhi(r));
@@ -577,6 +576,15 @@ __global__ __launch_bounds__(BLOCK) LB_OCCUPANCY void lb_step_kernel(StepArgs a)
     }
 }
 
+template <int S, bool SR>
+__global__ __launch_bounds__(BLOCK) LB_OCCUPANCY void lb_step_kernel(StepArgs a)
+{
+    const uint32_t n = block_id(a.remap, a.slab_blocks) * BLOCK + threadIdx.x;
+    if (n >= a.g.N)
+        return;
+    lb_cell<S, SR>(a, n, a.step);
+}
+
 // ---------------------------------------------------------------------------
 // Finite-volume Oldroyd-B stress update (Section 2.2 source, Section 3.3).
 // The increment (fluxes + source, products of small quantities) is formed in
@@ -592,11 +600,8 @@ __device__ __forceinline__ float face_overlap(const float u[3], int k, int s)
 }
 
 template <bool SR>
-__global__ __launch_bounds__(BLOCK) FV_OCCUPANCY void fv_step_kernel(StepArgs a)
+__device__ __forceinline__ void fv_cell(const StepArgs &a, uint32_t n, uint32_t step)
 {
-    const uint32_t n = block_id(a.remap, a.slab_blocks) * BLOCK + threadIdx.x;
-    if (n >= a.g.N)
-        return;
     const uint8_t *__restrict__ mask = a.mask;
     int x, y, z;
     coords(a.g, n, x, y, z);
@@ -679,7 +684,7 @@ __global__ __launch_bounds__(BLOCK) FV_OCCUPANCY void fv_step_kernel(StepArgs a)
     const int PI[6] = {0, 1, 2, 0, 0, 1};
     const int PJ[6] = {0, 1, 2, 1, 2, 2};
     const float epl = static_cast<float>(a.eta_p_lam), il = static_cast<float>(a.inv_lam);
-    Rng rng(n, a.step, a.seed ^ 0x5bd1e995u);
+    Rng rng(n, step, a.seed ^ 0x5bd1e995u);
     uint32_t r = 0;
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
@@ -694,6 +699,65 @@ __global__ __launch_bounds__(BLOCK) FV_OCCUPANCY void fv_step_kernel(StepArgs a)
             r = rng.next32();
         stp<ST_F32, SR>(a.tout_p[c], n, v, 1.f, (c & 1) ? rlo(r) : rhi(r));
     }
+}
+
+template <bool SR>
+__global__ __launch_bounds__(BLOCK) FV_OCCUPANCY void fv_step_kernel(StepArgs a)
+{
+    const uint32_t n = block_id(a.remap, a.slab_blocks) * BLOCK + threadIdx.x;
+    if (n >= a.g.N)
+        return;
+    fv_cell<SR>(a, n, a.step);
+}
+
+// ---------------------------------------------------------------------------
+// Batched step over many independent lattices (serving).  Block b belongs to
+// solve block_solve[b]; each solve holds the step arguments for both
+// population/stress buffer parities and its own step counter, so the same
+// launch advances every active solve by one step and the launches can be
+// captured once and replayed.
+
+template <bool SR>
+__global__ __launch_bounds__(BLOCK) void lb_batch_kernel(const BatchTable *__restrict__ t)
+{
+    const uint32_t b = blockIdx.x;
+    if (b >= t->total_blocks)
+        return;
+    const uint32_t s = t->block_solve[b];
+    const BatchSolve &bs = t->solves[s];
+    const uint32_t step = t->steps[s];
+    if (step >= bs.target)
+        return;
+    const StepArgs &a = bs.args[step & 1u];
+    const uint32_t n = (b - bs.first_block) * BLOCK + threadIdx.x;
+    if (n >= a.g.N)
+        return;
+    lb_cell<ST_F32, SR>(a, n, step);
+}
+
+template <bool SR>
+__global__ __launch_bounds__(BLOCK) void fv_batch_kernel(const BatchTable *__restrict__ t)
+{
+    const uint32_t b = blockIdx.x;
+    if (b >= t->total_blocks)
+        return;
+    const uint32_t s = t->block_solve[b];
+    const BatchSolve &bs = t->solves[s];
+    const uint32_t step = t->steps[s];
+    if (step >= bs.target || !bs.args[0].polymer)
+        return;
+    const StepArgs &a = bs.args[step & 1u];
+    const uint32_t n = (b - bs.first_block) * BLOCK + threadIdx.x;
+    if (n >= a.g.N)
+        return;
+    fv_cell<SR>(a, n, step);
+}
+
+__global__ void batch_advance_kernel(BatchTable *t)
+{
+    for (uint32_t s = threadIdx.x; s < t->n_solves; s += blockDim.x)
+        if (t->steps[s] < t->solves[s].target)
+            t->steps[s] += 1u;
 }
 
 // ---------------------------------------------------------------------------
@@ -1463,6 +1527,23 @@ hipError_t launch_fv_step(int storage, const StepArgs &a, hipStream_t s)
         hipLaunchKernelGGL(fv_step_kernel<true>, dim3(blocks_for(a.g.N)), dim3(BLOCK), 0, s, a);
     else
         hipLaunchKernelGGL(fv_step_kernel<false>, dim3(blocks_for(a.g.N)), dim3(BLOCK), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_step(const BatchTable *t, uint32_t max_blocks, int stochastic, int n_steps,
+                             hipStream_t s)
+{
+    for (int k = 0; k < n_steps; ++k) {
+        if (stochastic) {
+            hipLaunchKernelGGL(lb_batch_kernel<true>, dim3(max_blocks), dim3(BLOCK), 0, s, t);
+            hipLaunchKernelGGL(fv_batch_kernel<true>, dim3(max_blocks), dim3(BLOCK), 0, s, t);
+        } else {
+            hipLaunchKernelGGL(lb_batch_kernel<false>, dim3(max_blocks), dim3(BLOCK), 0, s, t);
+            hipLaunchKernelGGL(fv_batch_kernel<false>, dim3(max_blocks), dim3(BLOCK), 0, s, t);
+        }
+        hipLaunchKernelGGL(batch_advance_kernel, dim3(1), dim3(256), 0, s,
+                           const_cast<BatchTable *>(t));
+    }
     return hipGetLastError();
 }
 

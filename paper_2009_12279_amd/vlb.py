@@ -44,6 +44,21 @@ class vlb_params(ctypes.Structure):
                 ("body_force", ctypes.c_double * 3)]
 
 
+class vlb_request(ctypes.Structure):
+    _fields_ = [("dims", vlb_dims), ("mask", ctypes.c_char_p), ("params", vlb_params),
+                ("n_spheres", ctypes.c_int32), ("spheres", ctypes.POINTER(ctypes.c_double)),
+                ("n_steps", ctypes.c_int64), ("seed", ctypes.c_uint32)]
+
+
+class vlb_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("queued", ctypes.c_int64), ("running", ctypes.c_int64),
+                ("launches", ctypes.c_int64), ("graph_captures", ctypes.c_int64),
+                ("bytes_in_use", ctypes.c_uint64), ("cell_steps_launched", ctypes.c_uint64)]
+
+
+REQ_STATES = {0: "queued", 1: "running", 2: "done", 3: "cancelled", 4: "failed"}
+
 _lib = None
 _D = ctypes.POINTER(ctypes.c_double)
 _P = ctypes.c_void_p
@@ -80,6 +95,19 @@ SIGNATURES = [
     ("vlb_set_timing", ctypes.c_int, [_P, ctypes.c_int32]),
     ("vlb_kernel_time_ms", ctypes.c_double, [_P, ctypes.c_int32]),
     ("vlb_set_rounding", ctypes.c_int, [_P, ctypes.c_int, ctypes.c_uint32]),
+    ("vlb_server_create", ctypes.c_int, [ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32, _P,
+                                         ctypes.POINTER(_P)]),
+    ("vlb_server_set_rounding", ctypes.c_int, [_P, ctypes.c_int]),
+    ("vlb_server_request_bytes", ctypes.c_size_t, [ctypes.POINTER(vlb_dims)]),
+    ("vlb_server_submit", ctypes.c_int, [_P, ctypes.POINTER(vlb_request),
+                                         ctypes.POINTER(ctypes.c_uint64)]),
+    ("vlb_server_pump", ctypes.c_int, [_P, ctypes.c_int32]),
+    ("vlb_server_poll", ctypes.c_int, [_P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32)]),
+    ("vlb_server_result", ctypes.c_int, [_P, ctypes.c_uint64, _D, _D, _D]),
+    ("vlb_server_cancel", ctypes.c_int, [_P, ctypes.c_uint64]),
+    ("vlb_server_stats_get", ctypes.c_int, [_P, ctypes.POINTER(vlb_server_stats)]),
+    ("vlb_server_last_error", ctypes.c_char_p, [_P]),
+    ("vlb_server_destroy", None, [_P]),
 ]
 
 
@@ -405,3 +433,95 @@ class Lattice:
 
     def set_rounding(self, mode="stochastic", seed=0x2009):
         vlb_set_rounding(self._h, mode, seed)
+
+
+# ---- serving ------------------------------------------------------------------
+
+def _scheck(status, srv):
+    if status != VLB_OK:
+        msg = lib().vlb_server_last_error(srv) if srv else b""
+        raise VlbError(status, msg.decode() if msg else "")
+    return status
+
+
+def vlb_server_create(hbm_budget_bytes, max_slots=64, steps_per_launch=50, stream=None):
+    h = _P()
+    _scheck(lib().vlb_server_create(int(hbm_budget_bytes), int(max_slots), int(steps_per_launch),
+                                    None if stream is None else _P(int(stream)),
+                                    ctypes.byref(h)), None)
+    return h
+
+
+def vlb_server_request_bytes(shape, periodic=(1, 1, 1)):
+    d = make_dims(shape, periodic)
+    return int(lib().vlb_server_request_bytes(ctypes.byref(d)))
+
+
+def vlb_server_set_rounding(srv, mode="stochastic"):
+    return _scheck(lib().vlb_server_set_rounding(srv, ROUNDING[mode]), srv)
+
+
+def vlb_server_submit(srv, shape, mask, periodic=(1, 1, 1), params=None, spheres=(), n_steps=1,
+                      seed=0x2009):
+    nx, ny, nz = shape
+    m = np.ascontiguousarray(mask, dtype=np.uint8)
+    if m.shape != (nz, ny, nx):
+        raise ValueError("mask must be shaped [nz, ny, nx]")
+    req = vlb_request()
+    req.dims = make_dims(shape, periodic)
+    mb = m.tobytes()
+    req.mask = mb
+    p = vlb_params()
+    pr = dict(eta=1.0 / 3.0, beta=0.0, lambda_p=1.0, magic=3.0 / 16.0, body_force=(0, 0, 0))
+    pr.update(params or {})
+    p.eta, p.beta, p.lambda_p, p.magic = (float(pr[k]) for k in ("eta", "beta", "lambda_p", "magic"))
+    for a in range(3):
+        p.body_force[a] = float(pr["body_force"][a])
+    req.params = p
+    sp = np.ascontiguousarray(np.asarray(spheres, dtype=np.float64).reshape(-1, 4)) if len(spheres) \
+        else np.zeros((0, 4))
+    req.n_spheres = sp.shape[0]
+    req.spheres = _dp(sp) if sp.shape[0] else None
+    req.n_steps = int(n_steps)
+    req.seed = int(seed) & 0xFFFFFFFF
+    ticket = ctypes.c_uint64()
+    _scheck(lib().vlb_server_submit(srv, ctypes.byref(req), ctypes.byref(ticket)), srv)
+    return ticket.value
+
+
+def vlb_server_pump(srv, wait=False):
+    return _scheck(lib().vlb_server_pump(srv, int(bool(wait))), srv)
+
+
+def vlb_server_poll(srv, ticket):
+    st = ctypes.c_int32()
+    _scheck(lib().vlb_server_poll(srv, int(ticket), ctypes.byref(st)), srv)
+    return REQ_STATES[st.value]
+
+
+def vlb_server_result(srv, ticket, shape):
+    nx, ny, nz = shape
+    u = np.zeros((3, nz, ny, nx))
+    tau = np.zeros((6, nz, ny, nx))
+    lat = ctypes.c_double()
+    _scheck(lib().vlb_server_result(srv, int(ticket), _dp(u), _dp(tau),
+                                    ctypes.cast(ctypes.pointer(lat), _D)), srv)
+    return u, tau, lat.value
+
+
+def vlb_server_cancel(srv, ticket):
+    return _scheck(lib().vlb_server_cancel(srv, int(ticket)), srv)
+
+
+def vlb_server_stats_get(srv):
+    st = vlb_server_stats()
+    _scheck(lib().vlb_server_stats_get(srv, ctypes.byref(st)), srv)
+    return {k: getattr(st, k) for k, _ in vlb_server_stats._fields_}
+
+
+def vlb_server_last_error(srv):
+    return lib().vlb_server_last_error(srv).decode()
+
+
+def vlb_server_destroy(srv):
+    lib().vlb_server_destroy(srv)

@@ -1,0 +1,171 @@
+"""Serving (continuous batching): a solve gives bit-identical results alone,
+in a mix it joined while others were running, and through a plain lattice;
+admission respects the memory budget and the slot count; cancellation; and
+one served solve against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2009_12279_amd import inputs, vlb
+from parity import log
+
+pytestmark = pytest.mark.gpu
+
+GB = 1 << 30
+
+
+def make_request(seed, shape, n_steps, n_spheres=1, wi=0.5):
+    """A channel (walls in y, periodic x, z) with fixed spheres, driven by a
+    body force; lambda from the Weissenberg number at the wall shear rate."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = shape
+    mask = inputs.channel_mask(shape, wall_axes=(1,))
+    eta, g = 1 / 3, 1e-5
+    beta = float(rng.uniform(0.1, 0.9))
+    lam = max(1.0, wi / (g * (ny - 2) / (2 * eta)))
+    spheres = []
+    for _ in range(n_spheres):
+        r = float(rng.uniform(2.0, 3.5))
+        c = [rng.uniform(0, nx), rng.uniform(r + 2, ny - 3 - r), rng.uniform(0, nz)]
+        spheres.append(c + [r])
+    params = dict(eta=eta, beta=beta, lambda_p=lam, magic=3 / 16, body_force=(g, 0, 0))
+    return dict(shape=shape, mask=mask, periodic=(1, 0, 1), params=params, spheres=spheres,
+                n_steps=n_steps, seed=1000 + seed)
+
+
+REQS = [
+    (1, (16, 18, 12), 120, 1),
+    (2, (24, 14, 20), 200, 2),
+    (3, (20, 20, 20), 90, 0),
+    (4, (32, 12, 8), 160, 1),
+]
+
+
+def serve(reqs, budget=4 * GB, slots=16, k=10, stagger=True):
+    srv = vlb.vlb_server_create(budget, slots, k)
+    try:
+        tickets = {}
+        pending = list(reqs)
+        # submit the first one, then the others while it runs
+        first = pending.pop(0)
+        tickets[first["seed"]] = (vlb.vlb_server_submit(srv, **{k2: first[k2] for k2 in (
+            "shape", "mask", "periodic", "params", "spheres", "n_steps", "seed")}), first)
+        out = {}
+        rounds = 0
+        while len(out) < len(reqs):
+            vlb.vlb_server_pump(srv, wait=True)
+            rounds += 1
+            if pending and (not stagger or rounds % 2 == 0):
+                r = pending.pop(0)
+                tickets[r["seed"]] = (vlb.vlb_server_submit(srv, **{k2: r[k2] for k2 in (
+                    "shape", "mask", "periodic", "params", "spheres", "n_steps", "seed")}), r)
+            for seed, (t, r) in tickets.items():
+                if seed not in out and vlb.vlb_server_poll(srv, t) == "done":
+                    out[seed] = vlb.vlb_server_result(srv, t, r["shape"])
+            assert rounds < 10000
+        return out, vlb.vlb_server_stats_get(srv)
+    finally:
+        vlb.vlb_server_destroy(srv)
+
+
+def test_results_identical_alone_and_in_the_mix():
+    reqs = [make_request(*r) for r in REQS]
+    log("[serving] mix of 4 requests, staggered submission")
+    mixed, stats = serve(reqs)
+    log(f"[serving]   stats {stats}")
+    assert stats["completed"] == 4 and stats["launches"] > 0
+    for r in reqs:
+        log(f"[serving] alone seed={r['seed']} shape={r['shape']}")
+        alone, _ = serve([r], slots=1)
+        ua, ta, _ = alone[r["seed"]]
+        um, tm, lat = mixed[r["seed"]]
+        assert lat > 0
+        np.testing.assert_array_equal(ua, um)
+        np.testing.assert_array_equal(ta, tm)
+
+
+def test_served_solve_equals_plain_lattice():
+    r = make_request(7, (18, 16, 14), 150, 1)
+    log("[serving] served vs plain lattice")
+    out, _ = serve([r], slots=2, k=7)
+    us, ts, _ = out[r["seed"]]
+    L = vlb.Lattice(r["shape"], r["mask"], r["periodic"])
+    L.set_params(**r["params"])
+    for (cx, cy, cz, rad) in r["spheres"]:
+        L.add_sphere(center=(cx, cy, cz), radius=rad)
+    L.set_rounding("stochastic", r["seed"])
+    L.set_check_interval(0)
+    L.init_equilibrium()
+    L.step(r["n_steps"])
+    np.testing.assert_array_equal(L.velocity(), us)
+    np.testing.assert_array_equal(L.stress(), ts)
+    L.close()
+
+
+def test_admission_respects_budget_and_slots():
+    reqs = [make_request(10 + i, (16, 16, 16), 40, 0) for i in range(5)]
+    one = vlb.vlb_server_request_bytes((16, 16, 16))
+    log("[serving] budget for ~2 requests, 3 slots")
+    srv = vlb.vlb_server_create(int(2.5 * one), 3, 5)
+    try:
+        # a request that can never fit is refused at submission
+        big = make_request(99, (64, 64, 64), 10, 0)
+        with pytest.raises(vlb.VlbError) as ei:
+            vlb.vlb_server_submit(srv, **{k: big[k] for k in (
+                "shape", "mask", "periodic", "params", "spheres", "n_steps", "seed")})
+        assert ei.value.status == vlb.VLB_EBUSY
+        ts = [vlb.vlb_server_submit(srv, **{k: r[k] for k in (
+            "shape", "mask", "periodic", "params", "spheres", "n_steps", "seed")}) for r in reqs]
+        max_running = 0
+        for _ in range(200):
+            vlb.vlb_server_pump(srv, wait=True)
+            st = vlb.vlb_server_stats_get(srv)
+            max_running = max(max_running, st["running"])
+            assert st["bytes_in_use"] <= 2.5 * one
+            if st["completed"] == len(reqs):
+                break
+        assert st["completed"] == len(reqs)
+        assert max_running == 2
+        for t in ts:
+            assert vlb.vlb_server_poll(srv, t) == "done"
+    finally:
+        vlb.vlb_server_destroy(srv)
+
+
+def test_cancel_queued_and_running():
+    reqs = [make_request(20 + i, (16, 12, 10), 400, 0) for i in range(3)]
+    srv = vlb.vlb_server_create(4 * GB, 1, 5)
+    try:
+        ts = [vlb.vlb_server_submit(srv, **{k: r[k] for k in (
+            "shape", "mask", "periodic", "params", "spheres", "n_steps", "seed")}) for r in reqs]
+        vlb.vlb_server_pump(srv, wait=True)
+        assert vlb.vlb_server_poll(srv, ts[0]) == "running"
+        vlb.vlb_server_cancel(srv, ts[0])
+        vlb.vlb_server_cancel(srv, ts[2])
+        for _ in range(500):
+            vlb.vlb_server_pump(srv, wait=True)
+            if vlb.vlb_server_poll(srv, ts[1]) == "done":
+                break
+        assert vlb.vlb_server_poll(srv, ts[0]) == "cancelled"
+        assert vlb.vlb_server_poll(srv, ts[2]) == "cancelled"
+        assert vlb.vlb_server_poll(srv, ts[1]) == "done"
+    finally:
+        vlb.vlb_server_destroy(srv)
+
+
+def test_served_solve_matches_oracle():
+    r = make_request(30, (12, 14, 10), 300, 1)
+    out, _ = serve([r], slots=4, k=25)
+    us, ts, _ = out[r["seed"]]
+    o = oracle.Lattice(r["shape"], r["mask"], r["periodic"])
+    o.set_params(**r["params"])
+    for (cx, cy, cz, rad) in r["spheres"]:
+        o.add_sphere((cx, cy, cz), rad)
+    o.init_equilibrium()
+    o.step(r["n_steps"])
+    fl = o.mask() == 0
+    uo, to = o.velocity(), o.stress()
+    eu = np.max(np.abs(us[:, fl] - uo[:, fl])) / np.max(np.abs(uo[:, fl]))
+    et = np.max(np.abs(ts[:, fl] - to[:, fl])) / np.max(np.abs(to[:, fl]))
+    log(f"[serving] vs oracle: u {eu:.2e} tau {et:.2e}")
+    assert eu < 1e-5 and et < 1e-5
