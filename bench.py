@@ -131,6 +131,124 @@ def run_cpu_baseline(args):
                        f"(FP64 oracle, OpenMP {threads} threads)")
 
 
+def serving_requests(n, steps_scale):
+    """Seeded request list of the serving workload: edges drawn from
+    {32, 48, 64, 96, 128} per axis, walls at y = 0 and n_y - 1 (periodic x, z),
+    0-8 fixed spheres of radius 4-8 at least one cell clear of the walls and
+    of each other, Weissenberg number log-uniform in [0.05, 2] converted to
+    lambda_p with the wall shear rate of the empty channel, beta uniform in
+    [0.1, 0.9], 2000-20000 steps (times steps_scale)."""
+    from paper_2009_12279_amd import inputs
+
+    edges = [32, 48, 64, 96, 128]
+    eta, g = 1.0 / 3.0, 1e-6
+    out = []
+    for k in range(n):
+        st = inputs.Stream(5, k)
+        shape = tuple(int(edges[i]) for i in st.integers(0, 4, 3))
+        nx, ny, nz = shape
+        wi = float(np.exp(st.uniform(1, np.log(0.05), np.log(2.0))[0]))
+        beta = float(st.uniform(1, 0.1, 0.9)[0])
+        steps = int(st.integers(2000, 20000, 1)[0] * steps_scale)
+        count = int(st.integers(0, 8, 1)[0])
+        spheres = []
+        while count > 0:
+            try:
+                spheres = inputs.place_spheres(5, 1000 + k, shape, count, 4.0, 8.0, min_gap=1.0,
+                                               periodic=(1, 0, 1), margin=2.0, max_tries=2000)
+                break
+            except RuntimeError:
+                count -= 1
+        gamma = g * (ny - 2) / (2 * eta)
+        lam = max(1.0, wi / gamma)
+        out.append(dict(shape=shape, mask=inputs.channel_mask(shape, wall_axes=(1,)),
+                        periodic=(1, 0, 1), spheres=[list(c) + [r] for c, r in spheres],
+                        params=dict(eta=eta, beta=beta, lambda_p=lam, magic=3.0 / 16.0,
+                                    body_force=(g, 0.0, 0.0)),
+                        n_steps=steps, seed=0x2009 + k))
+    return out
+
+
+def run_serving(args):
+    """Sequential plain solves, then the same requests through the server with
+    Poisson arrivals at 1.5x the sequential service rate."""
+    import torch
+
+    from paper_2009_12279_amd import vlb
+
+    torch.cuda.set_device(0)
+    reqs = serving_requests(args.serving_requests, args.serving_steps_scale)
+    cell_steps = sum(int(np.prod(r["shape"])) * r["n_steps"] for r in reqs)
+    # sequential baseline: one plain lattice after another
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in reqs:
+        L = vlb.Lattice(r["shape"], r["mask"], r["periodic"])
+        L.set_params(**r["params"])
+        for c in r["spheres"]:
+            L.add_sphere(center=c[:3], radius=c[3])
+        L.set_rounding("stochastic", r["seed"])
+        L.set_check_interval(0)
+        L.init_equilibrium()
+        L.step(r["n_steps"])
+        L.velocity()
+        L.stress()
+        L.close()
+    seq_s = time.perf_counter() - t0
+    rate = 1.5 * len(reqs) / seq_s
+    budget = int(args.serving_budget_gb * (1 << 30))
+
+    def serve(arrivals):
+        srv = vlb.vlb_server_create(budget, args.serving_slots, args.serving_k)
+        lat = []
+        try:
+            tickets = {}
+            nxt = 0
+            t0 = time.perf_counter()
+            while len(lat) < len(reqs):
+                now = time.perf_counter() - t0
+                while nxt < len(reqs) and arrivals[nxt] <= now:
+                    r = reqs[nxt]
+                    tickets[nxt] = vlb.vlb_server_submit(srv, **{k: r[k] for k in (
+                        "shape", "mask", "periodic", "params", "spheres", "n_steps", "seed")})
+                    nxt += 1
+                vlb.vlb_server_pump(srv, wait=False)
+                for i, t in list(tickets.items()):
+                    if vlb.vlb_server_poll(srv, t) == "done":
+                        _, _, ms = vlb.vlb_server_result(srv, t, reqs[i]["shape"])
+                        lat.append(ms)
+                        del tickets[i]
+                if not tickets and nxt < len(reqs):
+                    time.sleep(max(0.0, min(0.002, arrivals[nxt] - (time.perf_counter() - t0))))
+            wall = time.perf_counter() - t0
+            stats = vlb.vlb_server_stats_get(srv)
+        finally:
+            vlb.vlb_server_destroy(srv)
+        return np.array(lat), wall, stats
+
+    # throughput with every request queued at t = 0, then latency under
+    # Poisson arrivals at 1.5x the sequential service rate
+    _, sat_s, sat_stats = serve(np.zeros(len(reqs)))
+    rng = np.random.default_rng(args.serving_requests)
+    lat, bat_s, stats = serve(np.cumsum(rng.exponential(1.0 / rate, len(reqs))))
+    lat = np.array(lat)
+    return dict(
+        requests=len(reqs), steps_scale=args.serving_steps_scale,
+        cell_steps=cell_steps, arrival_rate_hz=round(rate, 3),
+        budget_gb=args.serving_budget_gb, slots=args.serving_slots,
+        steps_per_launch=args.serving_k,
+        p50_ms=round(float(np.percentile(lat, 50)), 2),
+        p99_ms=round(float(np.percentile(lat, 99)), 2),
+        poisson_wall_s=round(bat_s, 3), saturated_wall_s=round(sat_s, 3),
+        sequential_wall_s=round(seq_s, 3),
+        batched_mlups=round(cell_steps / sat_s / 1e6, 1),
+        sequential_mlups=round(cell_steps / seq_s / 1e6, 1),
+        speedup=round(seq_s / sat_s, 3),
+        launches=stats["launches"], graph_captures=stats["graph_captures"],
+        graph_updates=stats["graph_updates"],
+    )
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -140,6 +258,12 @@ def main():
     ap.add_argument("--rounding", default=None, choices=[None, "nearest", "stochastic"])
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=48)
+    ap.add_argument("--serving-steps-scale", type=float, default=0.1)
+    ap.add_argument("--serving-budget-gb", type=float, default=8.0)
+    ap.add_argument("--serving-slots", type=int, default=64)
+    ap.add_argument("--serving-k", type=int, default=50)
+    ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (torch) so that hardware byte "
                          "counters can be scaled against a kernel of known traffic")
@@ -158,6 +282,7 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    serving = None if args.no_serving else run_serving(args)
     cpu = None
     if rank == 0 and not args.no_cpu_baseline:
         cpu = run_cpu_baseline(args)
@@ -200,6 +325,7 @@ def main():
             "traffic": None,
         },
         "cpu_baseline": cpu,
+        "serving": serving,
     }
     print(json.dumps(line), flush=True)
 

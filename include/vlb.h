@@ -226,7 +226,7 @@ typedef struct vlb_request {
 } vlb_request;
 
 typedef struct vlb_server_stats {
-    int64_t submitted, completed, queued, running, launches, graph_captures;
+    int64_t submitted, completed, queued, running, launches, graph_captures, graph_updates;
     uint64_t bytes_in_use, cell_steps_launched;
 } vlb_server_stats;
 

@@ -106,7 +106,7 @@ struct BatchTable {
     uint32_t n_solves;
     uint32_t total_blocks;
     const BatchSolve *solves;     // [n_solves]
-    const uint16_t *block_solve;  // [total_blocks]
+    const uint32_t *block_solve;  // [total_blocks]
     uint32_t *steps;              // [n_solves], advanced on the device
 };
 

@@ -393,27 +393,58 @@ __constant__ int8_t kCX[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 
 __constant__ int8_t kCY[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
 __constant__ int8_t kCZ[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
 
+// Field-wise copies of the geometry and boundary descriptors, for argument
+// blocks that live in the constant address space (the implicit copy
+// constructor cannot bind to those).
+template <class G>
+__device__ __forceinline__ Geom geom_copy(const G &g)
+{
+    Geom r;
+    r.nx = g.nx;
+    r.ny = g.ny;
+    r.nz = g.nz;
+    r.per[0] = g.per[0];
+    r.per[1] = g.per[1];
+    r.per[2] = g.per[2];
+    r.N = g.N;
+    r.plane = g.plane;
+    return r;
+}
+template <class B>
+__device__ __forceinline__ Bound bound_copy(const B &b)
+{
+    Bound r;
+    r.wall_vel = b.wall_vel;
+    r.n_walls = b.n_walls;
+    r.parts = b.parts;
+    r.n_parts = b.n_parts;
+    r.moving = b.moving;
+    return r;
+}
+
 // Bounce-back for every link of cell n into a solid cell (Section 3.1
 // velocity boundary condition): the post-collision population just stored
 // for direction j is reflected, with the moving-wall term, into the slot of
 // the solid cell that the next pull of this cell reads.  `links` has bit j
 // set for each solid neighbour along c_j.
-template <int S, bool SR, class R>
-__device__ void reflect_links(const StepArgs &a, typename Store<S>::T *fout, uint32_t n,
+template <int S, bool SR, class R, class A>
+__device__ void reflect_links(const A &a, typename Store<S>::T *fout, uint32_t n,
                               const Delta &d, uint32_t links, R rho, Rng &rng)
 {
-    const uint64_t P = a.g.plane;
+    const Geom g = geom_copy(a.g);
+    const Bound bnd = bound_copy(a.b);
+    const uint64_t P = g.plane;
     while (links) {
         const int j = __builtin_ctz(links);
         links &= links - 1;
         const int cx = kCX[j], cy = kCY[j], cz = kCZ[j];
         const uint32_t m = d.at_rt(n, cx, cy, cz);
         R val = static_cast<R>(ldp<S>(fout + j * P, n, a.inv_scale));
-        if (a.b.moving) {
+        if (bnd.moving) {
             int x, y, z;
-            coords(a.g, m, x, y, z);
+            coords(g, m, x, y, z);
             double ub[3];
-            boundary_velocity_d(a.g, a.b, a.mask[m], x, y, z, ub);
+            boundary_velocity_d(g, bnd, a.mask[m], x, y, z, ub);
             const double w = (cx * cx + cy * cy + cz * cz == 1) ? 1.0 / 18.0 : 1.0 / 36.0;
             val -= R(6) * static_cast<R>(w) * rho * static_cast<R>(cx * ub[0] + cy * ub[1] + cz * ub[2]);
         }
@@ -437,16 +468,17 @@ __device__ void reflect_links(const StepArgs &a, typename Store<S>::T *fout, uin
 
 // Stream-collide of cell n of the lattice described by `a`, at step `step`
 // (the step only seeds the rounding stream).
-template <int S, bool SR>
-__device__ __forceinline__ void lb_cell(const StepArgs &a, uint32_t n, uint32_t step)
+template <int S, bool SR, class A>
+__device__ __forceinline__ void lb_cell(const A &a, uint32_t n, uint32_t step)
 {
+    const Geom g = geom_copy(a.g);
     using St = Store<S>;
     using T = typename St::T;
     using R = typename St::R;
     const uint8_t *__restrict__ mask = a.mask;
     int x, y, z;
-    coords(a.g, n, x, y, z);
-    const Delta d(a.g, x, y, z);
+    coords(g, n, x, y, z);
+    const Delta d(g, x, y, z);
 
     // Every load is issued before any result is used (all addresses are in
     // bounds, also for solid cells), so a wave has all its memory requests
@@ -599,13 +631,14 @@ __device__ __forceinline__ float face_overlap(const float u[3], int k, int s)
     return ue * (1.f - fabsf(u[a1])) * (1.f - fabsf(u[a2]));
 }
 
-template <bool SR>
-__device__ __forceinline__ void fv_cell(const StepArgs &a, uint32_t n, uint32_t step)
+template <bool SR, class A>
+__device__ __forceinline__ void fv_cell(const A &a, uint32_t n, uint32_t step)
 {
+    const Geom g = geom_copy(a.g);
     const uint8_t *__restrict__ mask = a.mask;
     int x, y, z;
-    coords(a.g, n, x, y, z);
-    const Delta d(a.g, x, y, z);
+    coords(g, n, x, y, z);
+    const Delta d(g, x, y, z);
     // all loads first (in bounds for every cell), selection afterwards
     const float u0[3] = {*elem(a.u_p[0], n), *elem(a.u_p[1], n), *elem(a.u_p[2], n)};
     float t0[6];
@@ -657,6 +690,7 @@ __device__ __forceinline__ void fv_cell(const StepArgs &a, uint32_t n, uint32_t 
             G[k][j] = 0.5f * (un[k][0][j] - un[k][1][j]);
     }
     if (solid && a.b.moving) {
+            const Bound bnd = bound_copy(a.b);
         // velocity gradient with the boundary velocity at solid face neighbours
         while (solid) {
             const int b = __builtin_ctz(solid);
@@ -664,9 +698,9 @@ __device__ __forceinline__ void fv_cell(const StepArgs &a, uint32_t n, uint32_t 
             const int k = b >> 1, s = (b & 1) ? -1 : 1;
             const uint32_t m = d.at_rt(n, s * (k == 0), s * (k == 1), s * (k == 2));
             int mx, my, mz;
-            coords(a.g, m, mx, my, mz);
+            coords(g, m, mx, my, mz);
             double ub[3];
-            boundary_velocity_d(a.g, a.b, mask[m], mx, my, mz, ub);
+            boundary_velocity_d(g, bnd, mask[m], mx, my, mz, ub);
             const float hs = 0.5f * s;
             for (int j = 0; j < 3; ++j) {
                 const float gj = hs * static_cast<float>(ub[j]);
@@ -717,18 +751,31 @@ __global__ __launch_bounds__(BLOCK) FV_OCCUPANCY void fv_step_kernel(StepArgs a)
 // launch advances every active solve by one step and the launches can be
 // captured once and replayed.
 
+// The tables are read through the constant address space: the block's solve
+// index is wave-uniform, so every table read is a scalar load and the plane
+// pointers of the solve land in SGPRs, as the kernel arguments of the
+// single-lattice kernels do (vector loads would put them in VGPRs and cost
+// the scalar-base addressing of every population access).
+#define VLB_CONST_AS __attribute__((address_space(4)))
+template <class X>
+__device__ __forceinline__ const VLB_CONST_AS X *uniform_ptr(const X *p)
+{
+    return (const VLB_CONST_AS X *)(uintptr_t)p;
+}
+
 template <bool SR>
 __global__ __launch_bounds__(BLOCK) void lb_batch_kernel(const BatchTable *__restrict__ t)
 {
-    const uint32_t b = blockIdx.x;
-    if (b >= t->total_blocks)
+    const VLB_CONST_AS BatchTable &tb = *uniform_ptr(t);
+    const uint32_t b = block_id(1, 0);  // one contiguous range of blocks per XCD
+    if (b >= tb.total_blocks)
         return;
-    const uint32_t s = t->block_solve[b];
-    const BatchSolve &bs = t->solves[s];
-    const uint32_t step = t->steps[s];
+    const uint32_t s = uniform_ptr(tb.block_solve)[b];
+    const VLB_CONST_AS BatchSolve &bs = uniform_ptr(tb.solves)[s];
+    const uint32_t step = uniform_ptr(tb.steps)[s];
     if (step >= bs.target)
         return;
-    const StepArgs &a = bs.args[step & 1u];
+    const VLB_CONST_AS StepArgs &a = bs.args[step & 1u];
     const uint32_t n = (b - bs.first_block) * BLOCK + threadIdx.x;
     if (n >= a.g.N)
         return;
@@ -738,15 +785,16 @@ __global__ __launch_bounds__(BLOCK) void lb_batch_kernel(const BatchTable *__res
 template <bool SR>
 __global__ __launch_bounds__(BLOCK) void fv_batch_kernel(const BatchTable *__restrict__ t)
 {
-    const uint32_t b = blockIdx.x;
-    if (b >= t->total_blocks)
+    const VLB_CONST_AS BatchTable &tb = *uniform_ptr(t);
+    const uint32_t b = block_id(1, 0);
+    if (b >= tb.total_blocks)
         return;
-    const uint32_t s = t->block_solve[b];
-    const BatchSolve &bs = t->solves[s];
-    const uint32_t step = t->steps[s];
+    const uint32_t s = uniform_ptr(tb.block_solve)[b];
+    const VLB_CONST_AS BatchSolve &bs = uniform_ptr(tb.solves)[s];
+    const uint32_t step = uniform_ptr(tb.steps)[s];
     if (step >= bs.target || !bs.args[0].polymer)
         return;
-    const StepArgs &a = bs.args[step & 1u];
+    const VLB_CONST_AS StepArgs &a = bs.args[step & 1u];
     const uint32_t n = (b - bs.first_block) * BLOCK + threadIdx.x;
     if (n >= a.g.N)
         return;
@@ -1541,7 +1589,8 @@ hipError_t launch_batch_step(const BatchTable *t, uint32_t max_blocks, int stoch
             hipLaunchKernelGGL(lb_batch_kernel<false>, dim3(max_blocks), dim3(BLOCK), 0, s, t);
             hipLaunchKernelGGL(fv_batch_kernel<false>, dim3(max_blocks), dim3(BLOCK), 0, s, t);
         }
-        hipLaunchKernelGGL(batch_advance_kernel, dim3(1), dim3(256), 0, s,
+        // block size differs from BLOCK so graph users can tell this node apart
+        hipLaunchKernelGGL(batch_advance_kernel, dim3(1), dim3(64), 0, s,
                            const_cast<BatchTable *>(t));
     }
     return hipGetLastError();

@@ -82,7 +82,7 @@ struct vlb_server {
     // device tables
     vlb::BatchTable *d_table = nullptr;
     vlb::BatchSolve *d_solves = nullptr;
-    uint16_t *d_block_solve = nullptr;
+    uint32_t *d_block_solve = nullptr;
     uint32_t *d_steps = nullptr;
     uint32_t table_capacity_blocks = 0;
     uint32_t total_blocks = 0;
@@ -91,6 +91,9 @@ struct vlb_server {
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     uint32_t graph_blocks = 0;
+    // kernel nodes whose grid follows the total block count
+    std::vector<hipGraphNode_t> grid_nodes;
+    std::vector<hipKernelNodeParams> grid_params;
     hipEvent_t done_event = nullptr;
     bool in_flight = false;
     int stochastic = 1;
@@ -245,7 +248,7 @@ vlb_status rebuild_tables(vlb_server *srv, const std::vector<uint32_t> &steps)
 {
     const uint32_t ns = static_cast<uint32_t>(srv->slots.size());
     std::vector<vlb::BatchSolve> solves(ns);
-    std::vector<uint16_t> block_solve;
+    std::vector<uint32_t> block_solve;
     uint32_t first = 0;
     for (uint32_t s = 0; s < ns; ++s) {
         const Slot &sl = srv->slots[s];
@@ -254,7 +257,7 @@ vlb_status rebuild_tables(vlb_server *srv, const std::vector<uint32_t> &steps)
         solves[s].first_block = first;
         solves[s].nblocks = sl.nblocks;
         solves[s].target = sl.target;
-        block_solve.insert(block_solve.end(), sl.nblocks, static_cast<uint16_t>(s));
+        block_solve.insert(block_solve.end(), sl.nblocks, static_cast<uint32_t>(s));
         first += sl.nblocks;
     }
     srv->total_blocks = first;
@@ -263,7 +266,7 @@ vlb_status rebuild_tables(vlb_server *srv, const std::vector<uint32_t> &steps)
             (void)hipFree(srv->d_block_solve);
         srv->d_block_solve = nullptr;
         const uint32_t cap = std::max<uint32_t>(first, 2 * srv->table_capacity_blocks);
-        SCHK(srv, hipMalloc(&srv->d_block_solve, cap * sizeof(uint16_t)), "block table");
+        SCHK(srv, hipMalloc(&srv->d_block_solve, cap * sizeof(uint32_t)), "block table");
         srv->table_capacity_blocks = cap;
     }
     vlb::BatchTable t{};
@@ -277,7 +280,7 @@ vlb_status rebuild_tables(vlb_server *srv, const std::vector<uint32_t> &steps)
                                  hipMemcpyHostToDevice, srv->stream),
              "solve table");
     if (first)
-        SCHK(srv, hipMemcpyAsync(srv->d_block_solve, block_solve.data(), first * sizeof(uint16_t),
+        SCHK(srv, hipMemcpyAsync(srv->d_block_solve, block_solve.data(), first * sizeof(uint32_t),
                                  hipMemcpyHostToDevice, srv->stream),
              "block table");
     if (ns)
@@ -295,12 +298,29 @@ vlb_status ensure_graph(vlb_server *srv)
 {
     if (srv->graph_exec && srv->graph_blocks == srv->total_blocks)
         return VLB_OK;
-    if (srv->graph_exec)
+    if (srv->graph_exec) {
+        // same work with a different grid: update the batched kernel nodes in
+        // place rather than capturing and instantiating again
+        bool ok = true;
+        for (size_t k = 0; k < srv->grid_nodes.size() && ok; ++k) {
+            hipKernelNodeParams p = srv->grid_params[k];
+            p.gridDim.x = srv->total_blocks;
+            ok = hipGraphExecKernelNodeSetParams(srv->graph_exec, srv->grid_nodes[k], &p) ==
+                 hipSuccess;
+            if (ok)
+                srv->grid_params[k] = p;
+        }
+        if (ok) {
+            srv->graph_blocks = srv->total_blocks;
+            srv->stats.graph_updates += 1;
+            return VLB_OK;
+        }
+        (void)hipGetLastError();
         (void)hipGraphExecDestroy(srv->graph_exec);
-    if (srv->graph)
         (void)hipGraphDestroy(srv->graph);
-    srv->graph_exec = nullptr;
-    srv->graph = nullptr;
+        srv->graph_exec = nullptr;
+        srv->graph = nullptr;
+    }
     SCHK(srv, hipStreamBeginCapture(srv->stream, hipStreamCaptureModeThreadLocal), "capture");
     hipError_t e = vlb::launch_batch_step(srv->d_table, srv->total_blocks, srv->stochastic,
                                           srv->k_steps, srv->stream);
@@ -310,6 +330,26 @@ vlb_status ensure_graph(vlb_server *srv)
     SCHK(srv, e2, "end capture");
     srv->graph = g;
     SCHK(srv, hipGraphInstantiate(&srv->graph_exec, g, nullptr, nullptr, 0), "instantiate");
+    // remember the per-cell kernel nodes (block size BLOCK; the counter
+    // advance runs with a different block size)
+    size_t count = 0;
+    SCHK(srv, hipGraphGetNodes(g, nullptr, &count), "graph nodes");
+    std::vector<hipGraphNode_t> nodes(count);
+    SCHK(srv, hipGraphGetNodes(g, nodes.data(), &count), "graph nodes");
+    srv->grid_nodes.clear();
+    srv->grid_params.clear();
+    for (hipGraphNode_t nd : nodes) {
+        hipGraphNodeType ty;
+        SCHK(srv, hipGraphNodeGetType(nd, &ty), "graph node type");
+        if (ty != hipGraphNodeTypeKernel)
+            continue;
+        hipKernelNodeParams p{};
+        SCHK(srv, hipGraphKernelNodeGetParams(nd, &p), "graph node params");
+        if (p.blockDim.x == static_cast<unsigned>(vlb::BLOCK)) {
+            srv->grid_nodes.push_back(nd);
+            srv->grid_params.push_back(p);
+        }
+    }
     srv->graph_blocks = srv->total_blocks;
     srv->stats.graph_captures += 1;
     return VLB_OK;

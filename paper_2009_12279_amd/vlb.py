@@ -54,6 +54,7 @@ class vlb_server_stats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
                 ("queued", ctypes.c_int64), ("running", ctypes.c_int64),
                 ("launches", ctypes.c_int64), ("graph_captures", ctypes.c_int64),
+                ("graph_updates", ctypes.c_int64),
                 ("bytes_in_use", ctypes.c_uint64), ("cell_steps_launched", ctypes.c_uint64)]
 
 
