@@ -43,6 +43,35 @@ def algorithmic_bytes(storage):
     }
 
 
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "step_256cubed_hbm_traffic.md")
+KERNEL_SOURCES = ("paper_2009_12279_amd/csrc/vlb_kernels.hip", "paper_2009_12279_amd/csrc/vlb_internal.h")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE / WRITE_SIZE scaled against a copy of known size), or
+    None when the kernel sources have changed since the counters were taken."""
+    import hashlib
+
+    try:
+        text = open(TRAFFIC_SUMMARY).read()
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    recorded, value = None, None
+    for line in text.splitlines():
+        if line.startswith("source_sha256:"):
+            recorded = line.split(":", 1)[1].strip()
+        if line.startswith(f"traffic_bytes_per_launch {kernel}:"):
+            value = float(line.split(":", 1)[1])
+    if recorded != h.hexdigest():
+        return None
+    return value
+
+
 def build_workload(storage, steps_hint=0):
     from paper_2009_12279_amd import inputs
 
@@ -256,7 +285,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--rounding", default=None, choices=[None, "nearest", "stochastic"])
-    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--cpu-steps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=48)
     ap.add_argument("--serving-steps-scale", type=float, default=0.1)
@@ -289,6 +318,10 @@ def main():
     if rank != 0:
         return
     dtype = "f64" if args.storage == "f32" else "f32"
+    # counters were taken for the default configuration only
+    traffic = None
+    if args.storage == "f32" and args.rounding in (None, "stochastic"):
+        traffic = measured_traffic(g["dominant"])
     line = {
         "metric": METRIC,
         "value": round(g["mlups"], 1),
@@ -322,7 +355,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(g["achieved"] / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": traffic,
         },
         "cpu_baseline": cpu,
         "serving": serving,
