@@ -172,8 +172,10 @@ vlb_status vlb_read_wall_force(vlb_lattice *lat, double force[3]);
 vlb_status vlb_check_health(vlb_lattice *lat, double *max_speed, int64_t *non_finite);
 vlb_status vlb_set_check_interval(vlb_lattice *lat, int64_t steps);
 
-/* Checkpoint: parameters, mask, walls, particles, step count and the state in
- * its storage precision.  vlb_load creates a new lattice. */
+/* Checkpoint: parameters, mask, walls, particles, step count, rounding mode
+ * and seed, and the state in its storage precision, so that a restarted run
+ * continues bit for bit.  vlb_load creates a new lattice (VLB_EINVAL for a
+ * file that is not a checkpoint of this format). */
 vlb_status vlb_save(vlb_lattice *lat, const char *path);
 vlb_status vlb_load(const char *path, void *stream, vlb_lattice **out);
 

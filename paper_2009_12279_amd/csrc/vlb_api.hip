@@ -907,7 +907,7 @@ vlb_status vlb_set_check_interval(vlb_lattice *lat, int64_t steps)
 // checkpoint
 
 namespace {
-constexpr uint64_t kMagic = 0x31304B434C424C56ull;  // "VLBLCK01"
+constexpr uint64_t kMagic = 0x32304B434C424C56ull;  // "VLBLCK02"
 
 struct FileHeader {
     uint64_t magic;
@@ -917,6 +917,8 @@ struct FileHeader {
     vlb_params params;
     float scale;
     int32_t any_movable;
+    int32_t rounding;  // vlb_rounding of stored values
+    uint32_t seed;     // seed of the stochastic-rounding stream
 };
 }  // namespace
 
@@ -969,6 +971,8 @@ vlb_status vlb_save(vlb_lattice *lat, const char *path)
     h.params = lat->params;
     h.scale = lat->scale;
     h.any_movable = lat->any_movable;
+    h.rounding = lat->rounding;
+    h.seed = lat->seed;
     bool ok = std::fwrite(&h, sizeof h, 1, fp) == 1;
     ok = ok && std::fwrite(lat->wall_h.data(), sizeof(double), 64 * 3, fp) == 64 * 3;
     ok = ok && (parts.empty() || std::fwrite(parts.data(), sizeof(Particle), parts.size(), fp) ==
@@ -1045,6 +1049,8 @@ vlb_status vlb_load(const char *path, void *stream, vlb_lattice **out)
     lat->parts_h = parts;
     lat->any_movable = h.any_movable != 0;
     lat->step = h.step;
+    lat->rounding = h.rounding == VLB_ROUND_NEAREST ? VLB_ROUND_NEAREST : VLB_ROUND_STOCHASTIC;
+    lat->seed = h.seed;
     lat->scale = h.scale;
     lat->inv_scale = 1.f / h.scale;
     hipError_t e = hipMemcpyAsync(lat->d_mask, mask.data(), N, hipMemcpyHostToDevice, lat->stream);

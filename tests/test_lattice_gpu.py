@@ -1,0 +1,111 @@
+"""The lattice handle on the GPU: the health check (speed limit, sticky
+instability, reads still allowed), checkpoint restart bit for bit in every
+storage precision and with a moving particle, and device-side error paths."""
+import numpy as np
+import pytest
+
+from paper_2009_12279_amd import inputs, vlb
+from parity import log
+
+pytestmark = pytest.mark.gpu
+
+
+def test_health_check_flags_excess_speed_and_is_sticky():
+    shape = (8, 12, 6)
+    nx, ny, nz = shape
+    mask = inputs.channel_mask(shape, wall_axes=(1,))
+    L = vlb.Lattice(shape, mask, (1, 0, 1))
+    L.set_params(eta=1 / 3, beta=0.5, lambda_p=50.0)
+    u = np.zeros((3, nz, ny, nx))
+    u[0, 3, 5, 4] = 0.35
+    L.init_equilibrium(u)
+    log("[lattice] health check on a state above the speed limit")
+    st, speed, bad = vlb.vlb_check_health(L.handle, raise_on_unstable=False)
+    assert st == vlb.VLB_EUNSTABLE and speed == pytest.approx(0.35, rel=1e-6) and bad == 0
+    with pytest.raises(vlb.VlbError) as ei:
+        L.step(1)
+    assert ei.value.status == vlb.VLB_EUNSTABLE
+    assert L.step_count == 0
+    assert np.isfinite(L.velocity()).all()
+    L.close()
+
+
+def test_periodic_check_inside_step_stops_the_run():
+    """A uniform flow above the limit stays uniform; with a check every step
+    the run stops after the first step and reports the sticky state."""
+    shape = (8, 8, 8)
+    L = vlb.Lattice(shape, None, (1, 1, 1))
+    L.set_params(eta=1 / 3, beta=0.0, lambda_p=1.0)
+    u = np.zeros((3, 8, 8, 8))
+    u[0] = 0.35
+    L.init_equilibrium(u)
+    L.set_check_interval(1)
+    log("[lattice] check interval 1, uniform u = 0.35")
+    with pytest.raises(vlb.VlbError) as ei:
+        L.step(5)
+    assert ei.value.status == vlb.VLB_EUNSTABLE
+    L.sync()
+    assert L.step_count == 1
+    np.testing.assert_allclose(L.velocity()[0], 0.35, rtol=1e-6)
+    L.close()
+
+
+def _duct_with_moving_sphere(storage):
+    shape = (20, 18, 26)
+    mask = inputs.channel_mask(shape, wall_axes=(0, 1, 2))
+    L = vlb.Lattice(shape, mask, (0, 0, 0), storage=storage)
+    L.set_params(eta=1 / 6, beta=0.5, lambda_p=40.0, magic=3 / 16, body_force=(2e-6, 0, 0))
+    L.add_sphere(center=(9.5, 8.7, 13.2), radius=3.4, density_ratio=1.5, movable=True,
+                 f_ext=(8e-3, 0.0, -2e-2))
+    L.set_check_interval(0)
+    L.init_equilibrium()
+    return L
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+def test_checkpoint_restart_is_bitwise(tmp_path, storage):
+    path = str(tmp_path / f"ck_{storage}.vlb")
+    log(f"[lattice] checkpoint restart storage={storage}")
+    L = _duct_with_moving_sphere(storage)
+    L.set_rounding("stochastic", 77)
+    L.step(100)
+    L.save(path)
+    m_saved = L.mask()
+    L.step(200)
+    ref = (L.populations(), L.stress(), L.mask(), L.particle(0), L.step_count)
+    L.close()
+    R = vlb.Lattice.load(path, (20, 18, 26))
+    assert R.step_count == 100
+    R.step(200)
+    got = (R.populations(), R.stress(), R.mask(), R.particle(0), R.step_count)
+    R.close()
+    np.testing.assert_array_equal(got[0], ref[0])
+    np.testing.assert_array_equal(got[1], ref[1])
+    np.testing.assert_array_equal(got[2], ref[2])
+    for k in ("pos", "vel", "omega", "force", "torque"):
+        np.testing.assert_array_equal(got[3][k], ref[3][k])
+    assert got[4] == ref[4] == 300
+    # the sphere converted cells after the checkpoint
+    assert not np.array_equal(got[2], m_saved)
+
+
+def test_load_rejects_a_file_that_is_not_a_checkpoint(tmp_path):
+    p = tmp_path / "junk.vlb"
+    p.write_bytes(b"not a checkpoint" * 8)
+    with pytest.raises(vlb.VlbError) as ei:
+        vlb.Lattice.load(str(p), (4, 4, 4))
+    assert ei.value.status == vlb.VLB_EINVAL
+
+
+def test_stepping_an_unset_lattice_and_bad_particle_ids():
+    L = vlb.Lattice((6, 6, 6), None, (1, 1, 1))
+    L.set_params(eta=1 / 3)
+    L.init_equilibrium()
+    with pytest.raises(vlb.VlbError) as ei:
+        L.particle(3)
+    assert ei.value.status in (vlb.VLB_EINVAL, vlb.VLB_ENOTFOUND)
+    with pytest.raises(vlb.VlbError):
+        L.step(-1)
+    L.step(2)
+    assert L.step_count == 2
+    L.close()
