@@ -57,6 +57,24 @@ int remap_blocks(const vlb::Geom &g, uint32_t &slab_blocks)
     return mode;
 }
 
+// Stress-update kernel: tiled (64 x 4 tiles marching through 16 planes)
+// where the lattice is large enough, per-cell otherwise.  VLB_FV_TILE
+// overrides it (0 = per-cell kernel, 4 or 8 = rows per tile, negative = that
+// many rows whatever the lattice size) and VLB_FV_ZC sets the planes per
+// chunk; both are read at every step.
+int fv_tile_rows()
+{
+    const char *e = std::getenv("VLB_FV_TILE");
+    return e ? std::atoi(e) : 4;
+}
+
+uint32_t fv_z_chunk()
+{
+    const char *e = std::getenv("VLB_FV_ZC");
+    const long v = e ? std::atol(e) : 16;
+    return static_cast<uint32_t>(v > 0 && v < 65536 ? v : 16);
+}
+
 size_t storage_bytes(int storage) { return storage == vlb::ST_F32 ? 4 : 2; }
 
 float default_scale(int storage) { return storage == vlb::ST_F16 ? 1024.f : 1.f; }
@@ -658,7 +676,8 @@ vlb_status vlb_step(vlb_lattice *lat, int64_t n_steps)
         if (ev)
             HIPCHK(lat, hipEventRecord(ev[1], lat->stream), "event");
         if (lat->polymer)
-            HIPCHK(lat, vlb::launch_fv_step(lat->storage, a, lat->stream), "stress update launch");
+            HIPCHK(lat, vlb::launch_fv_step(lat->storage, a, lat->stream, fv_tile_rows(), fv_z_chunk()),
+                   "stress update launch");
         if (ev)
             HIPCHK(lat, hipEventRecord(ev[2], lat->stream), "event");
         if (lat->any_movable) {

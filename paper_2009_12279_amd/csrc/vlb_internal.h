@@ -116,7 +116,12 @@ hipError_t launch_lb_step(int storage, const StepArgs &a, hipStream_t s);
 // step) over every solve of the table; grid of max_blocks blocks.
 hipError_t launch_batch_step(const BatchTable *t, uint32_t max_blocks, int stochastic, int n_steps,
                              hipStream_t s);
-hipError_t launch_fv_step(int storage, const StepArgs &a, hipStream_t s);
+// tile_rows 4 or 8 selects the tiled kernel (64 x tile_rows tiles marching
+// through z_chunk planes, 0 = 16) where the lattice is large enough for it,
+// -4 or -8 the tiled kernel for any lattice; anything else the per-cell
+// kernel.
+hipError_t launch_fv_step(int storage, const StepArgs &a, hipStream_t s, int tile_rows,
+                          uint32_t z_chunk);
 hipError_t launch_init_equilibrium(int storage, const Geom &g, const uint8_t *mask,
                                    const double *u, void *f, float scale, hipStream_t s);
 hipError_t launch_set_populations(int storage, const Geom &g, const uint8_t *mask,

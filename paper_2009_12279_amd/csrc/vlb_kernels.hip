@@ -631,39 +631,17 @@ __device__ __forceinline__ float face_overlap(const float u[3], int k, int s)
     return ue * (1.f - fabsf(u[a1])) * (1.f - fabsf(u[a2]));
 }
 
+// Stress update of fluid cell n at (x, y, z) from its own velocity and stress
+// (u0, t0) and those of its six face neighbours (un, tn: [axis k][side], side 0
+// along +e_k, side 1 along -e_k), `solid` holding bit 2k+side for each solid
+// face neighbour.  Shared by the per-cell and the tiled kernels, so both give
+// the same bits.
 template <bool SR, class A>
-__device__ __forceinline__ void fv_cell(const A &a, uint32_t n, uint32_t step)
+__device__ __forceinline__ void fv_compute(const A &a, const Geom &g, uint32_t n, int x, int y, int z,
+                                           uint32_t step, const float u0[3], const float t0[6],
+                                           float un[3][2][3], const float tn[3][2][6],
+                                           uint32_t solid)
 {
-    const Geom g = geom_copy(a.g);
-    const uint8_t *__restrict__ mask = a.mask;
-    int x, y, z;
-    coords(g, n, x, y, z);
-    const Delta d(g, x, y, z);
-    // all loads first (in bounds for every cell), selection afterwards
-    const float u0[3] = {*elem(a.u_p[0], n), *elem(a.u_p[1], n), *elem(a.u_p[2], n)};
-    float t0[6];
-#pragma unroll
-    for (int c = 0; c < 6; ++c)
-        t0[c] = *elem(a.tin_p[c], n);
-    float un[3][2][3], tn[3][2][6];
-    uint32_t solid = 0;  // bit 2k+side: face neighbour along +/- e_k is solid
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-#pragma unroll
-        for (int side = 0; side < 2; ++side) {
-            const int s = side == 0 ? 1 : -1;
-            const uint32_t m = d.at(n, s * (k == 0), s * (k == 1), s * (k == 2));
-            solid |= (mask[m] != 0 ? 1u : 0u) << (2 * k + side);
-#pragma unroll
-            for (int j = 0; j < 3; ++j)
-                un[k][side][j] = *elem(a.u_p[j], m);
-#pragma unroll
-            for (int c = 0; c < 6; ++c)
-                tn[k][side][c] = *elem(a.tin_p[c], m);
-        }
-    if (mask[n] != 0)
-        return;
-
     float G[3][3];
     float in_sum[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     float out_tot = 0.f;
@@ -690,7 +668,8 @@ __device__ __forceinline__ void fv_cell(const A &a, uint32_t n, uint32_t step)
             G[k][j] = 0.5f * (un[k][0][j] - un[k][1][j]);
     }
     if (solid && a.b.moving) {
-            const Bound bnd = bound_copy(a.b);
+        const Bound bnd = bound_copy(a.b);
+        const Delta d(g, x, y, z);
         // velocity gradient with the boundary velocity at solid face neighbours
         while (solid) {
             const int b = __builtin_ctz(solid);
@@ -700,7 +679,7 @@ __device__ __forceinline__ void fv_cell(const A &a, uint32_t n, uint32_t step)
             int mx, my, mz;
             coords(g, m, mx, my, mz);
             double ub[3];
-            boundary_velocity_d(g, bnd, mask[m], mx, my, mz, ub);
+            boundary_velocity_d(g, bnd, a.mask[m], mx, my, mz, ub);
             const float hs = 0.5f * s;
             for (int j = 0; j < 3; ++j) {
                 const float gj = hs * static_cast<float>(ub[j]);
@@ -735,6 +714,42 @@ __device__ __forceinline__ void fv_cell(const A &a, uint32_t n, uint32_t step)
     }
 }
 
+// Per-cell stress update: every neighbour value is loaded from memory.
+template <bool SR, class A>
+__device__ __forceinline__ void fv_cell(const A &a, uint32_t n, uint32_t step)
+{
+    const Geom g = geom_copy(a.g);
+    const uint8_t *__restrict__ mask = a.mask;
+    int x, y, z;
+    coords(g, n, x, y, z);
+    const Delta d(g, x, y, z);
+    // all loads first (in bounds for every cell), selection afterwards
+    const float u0[3] = {*elem(a.u_p[0], n), *elem(a.u_p[1], n), *elem(a.u_p[2], n)};
+    float t0[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c)
+        t0[c] = *elem(a.tin_p[c], n);
+    float un[3][2][3], tn[3][2][6];
+    uint32_t solid = 0;  // bit 2k+side: face neighbour along +/- e_k is solid
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const int s = side == 0 ? 1 : -1;
+            const uint32_t m = d.at(n, s * (k == 0), s * (k == 1), s * (k == 2));
+            solid |= (mask[m] != 0 ? 1u : 0u) << (2 * k + side);
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                un[k][side][j] = *elem(a.u_p[j], m);
+#pragma unroll
+            for (int c = 0; c < 6; ++c)
+                tn[k][side][c] = *elem(a.tin_p[c], m);
+        }
+    if (mask[n] != 0)
+        return;
+    fv_compute<SR>(a, g, n, x, y, z, step, u0, t0, un, tn, solid);
+}
+
 template <bool SR>
 __global__ __launch_bounds__(BLOCK) FV_OCCUPANCY void fv_step_kernel(StepArgs a)
 {
@@ -742,6 +757,157 @@ __global__ __launch_bounds__(BLOCK) FV_OCCUPANCY void fv_step_kernel(StepArgs a)
     if (n >= a.g.N)
         return;
     fv_cell<SR>(a, n, a.step);
+}
+
+// ---------------------------------------------------------------------------
+// Tiled stress update.  A block owns an FV_TX x TY tile of the x-y plane and
+// marches through a chunk of z-planes.  The velocity, stress and solid flag
+// of the thread's own column ride along in registers for planes z-1, z and
+// z+1 (the z neighbours); plane z of the tile plus a one-cell ring is staged
+// in LDS for the x and y neighbours.  Every slot holds the cell at the
+// periodically wrapped coordinates, as the per-cell kernel's index deltas do.
+// Per cell a thread issues its own 10 loads, plus one ring cell for about
+// half of the threads, instead of the per-cell kernel's 70.
+
+constexpr int FV_TX = 64;
+constexpr int FV_NV = 10;  // u (3), tau (6), solid flag
+
+__device__ __forceinline__ int wrap_coord(int v, int n)
+{
+    const int r = v % n;
+    return r < 0 ? r + n : r;
+}
+
+__device__ __forceinline__ void fv_load(const StepArgs &a, uint32_t idx, float v[FV_NV])
+{
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+        v[j] = *elem(a.u_p[j], idx);
+#pragma unroll
+    for (int c = 0; c < 6; ++c)
+        v[3 + c] = *elem(a.tin_p[c], idx);
+    v[9] = a.mask[idx] != 0 ? 1.f : 0.f;
+}
+
+template <bool SR, int TY>
+__global__ __launch_bounds__(FV_TX * TY) void fv_tile_kernel(StepArgs a, uint32_t zc)
+{
+    static_assert(FV_TX * TY >= 2 * FV_TX + 2 * TY, "ring larger than the block");
+    constexpr int W = FV_TX + 2, S = W * (TY + 2);
+    __shared__ float lds[2][FV_NV][S];
+    const Geom g = a.g;
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const uint32_t nxy = static_cast<uint32_t>(nx) * ny;
+    const uint32_t tiles_x = (nx + FV_TX - 1) / FV_TX, tiles_y = (ny + TY - 1) / TY;
+    // block -> (x tile, y tile, z chunk); with the XCD-aware order each of the
+    // 8 XCDs takes a slab of y tiles of every chunk, so ring rows and chunk
+    // boundary planes are read through its own L2
+    uint32_t tx, ty, cz;
+    const uint32_t b = blockIdx.x;
+    if (a.remap && (tiles_y & 7u) == 0) {
+        const uint32_t y8 = tiles_y >> 3, k = b & 7u, q = b >> 3, per = tiles_x * y8;
+        cz = q / per;
+        const uint32_t r = q - cz * per;
+        ty = k * y8 + r / tiles_x;
+        tx = r % tiles_x;
+    } else {
+        tx = b % tiles_x;
+        const uint32_t t = b / tiles_x;
+        ty = t % tiles_y;
+        cz = t / tiles_y;
+    }
+    const int tid = threadIdx.x, lx = tid % FV_TX, ly = tid / FV_TX;
+    const int x = static_cast<int>(tx) * FV_TX + lx, y = static_cast<int>(ty) * TY + ly;
+    const bool in_tile = x < nx && y < ny;
+    const uint32_t own_xy = wrap_coord(x, nx) + static_cast<uint32_t>(nx) * wrap_coord(y, ny);
+    const int own_slot = (ly + 1) * W + lx + 1;
+    // ring cell loaded by this thread, if any
+    int hslot = -1;
+    uint32_t halo_xy = 0;
+    if (tid < 2 * FV_TX) {
+        const int top = tid >= FV_TX, hx = static_cast<int>(tx) * FV_TX + (tid % FV_TX);
+        const int hy = top ? static_cast<int>(ty) * TY + TY : static_cast<int>(ty) * TY - 1;
+        hslot = (top ? TY + 1 : 0) * W + (tid % FV_TX) + 1;
+        halo_xy = wrap_coord(hx, nx) + static_cast<uint32_t>(nx) * wrap_coord(hy, ny);
+    } else if (tid < 2 * FV_TX + 2 * TY) {
+        const int j = tid - 2 * FV_TX, right = j >= TY, r = j % TY;
+        const int hx = right ? static_cast<int>(tx) * FV_TX + FV_TX : static_cast<int>(tx) * FV_TX - 1;
+        const int hy = static_cast<int>(ty) * TY + r;
+        hslot = (r + 1) * W + (right ? W - 1 : 0);
+        halo_xy = wrap_coord(hx, nx) + static_cast<uint32_t>(nx) * wrap_coord(hy, ny);
+    }
+    const int z0 = static_cast<int>(cz * zc);
+    const int z1 = min(z0 + static_cast<int>(zc), nz);
+    // own column at z-1, z, z+1 and the ring cell at z
+    float P[FV_NV], C[FV_NV], N[FV_NV], HV[FV_NV];
+    fv_load(a, own_xy + wrap_coord(z0 - 1, nz) * nxy, P);
+    fv_load(a, own_xy + static_cast<uint32_t>(z0) * nxy, C);
+    fv_load(a, own_xy + wrap_coord(z0 + 1, nz) * nxy, N);
+    if (hslot >= 0)
+        fv_load(a, halo_xy + static_cast<uint32_t>(z0) * nxy, HV);
+    for (int z = z0; z < z1; ++z) {
+        const int buf = (z - z0) & 1;
+#pragma unroll
+        for (int v = 0; v < FV_NV; ++v)
+            lds[buf][v][own_slot] = C[v];
+        if (hslot >= 0) {
+#pragma unroll
+            for (int v = 0; v < FV_NV; ++v)
+                lds[buf][v][hslot] = HV[v];
+        }
+        // the column at z+2 is in flight while this plane is computed
+        const bool more = z + 1 < z1;
+        float NN[FV_NV];
+        if (more)
+            fv_load(a, own_xy + wrap_coord(z + 2, nz) * nxy, NN);
+        __syncthreads();
+        if (in_tile && C[9] == 0.f) {
+            const float u0[3] = {C[0], C[1], C[2]};
+            const float t0[6] = {C[3], C[4], C[5], C[6], C[7], C[8]};
+            float un[3][2][3], tn[3][2][6];
+            uint32_t solid = 0;
+            const int sl[2][2] = {{own_slot + 1, own_slot - 1}, {own_slot + W, own_slot - W}};
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+#pragma unroll
+                for (int side = 0; side < 2; ++side) {
+                    const int q = sl[k][side];
+#pragma unroll
+                    for (int j = 0; j < 3; ++j)
+                        un[k][side][j] = lds[buf][j][q];
+#pragma unroll
+                    for (int c = 0; c < 6; ++c)
+                        tn[k][side][c] = lds[buf][3 + c][q];
+                    solid |= (lds[buf][9][q] != 0.f ? 1u : 0u) << (2 * k + side);
+                }
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                un[2][0][j] = N[j];
+                un[2][1][j] = P[j];
+            }
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                tn[2][0][c] = N[3 + c];
+                tn[2][1][c] = P[3 + c];
+            }
+            solid |= (N[9] != 0.f ? 1u : 0u) << 4;
+            solid |= (P[9] != 0.f ? 1u : 0u) << 5;
+            const uint32_t n = own_xy + static_cast<uint32_t>(z) * nxy;
+            fv_compute<SR>(a, g, n, x, y, z, a.step, u0, t0, un, tn, solid);
+        }
+        if (more) {
+#pragma unroll
+            for (int v = 0; v < FV_NV; ++v) {
+                P[v] = C[v];
+                C[v] = N[v];
+                N[v] = NN[v];
+            }
+            // the ring cell of the next plane (LDS buffer buf^1 is free: every
+            // thread has passed this plane's barrier)
+            if (hslot >= 0)
+                fv_load(a, halo_xy + static_cast<uint32_t>(z + 1) * nxy, HV);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1568,9 +1734,39 @@ hipError_t launch_lb_step(int storage, const StepArgs &a, hipStream_t s)
     });
 }
 
-hipError_t launch_fv_step(int storage, const StepArgs &a, hipStream_t s)
+hipError_t launch_fv_step(int storage, const StepArgs &a, hipStream_t s, int tile_rows,
+                          uint32_t z_chunk)
 {
     (void)storage;
+    // The tiled kernel needs x rows that fill its 64-wide tiles and enough
+    // blocks to fill the chip (chunks are shortened down to 4 planes for
+    // that); small lattices take the per-cell kernel unless the tiled one is
+    // forced (negative tile_rows).
+    const bool force = tile_rows < 0;
+    if (force)
+        tile_rows = -tile_rows;
+    const uint32_t rows = tile_rows > 0 ? static_cast<uint32_t>(tile_rows) : 1u;
+    const uint32_t tiles_xy = ((a.g.nx + FV_TX - 1) / FV_TX) * ((a.g.ny + rows - 1) / rows);
+    uint32_t zc = z_chunk ? z_chunk : 16u;
+    while (!force && zc > 4 && tiles_xy * ((a.g.nz + zc - 1) / zc) < 2048)
+        zc /= 2;
+    const bool rows_fill = a.g.nx % FV_TX == 0 || a.g.nx >= 4 * FV_TX;
+    if ((tile_rows == 4 || tile_rows == 8) &&
+        (force || (rows_fill && tiles_xy * ((a.g.nz + zc - 1) / zc) >= 1024))) {
+        const uint32_t tiles = tiles_xy * ((a.g.nz + zc - 1) / zc);
+        if (tile_rows == 4) {
+            if (a.stochastic)
+                hipLaunchKernelGGL((fv_tile_kernel<true, 4>), dim3(tiles), dim3(FV_TX * 4), 0, s, a, zc);
+            else
+                hipLaunchKernelGGL((fv_tile_kernel<false, 4>), dim3(tiles), dim3(FV_TX * 4), 0, s, a, zc);
+        } else {
+            if (a.stochastic)
+                hipLaunchKernelGGL((fv_tile_kernel<true, 8>), dim3(tiles), dim3(FV_TX * 8), 0, s, a, zc);
+            else
+                hipLaunchKernelGGL((fv_tile_kernel<false, 8>), dim3(tiles), dim3(FV_TX * 8), 0, s, a, zc);
+        }
+        return hipGetLastError();
+    }
     if (a.stochastic)
         hipLaunchKernelGGL(fv_step_kernel<true>, dim3(blocks_for(a.g.N)), dim3(BLOCK), 0, s, a);
     else
