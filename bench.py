@@ -137,6 +137,52 @@ def run_gpu(args):
                 step_achieved=step_achieved, alg=alg, health=health)
 
 
+def run_moving(args):
+    """The settling-sphere box (64x64x256, walls on every axis, one movable
+    sphere r = 6 of density ratio 1.5 under an external force -0.004 along z,
+    beta = 0.5, Wi = 1): the step with momentum exchange, the rigid-body
+    update and the fluid/solid conversion running every step."""
+    import torch
+
+    from paper_2009_12279_amd import inputs, vlb
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream(0)
+    shape = (64, 64, 256)
+    eta, r, F = 1.0 / 3.0, 6.0, 0.004
+    lam = r / (F / (6 * np.pi * eta * r))
+    mask = inputs.channel_mask(shape, wall_axes=(0, 1, 2))
+    lat = vlb.Lattice(shape, mask, (0, 0, 0), stream=stream.cuda_stream)
+    lat.set_params(eta=eta, beta=0.5, lambda_p=lam, magic=3.0 / 16.0)
+    lat.add_sphere(center=(31.5, 31.5, 191.5), radius=r, density_ratio=1.5, movable=True,
+                   f_ext=(0.0, 0.0, -F))
+    lat.set_check_interval(0)
+    lat.init_equilibrium()
+    lat.step(args.warmup)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    lat.step(args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    lat.set_timing(True)
+    lat.step(args.steps)
+    torch.cuda.synchronize()
+    k_ms = {"stream_collide": lat.kernel_time_ms(0), "stress_update": lat.kernel_time_ms(1),
+            "particles": lat.kernel_time_ms(2)}
+    lat.set_timing(False)
+    p = lat.particle(0)
+    lat.close()
+    N = int(np.prod(shape))
+    return dict(workload="settling sphere: 64x64x256 closed box, movable sphere r=6, density "
+                         "ratio 1.5, F_z=-0.004, beta=0.5, Wi=1 (lambda_p=%.0f)" % lam,
+                steps=args.steps, ms_per_step=round(ms, 4), mlups=round(N / (ms * 1e-3) / 1e6, 1),
+                kernel_ms={k: round(v, 5) for k, v in k_ms.items()},
+                sphere_z=round(float(p["pos"][2]), 4), sphere_vz=float(p["vel"][2]))
+
+
 def run_cpu_baseline(args):
     import oracle
 
@@ -293,6 +339,8 @@ def main():
     ap.add_argument("--serving-slots", type=int, default=64)
     ap.add_argument("--serving-k", type=int, default=50)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-moving", action="store_true",
+                    help="skip the settling-sphere (moving boundary) measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (torch) so that hardware byte "
                          "counters can be scaled against a kernel of known traffic")
@@ -311,6 +359,7 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    moving = None if args.no_moving else run_moving(args)
     serving = None if args.no_serving else run_serving(args)
     cpu = None
     if rank == 0 and not args.no_cpu_baseline:
@@ -358,6 +407,7 @@ def main():
             "traffic": traffic,
         },
         "cpu_baseline": cpu,
+        "moving_particle": moving,
         "serving": serving,
     }
     print(json.dumps(line), flush=True)

@@ -198,16 +198,19 @@ double vlb_kernel_time_ms(const vlb_lattice *lat, int32_t which);
 /* ------------------------------------------------------------------------
  * Serving: continuous batching of independent solves (FP32 storage).
  *
- * A server owns a FIFO queue of requests and a set of slots.  vlb_server_pump
- * retires finished solves (their velocity and stress are copied to the host
- * and their device memory freed), admits queued requests in order while a
- * slot is free and the request's device footprint fits the HBM budget, and
- * launches steps_per_launch batched steps that advance every admitted solve
- * together (a replayed hipGraph).  Requests submitted while others run join
- * at the next pump.  Each solve computes exactly what a lone vlb_lattice with
- * the same mask, parameters and rounding seed computes: results do not
- * depend on what else is in the batch.  Walls in a request mask are at rest;
- * moving particles are not served.
+ * A server owns a FIFO queue of requests, a set of slots and an arena: one
+ * device allocation of the whole HBM budget, made at creation, from which
+ * admitted solves take their buffers.  vlb_server_pump retires finished
+ * solves (their velocity and stress are copied to the host), admits queued
+ * requests in order while a slot is free and the request's footprint fits
+ * in the budget and in a free range of the arena, and issues replays of
+ * steps_per_launch batched steps that advance every admitted solve together
+ * (a replayed hipGraph), keeping up to two replays in flight so that the
+ * host's retire/admit work overlaps the GPU's.  Requests submitted while
+ * others run join at the next pump.  Each solve computes exactly what a lone
+ * vlb_lattice with the same mask, parameters and rounding seed computes:
+ * results do not depend on what else is in the batch.  Walls in a request
+ * mask are at rest; moving particles are not served.
  */
 typedef enum vlb_request_state {
     VLB_REQ_QUEUED = 0,
@@ -234,9 +237,11 @@ typedef struct vlb_server_stats {
 
 typedef struct vlb_server vlb_server;
 
-/* hbm_budget_bytes bounds the summed footprint of admitted solves;
- * max_slots bounds their number (<= 4096); steps_per_launch is the number
- * of batched steps per pump (1..4096).  stream as for vlb_create. */
+/* hbm_budget_bytes bounds the summed footprint of admitted solves and is
+ * allocated at once (VLB_ENOMEM if the device cannot hold it); max_slots
+ * bounds their number (<= 4096); steps_per_launch is the number of batched
+ * steps per replay (1..4096).  stream as for vlb_create (the server adds two
+ * streams of its own for uploads, result reads and graph capture). */
 vlb_status vlb_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t steps_per_launch,
                              void *stream, vlb_server **out);
 /* Device bytes a request of these dimensions holds while admitted. */
@@ -246,8 +251,9 @@ vlb_status vlb_server_set_rounding(vlb_server *srv, vlb_rounding mode);
 /* Queue a request (inputs copied).  VLB_EBUSY if it can never fit the budget,
  * VLB_EINVAL for invalid dimensions, mask or parameters. */
 vlb_status vlb_server_submit(vlb_server *srv, const vlb_request *req, uint64_t *ticket);
-/* One scheduling round (retire, admit, launch).  wait = 0 returns at once if
- * the previous launch is still running; wait = 1 waits for it. */
+/* One scheduling round: retire, admit, and top up to two replays in flight.
+ * wait = 0 returns at once when two replays are in flight; wait = 1 first
+ * waits for the oldest replay unless one has completed since the last call. */
 vlb_status vlb_server_pump(vlb_server *srv, int32_t wait);
 vlb_status vlb_server_poll(vlb_server *srv, uint64_t ticket, int32_t *state);
 /* Copy the result of a finished request (u: 3*N, tau: 6*N doubles, either

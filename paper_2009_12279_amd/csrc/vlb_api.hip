@@ -557,7 +557,9 @@ vlb_status vlb_add_sphere(vlb_lattice *lat, const double center[3], double radiu
 {
     if (!lat)
         return VLB_EINVAL;
-    if (!center || !(radius > 0.0) || !(density_ratio > 0.0))
+    if (!center || !std::isfinite(center[0]) || !std::isfinite(center[1]) ||
+        !std::isfinite(center[2]) || !(radius > 0.0) || !std::isfinite(radius) ||
+        !(density_ratio > 0.0))
         return fail(lat, VLB_EINVAL, "vlb_add_sphere: invalid centre, radius or density");
     if (lat->parts_h.size() >= static_cast<size_t>(vlb::MAX_PARTICLES))
         return fail(lat, VLB_EINVAL, "vlb_add_sphere: particle table full");
@@ -581,13 +583,29 @@ vlb_status vlb_add_sphere(vlb_lattice *lat, const double center[3], double radiu
     P.movable = movable ? 1 : 0;
     const int id = static_cast<int>(cur.size());
     const int n[3] = {lat->g.nx, lat->g.ny, lat->g.nz};
+    // cells with |x - R|^2 < r^2, searched over the sphere's bounding box
+    // (wrapped on periodic axes; the whole axis once if the box covers it)
+    int lo[3], hi[3];
+    for (int k = 0; k < 3; ++k) {
+        lo[k] = static_cast<int>(std::floor(P.R[k] - radius)) - 1;
+        hi[k] = static_cast<int>(std::ceil(P.R[k] + radius)) + 1;
+        if (!lat->g.per[k]) {
+            lo[k] = std::max(lo[k], 0);
+            hi[k] = std::min(hi[k], n[k] - 1);
+        } else if (hi[k] - lo[k] + 1 >= n[k]) {
+            lo[k] = 0;
+            hi[k] = n[k] - 1;
+        }
+    }
     std::vector<uint32_t> cells;
-    for (int z = 0; z < n[2]; ++z)
-        for (int y = 0; y < n[1]; ++y)
-            for (int x = 0; x < n[0]; ++x) {
-                const int c[3] = {x, y, z};
+    for (int zz = lo[2]; zz <= hi[2]; ++zz)
+        for (int yy = lo[1]; yy <= hi[1]; ++yy)
+            for (int xx = lo[0]; xx <= hi[0]; ++xx) {
+                const int raw[3] = {xx, yy, zz};
+                int c[3];
                 double d[3];
                 for (int k = 0; k < 3; ++k) {
+                    c[k] = ((raw[k] % n[k]) + n[k]) % n[k];
                     d[k] = static_cast<double>(c[k]) - P.R[k];
                     if (lat->g.per[k]) {
                         const double L = static_cast<double>(n[k]);
@@ -595,7 +613,8 @@ vlb_status vlb_add_sphere(vlb_lattice *lat, const double center[3], double radiu
                     }
                 }
                 if (sq_norm(d) < radius * radius) {
-                    const uint32_t idx = x + static_cast<uint32_t>(n[0]) * (y + static_cast<uint32_t>(n[1]) * z);
+                    const uint32_t idx = c[0] + static_cast<uint32_t>(n[0]) *
+                                                    (c[1] + static_cast<uint32_t>(n[1]) * c[2]);
                     if (lat->mask_h[idx] != 0)
                         return fail(lat, VLB_EINVAL, "vlb_add_sphere: overlaps a non-fluid cell");
                     cells.push_back(idx);

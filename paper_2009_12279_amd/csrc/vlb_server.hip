@@ -1,15 +1,23 @@
 // Serving runtime of libvlb: continuous batching of independent solves.
 //
 // Requests wait in a FIFO queue.  A request is admitted when a slot is free
-// and its device footprint fits the HBM budget; it then owns its buffers
-// (populations, stress, velocity, mask) until it retires.  One batched launch
-// advances every admitted solve by one step; K such steps (stream-collide,
-// stress update and the per-solve step-counter advance) are captured in a
-// hipGraph and replayed.  The graph only refers to fixed device tables, so
-// admissions and retirements rewrite the tables between replays; the graph is
-// captured again only when the total number of blocks changes.  A request's
-// latency runs from vlb_server_submit to the moment its result is on the
-// host.
+// and its device footprint fits in the server's arena, one device allocation
+// of the whole HBM budget made at creation; the solve then owns its range of
+// the arena (populations, stress, velocity, mask) until it retires.  One
+// batched launch advances every admitted solve by one step; K such steps
+// (stream-collide, stress update and the per-solve step-counter advance) are
+// captured in a hipGraph and replayed.  The graph only refers to fixed device
+// tables, which are rewritten in stream order between replays.
+//
+// Scheduling keeps the GPU fed: up to two replays are in flight, and the host
+// retires finished solves (results read on a second stream), admits new ones
+// (uploads and initialisation on that stream) and rewrites the tables while
+// the earlier replay runs.  Every admitted solve advances by exactly K steps
+// per replay until its target, so the host knows from the count of completed
+// replays which solves have finished, without reading the device.  A retired
+// solve's arena range is reused only after every replay issued while it was
+// in the tables has completed.  A request's latency runs from
+// vlb_server_submit to the moment its result is on the host.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -48,8 +56,9 @@ struct Request {
 
 struct Slot {
     uint64_t ticket = 0;
+    uint32_t id = 0;                    // index in the device solve and step tables
     vlb::Geom g{};
-    uint64_t bytes = 0;
+    uint64_t offset = 0, bytes = 0;     // range of the arena
     uint8_t *mask = nullptr;
     float *f[2] = {nullptr, nullptr};
     float *tau[2] = {nullptr, nullptr};
@@ -57,6 +66,13 @@ struct Slot {
     vlb::StepArgs args[2]{};
     uint32_t target = 0;
     uint32_t nblocks = 0;
+    uint64_t last_launch = 0;           // the replay that takes it to its target
+};
+
+// arena range of a retired solve, reusable once `free_after` replays have
+// completed (replays issued while it was in the tables may still touch it)
+struct Quarantined {
+    uint64_t offset, bytes, free_after;
 };
 
 uint64_t footprint(const vlb_dims &d)
@@ -72,30 +88,53 @@ struct vlb_server {
     uint64_t budget = 0;
     int max_slots = 0;
     int k_steps = 1;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;   // replays and table updates
     bool own_stream = false;
+    hipStream_t io = nullptr;       // admissions and result reads
+    hipStream_t cap = nullptr;      // graph capture only
     uint64_t next_ticket = 1;
     uint64_t used = 0;
     std::map<uint64_t, Request> requests;
     std::deque<uint64_t> queue;
-    std::vector<Slot> slots;
-    // device tables
+    std::vector<Slot> slots;        // admitted solves
+    std::vector<uint32_t> free_ids;
+    std::vector<uint32_t> new_ids;  // admitted since the last table update
+    // arena: one allocation of the budget, handed out in ranges
+    char *arena = nullptr;
+    std::map<uint64_t, uint64_t> free_ranges;  // offset -> bytes
+    std::vector<Quarantined> quarantine;
+    // device tables (solves and step counters indexed by slot id) and their
+    // pinned staging
     vlb::BatchTable *d_table = nullptr;
     vlb::BatchSolve *d_solves = nullptr;
     uint32_t *d_block_solve = nullptr;
     uint32_t *d_steps = nullptr;
     uint32_t table_capacity_blocks = 0;
+    vlb::BatchTable *h_table = nullptr;
+    vlb::BatchSolve *h_solves = nullptr;
+    uint32_t *h_block_solve = nullptr;
+    uint32_t *h_zero = nullptr;
+    hipEvent_t tables_copied = nullptr;
     uint32_t total_blocks = 0;
-    bool tables_dirty = true;
-    // graph of k_steps batched steps for the current block count
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t graph_exec = nullptr;
-    uint32_t graph_blocks = 0;
-    // kernel nodes whose grid follows the total block count
-    std::vector<hipGraphNode_t> grid_nodes;
-    std::vector<hipKernelNodeParams> grid_params;
-    hipEvent_t done_event = nullptr;
-    bool in_flight = false;
+    bool tables_dirty = false;
+    bool admitted_since_launch = false;
+    hipEvent_t io_done = nullptr;
+    // result staging (doubles)
+    double *d_result = nullptr;
+    uint64_t d_result_cap = 0;
+    double *h_result = nullptr;
+    uint64_t h_result_cap = 0;
+    // two graph executables, used by alternate replays, so that one can be
+    // updated while the other is in flight
+    struct GraphSet {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        uint32_t blocks = 0;
+        std::vector<hipGraphNode_t> nodes;  // kernel nodes whose grid is the block count
+        std::vector<hipKernelNodeParams> params;
+    } graphs[2];
+    hipEvent_t launch_done[2] = {nullptr, nullptr};
+    uint64_t n_launched = 0, n_completed = 0;
     int stochastic = 1;
     vlb_server_stats stats{};
     std::string err = "no error";
@@ -118,13 +157,50 @@ vlb_status sfail(vlb_server *s, vlb_status st, const std::string &msg)
                          std::string(what) + ": " + hipGetErrorString(e_));                \
     } while (0)
 
-void free_slot(Slot &sl)
+// ---- arena ----------------------------------------------------------------
+
+bool arena_alloc(vlb_server *srv, uint64_t bytes, uint64_t &offset)
 {
-    void *p[] = {sl.mask, sl.f[0], sl.f[1], sl.tau[0], sl.tau[1], sl.u};
-    for (void *q : p)
-        if (q)
-            (void)hipFree(q);
-    sl = Slot{};
+    for (auto it = srv->free_ranges.begin(); it != srv->free_ranges.end(); ++it) {
+        if (it->second < bytes)
+            continue;
+        offset = it->first;
+        const uint64_t rest = it->second - bytes;
+        srv->free_ranges.erase(it);
+        if (rest)
+            srv->free_ranges.emplace(offset + bytes, rest);
+        return true;
+    }
+    return false;
+}
+
+void arena_release(vlb_server *srv, uint64_t offset, uint64_t bytes)
+{
+    auto next = srv->free_ranges.lower_bound(offset);
+    if (next != srv->free_ranges.end() && offset + bytes == next->first) {
+        bytes += next->second;
+        next = srv->free_ranges.erase(next);
+    }
+    if (next != srv->free_ranges.begin()) {
+        auto prev = std::prev(next);
+        if (prev->first + prev->second == offset) {
+            prev->second += bytes;
+            return;
+        }
+    }
+    srv->free_ranges.emplace(offset, bytes);
+}
+
+void release_quarantine(vlb_server *srv)
+{
+    std::vector<Quarantined> keep;
+    for (const Quarantined &q : srv->quarantine) {
+        if (q.free_after <= srv->n_completed)
+            arena_release(srv, q.offset, q.bytes);
+        else
+            keep.push_back(q);
+    }
+    srv->quarantine.swap(keep);
 }
 
 bool params_ok(const vlb_params &p, double &wp, double &wm)
@@ -188,10 +264,20 @@ void make_args(vlb_server *srv, Slot &sl, const Request &rq)
     }
 }
 
-vlb_status admit(vlb_server *srv, Request &rq)
+// Admit a request into an arena range: uploads and initialisation run on the
+// io stream (the next replay waits for them).  `no_room` when no range is
+// free yet (the request waits for retirements).
+vlb_status admit(vlb_server *srv, Request &rq, bool &no_room)
 {
+    const uint64_t bytes = footprint(rq.dims);
+    uint64_t offset = 0;
+    no_room = srv->free_ids.empty() || !arena_alloc(srv, bytes, offset);
+    if (no_room)
+        return VLB_OK;
     Slot sl;
     sl.ticket = rq.ticket;
+    sl.id = srv->free_ids.back();
+    srv->free_ids.pop_back();
     const uint64_t N = static_cast<uint64_t>(rq.dims.nx) * rq.dims.ny * rq.dims.nz;
     sl.g.nx = rq.dims.nx;
     sl.g.ny = rq.dims.ny;
@@ -200,144 +286,161 @@ vlb_status admit(vlb_server *srv, Request &rq)
         sl.g.per[a] = rq.dims.periodic[a] ? 1 : 0;
     sl.g.N = static_cast<uint32_t>(N);
     sl.g.plane = round_up(N, kAlign);
-    sl.bytes = footprint(rq.dims);
+    sl.offset = offset;
+    sl.bytes = bytes;
     sl.target = rq.steps;
     sl.nblocks = static_cast<uint32_t>((N + vlb::BLOCK - 1) / vlb::BLOCK);
     const uint64_t P = sl.g.plane;
-    hipError_t e = hipSuccess;
-    auto alloc = [&](void **p, size_t bytes) {
-        if (e == hipSuccess)
-            e = hipMalloc(p, bytes);
-    };
-    alloc(reinterpret_cast<void **>(&sl.mask), round_up(N, kAlign));
-    for (int b = 0; b < 2; ++b) {
-        alloc(reinterpret_cast<void **>(&sl.f[b]), vlb::Q * P * 4);
-        alloc(reinterpret_cast<void **>(&sl.tau[b]), 6 * P * 4);
-    }
-    alloc(reinterpret_cast<void **>(&sl.u), 3 * P * 4);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(sl.mask, rq.mask.data(), N, hipMemcpyHostToDevice, srv->stream);
+    char *base = srv->arena + offset;
+    sl.f[0] = reinterpret_cast<float *>(base);
+    sl.f[1] = sl.f[0] + vlb::Q * P;
+    sl.tau[0] = sl.f[1] + vlb::Q * P;
+    sl.tau[1] = sl.tau[0] + 6 * P;
+    sl.u = sl.tau[1] + 6 * P;
+    sl.mask = reinterpret_cast<uint8_t *>(sl.u + 3 * P);
+    const uint64_t K = static_cast<uint64_t>(srv->k_steps);
+    sl.last_launch = srv->n_launched + (sl.target + K - 1) / K - 1;  // unused for target 0
+    hipError_t e = hipMemcpyAsync(sl.mask, rq.mask.data(), N, hipMemcpyHostToDevice, srv->io);
     for (int b = 0; b < 2 && e == hipSuccess; ++b) {
-        e = hipMemsetAsync(sl.tau[b], 0, 6 * P * 4, srv->stream);
+        e = hipMemsetAsync(sl.tau[b], 0, 6 * P * 4, srv->io);
         if (e == hipSuccess)
-            e = hipMemsetAsync(sl.f[b], 0, vlb::Q * P * 4, srv->stream);
+            e = hipMemsetAsync(sl.f[b], 0, vlb::Q * P * 4, srv->io);
     }
     if (e == hipSuccess)
-        e = hipMemsetAsync(sl.u, 0, 3 * P * 4, srv->stream);
+        e = hipMemsetAsync(sl.u, 0, 3 * P * 4, srv->io);
     if (e == hipSuccess)
-        e = vlb::launch_init_equilibrium(vlb::ST_F32, sl.g, sl.mask, nullptr, sl.f[0], 1.f,
-                                         srv->stream);
+        e = vlb::launch_init_equilibrium(vlb::ST_F32, sl.g, sl.mask, nullptr, sl.f[0], 1.f, srv->io);
     if (e != hipSuccess) {
-        free_slot(sl);
-        return sfail(srv, e == hipErrorOutOfMemory ? VLB_ENOMEM : VLB_EDEVICE,
-                     std::string("admission: ") + hipGetErrorString(e));
+        arena_release(srv, offset, bytes);
+        srv->free_ids.push_back(sl.id);
+        return sfail(srv, VLB_EDEVICE, std::string("admission: ") + hipGetErrorString(e));
     }
     make_args(srv, sl, rq);
     srv->used += sl.bytes;
+    srv->new_ids.push_back(sl.id);
     srv->slots.push_back(sl);
     rq.state = VLB_REQ_RUNNING;
-    rq.mask.clear();
-    rq.mask.shrink_to_fit();
     srv->tables_dirty = true;
+    srv->admitted_since_launch = true;
     return VLB_OK;
 }
 
-// device tables from the current slot list (steps of new solves start at 0;
-// running solves keep theirs)
-vlb_status rebuild_tables(vlb_server *srv, const std::vector<uint32_t> &steps)
+// Rewrite the device tables from the slot list, in stream order behind the
+// replays already issued: solve entries by slot id (free ids get a zero
+// target, so the counter advance leaves them alone), the block-to-solve map
+// and zeroed step counters for newly admitted solves.
+vlb_status rebuild_tables(vlb_server *srv)
 {
-    const uint32_t ns = static_cast<uint32_t>(srv->slots.size());
-    std::vector<vlb::BatchSolve> solves(ns);
-    std::vector<uint32_t> block_solve;
-    uint32_t first = 0;
-    for (uint32_t s = 0; s < ns; ++s) {
-        const Slot &sl = srv->slots[s];
-        solves[s].args[0] = sl.args[0];
-        solves[s].args[1] = sl.args[1];
-        solves[s].first_block = first;
-        solves[s].nblocks = sl.nblocks;
-        solves[s].target = sl.target;
-        block_solve.insert(block_solve.end(), sl.nblocks, static_cast<uint32_t>(s));
-        first += sl.nblocks;
+    SCHK(srv, hipEventSynchronize(srv->tables_copied), "table staging");
+    uint32_t n_ids = 0, total = 0;
+    for (const Slot &sl : srv->slots) {
+        n_ids = std::max(n_ids, sl.id + 1);
+        total += sl.nblocks;
     }
-    srv->total_blocks = first;
-    if (first > srv->table_capacity_blocks) {
+    if (total > srv->table_capacity_blocks) {
+        const uint32_t cap = std::max<uint32_t>(total, 2 * srv->table_capacity_blocks);
         if (srv->d_block_solve)
-            (void)hipFree(srv->d_block_solve);
+            (void)hipFree(srv->d_block_solve);  // waits for the replays that use it
+        if (srv->h_block_solve)
+            (void)hipHostFree(srv->h_block_solve);
         srv->d_block_solve = nullptr;
-        const uint32_t cap = std::max<uint32_t>(first, 2 * srv->table_capacity_blocks);
+        srv->h_block_solve = nullptr;
+        srv->table_capacity_blocks = 0;
         SCHK(srv, hipMalloc(&srv->d_block_solve, cap * sizeof(uint32_t)), "block table");
+        SCHK(srv, hipHostMalloc(&srv->h_block_solve, cap * sizeof(uint32_t)), "block table");
         srv->table_capacity_blocks = cap;
     }
-    vlb::BatchTable t{};
-    t.n_solves = ns;
-    t.total_blocks = first;
+    std::memset(srv->h_solves, 0, n_ids * sizeof(vlb::BatchSolve));
+    uint32_t first = 0;
+    for (const Slot &sl : srv->slots) {
+        vlb::BatchSolve &bs = srv->h_solves[sl.id];
+        bs.args[0] = sl.args[0];
+        bs.args[1] = sl.args[1];
+        bs.first_block = first;
+        bs.nblocks = sl.nblocks;
+        bs.target = sl.target;
+        for (uint32_t k = 0; k < sl.nblocks; ++k)
+            srv->h_block_solve[first + k] = sl.id;
+        first += sl.nblocks;
+    }
+    srv->total_blocks = total;
+    vlb::BatchTable &t = *srv->h_table;
+    t.n_solves = n_ids;
+    t.total_blocks = total;
     t.solves = srv->d_solves;
     t.block_solve = srv->d_block_solve;
     t.steps = srv->d_steps;
-    if (ns)
-        SCHK(srv, hipMemcpyAsync(srv->d_solves, solves.data(), ns * sizeof(vlb::BatchSolve),
+    for (uint32_t id : srv->new_ids)
+        SCHK(srv, hipMemcpyAsync(srv->d_steps + id, srv->h_zero, sizeof(uint32_t),
+                                 hipMemcpyHostToDevice, srv->stream),
+             "step reset");
+    srv->new_ids.clear();
+    if (n_ids)
+        SCHK(srv, hipMemcpyAsync(srv->d_solves, srv->h_solves, n_ids * sizeof(vlb::BatchSolve),
                                  hipMemcpyHostToDevice, srv->stream),
              "solve table");
-    if (first)
-        SCHK(srv, hipMemcpyAsync(srv->d_block_solve, block_solve.data(), first * sizeof(uint32_t),
+    if (total)
+        SCHK(srv, hipMemcpyAsync(srv->d_block_solve, srv->h_block_solve, total * sizeof(uint32_t),
                                  hipMemcpyHostToDevice, srv->stream),
              "block table");
-    if (ns)
-        SCHK(srv, hipMemcpyAsync(srv->d_steps, steps.data(), ns * sizeof(uint32_t),
-                                 hipMemcpyHostToDevice, srv->stream),
-             "step table");
-    SCHK(srv, hipMemcpyAsync(srv->d_table, &t, sizeof t, hipMemcpyHostToDevice, srv->stream),
+    SCHK(srv, hipMemcpyAsync(srv->d_table, srv->h_table, sizeof(vlb::BatchTable),
+                             hipMemcpyHostToDevice, srv->stream),
          "table");
-    SCHK(srv, hipStreamSynchronize(srv->stream), "tables");
+    SCHK(srv, hipEventRecord(srv->tables_copied, srv->stream), "table event");
     srv->tables_dirty = false;
     return VLB_OK;
 }
 
-vlb_status ensure_graph(vlb_server *srv)
+void drop_graph(vlb_server::GraphSet &gs)
 {
-    if (srv->graph_exec && srv->graph_blocks == srv->total_blocks)
+    if (gs.exec)
+        (void)hipGraphExecDestroy(gs.exec);
+    if (gs.graph)
+        (void)hipGraphDestroy(gs.graph);
+    gs = vlb_server::GraphSet{};
+}
+
+// Graph of K batched steps for the current block count.  The set is not in
+// flight (its previous replay has completed), so its grid can be updated in
+// place rather than captured again.
+vlb_status ensure_graph(vlb_server *srv, vlb_server::GraphSet &gs)
+{
+    if (gs.exec && gs.blocks == srv->total_blocks)
         return VLB_OK;
-    if (srv->graph_exec) {
-        // same work with a different grid: update the batched kernel nodes in
-        // place rather than capturing and instantiating again
+    if (gs.exec) {
         bool ok = true;
-        for (size_t k = 0; k < srv->grid_nodes.size() && ok; ++k) {
-            hipKernelNodeParams p = srv->grid_params[k];
+        for (size_t k = 0; k < gs.nodes.size() && ok; ++k) {
+            hipKernelNodeParams p = gs.params[k];
             p.gridDim.x = srv->total_blocks;
-            ok = hipGraphExecKernelNodeSetParams(srv->graph_exec, srv->grid_nodes[k], &p) ==
-                 hipSuccess;
+            ok = hipGraphExecKernelNodeSetParams(gs.exec, gs.nodes[k], &p) == hipSuccess;
             if (ok)
-                srv->grid_params[k] = p;
+                gs.params[k] = p;
         }
         if (ok) {
-            srv->graph_blocks = srv->total_blocks;
+            gs.blocks = srv->total_blocks;
             srv->stats.graph_updates += 1;
             return VLB_OK;
         }
         (void)hipGetLastError();
-        (void)hipGraphExecDestroy(srv->graph_exec);
-        (void)hipGraphDestroy(srv->graph);
-        srv->graph_exec = nullptr;
-        srv->graph = nullptr;
+        drop_graph(gs);
     }
-    SCHK(srv, hipStreamBeginCapture(srv->stream, hipStreamCaptureModeThreadLocal), "capture");
+    SCHK(srv, hipStreamBeginCapture(srv->cap, hipStreamCaptureModeThreadLocal), "capture");
     hipError_t e = vlb::launch_batch_step(srv->d_table, srv->total_blocks, srv->stochastic,
-                                          srv->k_steps, srv->stream);
+                                          srv->k_steps, srv->cap);
     hipGraph_t g = nullptr;
-    hipError_t e2 = hipStreamEndCapture(srv->stream, &g);
+    hipError_t e2 = hipStreamEndCapture(srv->cap, &g);
     SCHK(srv, e, "capture launch");
     SCHK(srv, e2, "end capture");
-    srv->graph = g;
-    SCHK(srv, hipGraphInstantiate(&srv->graph_exec, g, nullptr, nullptr, 0), "instantiate");
+    gs.graph = g;
+    SCHK(srv, hipGraphInstantiate(&gs.exec, g, nullptr, nullptr, 0), "instantiate");
     // remember the per-cell kernel nodes (block size BLOCK; the counter
     // advance runs with a different block size)
     size_t count = 0;
     SCHK(srv, hipGraphGetNodes(g, nullptr, &count), "graph nodes");
     std::vector<hipGraphNode_t> nodes(count);
     SCHK(srv, hipGraphGetNodes(g, nodes.data(), &count), "graph nodes");
-    srv->grid_nodes.clear();
-    srv->grid_params.clear();
+    gs.nodes.clear();
+    gs.params.clear();
     for (hipGraphNode_t nd : nodes) {
         hipGraphNodeType ty;
         SCHK(srv, hipGraphNodeGetType(nd, &ty), "graph node type");
@@ -346,45 +449,113 @@ vlb_status ensure_graph(vlb_server *srv)
         hipKernelNodeParams p{};
         SCHK(srv, hipGraphKernelNodeGetParams(nd, &p), "graph node params");
         if (p.blockDim.x == static_cast<unsigned>(vlb::BLOCK)) {
-            srv->grid_nodes.push_back(nd);
-            srv->grid_params.push_back(p);
+            gs.nodes.push_back(nd);
+            gs.params.push_back(p);
         }
     }
-    srv->graph_blocks = srv->total_blocks;
+    gs.blocks = srv->total_blocks;
     srv->stats.graph_captures += 1;
     return VLB_OK;
 }
 
-// results of a finished slot: velocity (moments of the final state) and stress
-vlb_status collect(vlb_server *srv, Slot &sl, Request &rq)
+// Results of finished solves (their last replay has completed): velocity from
+// the moments of the final state and the stress, read on the io stream into
+// pinned staging while later replays run.
+vlb_status collect(vlb_server *srv, const std::vector<Slot> &done)
 {
-    const uint64_t N = sl.g.N;
-    const int par = static_cast<int>(sl.target & 1u);
-    double *d = nullptr;
-    SCHK(srv, hipMalloc(&d, 9 * N * sizeof(double)), "result buffer");
-    const float gv[3] = {static_cast<float>(rq.params.body_force[0]),
-                         static_cast<float>(rq.params.body_force[1]),
-                         static_cast<float>(rq.params.body_force[2])};
-    vlb::Bound b{};
-    hipError_t e = vlb::launch_read_moments(vlb::ST_F32, sl.g, b, sl.mask, sl.f[par], sl.tau[par],
-                                            rq.params.beta > 0.0, gv, 1.f, nullptr, d, srv->stream);
+    uint64_t total = 0;
+    for (const Slot &sl : done)
+        total += 9ull * sl.g.N;
+    if (total == 0)
+        return VLB_OK;
+    if (total > srv->d_result_cap) {
+        if (srv->d_result)
+            (void)hipFree(srv->d_result);
+        srv->d_result = nullptr;
+        srv->d_result_cap = 0;
+        SCHK(srv, hipMalloc(&srv->d_result, total * sizeof(double)), "result buffer");
+        srv->d_result_cap = total;
+    }
+    if (total > srv->h_result_cap) {
+        if (srv->h_result)
+            (void)hipHostFree(srv->h_result);
+        srv->h_result = nullptr;
+        srv->h_result_cap = 0;
+        SCHK(srv, hipHostMalloc(&srv->h_result, total * sizeof(double)), "result staging");
+        srv->h_result_cap = total;
+    }
+    uint64_t off = 0;
+    hipError_t e = hipSuccess;
+    for (const Slot &sl : done) {
+        const Request &rq = srv->requests[sl.ticket];
+        const uint64_t N = sl.g.N;
+        const int par = static_cast<int>(sl.target & 1u);
+        const float gv[3] = {static_cast<float>(rq.params.body_force[0]),
+                             static_cast<float>(rq.params.body_force[1]),
+                             static_cast<float>(rq.params.body_force[2])};
+        vlb::Bound b{};
+        double *d = srv->d_result + off;
+        if (e == hipSuccess)
+            e = vlb::launch_read_moments(vlb::ST_F32, sl.g, b, sl.mask, sl.f[par], sl.tau[par],
+                                         rq.params.beta > 0.0, gv, 1.f, nullptr, d, srv->io);
+        if (e == hipSuccess)
+            e = vlb::launch_read_stress(sl.g, sl.mask, sl.tau[par], d + 3 * N, srv->io);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(srv->h_result + off, d, 9 * N * sizeof(double),
+                               hipMemcpyDeviceToHost, srv->io);
+        off += 9 * N;
+    }
     if (e == hipSuccess)
-        e = vlb::launch_read_stress(sl.g, sl.mask, sl.tau[par], d + 3 * N, srv->stream);
-    rq.u.resize(3 * N);
-    rq.tau.resize(6 * N);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(rq.u.data(), d, 3 * N * sizeof(double), hipMemcpyDeviceToHost, srv->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(rq.tau.data(), d + 3 * N, 6 * N * sizeof(double), hipMemcpyDeviceToHost,
-                           srv->stream);
-    if (e == hipSuccess)
-        e = hipStreamSynchronize(srv->stream);
-    (void)hipFree(d);
+        e = hipStreamSynchronize(srv->io);
+    off = 0;
+    const auto now = clock_type::now();
+    for (const Slot &sl : done) {
+        Request &rq = srv->requests[sl.ticket];
+        const uint64_t N = sl.g.N;
+        if (e == hipSuccess) {
+            rq.u.assign(srv->h_result + off, srv->h_result + off + 3 * N);
+            rq.tau.assign(srv->h_result + off + 3 * N, srv->h_result + off + 9 * N);
+            rq.latency_ms = std::chrono::duration<double, std::milli>(now - rq.submitted).count();
+            rq.state = VLB_REQ_DONE;
+            srv->stats.completed += 1;
+        } else {
+            rq.state = VLB_REQ_FAILED;
+            rq.error = std::string("result readout: ") + hipGetErrorString(e);
+        }
+        rq.mask.clear();
+        rq.mask.shrink_to_fit();
+        off += 9 * N;
+    }
     SCHK(srv, e, "result readout");
-    rq.latency_ms =
-        std::chrono::duration<double, std::milli>(clock_type::now() - rq.submitted).count();
-    rq.state = VLB_REQ_DONE;
-    srv->stats.completed += 1;
+    return VLB_OK;
+}
+
+// Retire solves: the arena range waits in quarantine until every replay
+// issued so far has completed.
+void retire(vlb_server *srv, const Slot &sl)
+{
+    srv->quarantine.push_back(Quarantined{sl.offset, sl.bytes, srv->n_launched});
+    srv->used -= sl.bytes;
+    srv->free_ids.push_back(sl.id);
+    srv->tables_dirty = true;
+}
+
+// Mark completed replays done; with `block`, wait for the oldest one.
+vlb_status reap(vlb_server *srv, bool block)
+{
+    while (srv->n_completed < srv->n_launched) {
+        hipEvent_t ev = srv->launch_done[srv->n_completed & 1u];
+        const hipError_t q = hipEventQuery(ev);
+        if (q == hipErrorNotReady) {
+            if (!block)
+                break;
+            SCHK(srv, hipEventSynchronize(ev), "replay wait");
+            block = false;
+        } else {
+            SCHK(srv, q, "replay query");
+        }
+        srv->n_completed += 1;
+    }
     return VLB_OK;
 }
 
@@ -398,15 +569,18 @@ vlb_status vlb_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t
     if (!out)
         return VLB_EINVAL;
     *out = nullptr;
-    if (max_slots < 1 || max_slots > 4096 || steps_per_launch < 1 || steps_per_launch > 4096)
+    if (max_slots < 1 || max_slots > 4096 || steps_per_launch < 1 || steps_per_launch > 4096 ||
+        hbm_budget_bytes < kAlign)
         return VLB_EINVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
         return VLB_EDEVICE;
     vlb_server *srv = new vlb_server();
-    srv->budget = hbm_budget_bytes;
+    srv->budget = hbm_budget_bytes / kAlign * kAlign;
     srv->max_slots = max_slots;
     srv->k_steps = steps_per_launch;
+    for (int id = max_slots - 1; id >= 0; --id)
+        srv->free_ids.push_back(static_cast<uint32_t>(id));
     hipError_t e = hipSuccess;
     if (stream) {
         srv->stream = static_cast<hipStream_t>(stream);
@@ -415,13 +589,33 @@ vlb_status vlb_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t
         srv->own_stream = true;
     }
     if (e == hipSuccess)
+        e = hipStreamCreate(&srv->io);
+    if (e == hipSuccess)
+        e = hipStreamCreate(&srv->cap);
+    if (e == hipSuccess)
+        e = hipMalloc(&srv->arena, srv->budget);
+    if (e == hipSuccess)
+        srv->free_ranges.emplace(0, srv->budget);
+    if (e == hipSuccess)
         e = hipMalloc(&srv->d_table, sizeof(vlb::BatchTable));
     if (e == hipSuccess)
         e = hipMalloc(&srv->d_solves, max_slots * sizeof(vlb::BatchSolve));
     if (e == hipSuccess)
         e = hipMalloc(&srv->d_steps, max_slots * sizeof(uint32_t));
     if (e == hipSuccess)
-        e = hipEventCreateWithFlags(&srv->done_event, hipEventDisableTiming);
+        e = hipHostMalloc(&srv->h_table, sizeof(vlb::BatchTable));
+    if (e == hipSuccess)
+        e = hipHostMalloc(&srv->h_solves, max_slots * sizeof(vlb::BatchSolve));
+    if (e == hipSuccess)
+        e = hipHostMalloc(&srv->h_zero, sizeof(uint32_t));
+    if (e == hipSuccess)
+        *srv->h_zero = 0;
+    for (hipEvent_t *ev : {&srv->launch_done[0], &srv->launch_done[1], &srv->tables_copied,
+                           &srv->io_done})
+        if (e == hipSuccess)
+            e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
+    if (e == hipSuccess)
+        e = hipEventRecord(srv->tables_copied, srv->stream);
     if (e != hipSuccess) {
         vlb_server_destroy(srv);
         return e == hipErrorOutOfMemory ? VLB_ENOMEM : VLB_EDEVICE;
@@ -443,7 +637,14 @@ vlb_status vlb_server_set_rounding(vlb_server *srv, vlb_rounding mode)
         return VLB_EINVAL;
     if (!srv->slots.empty() || !srv->queue.empty())
         return sfail(srv, VLB_ESTATE, "vlb_server_set_rounding: server is not idle");
-    srv->stochastic = mode == VLB_ROUND_STOCHASTIC;
+    const int st = mode == VLB_ROUND_STOCHASTIC;
+    if (st != srv->stochastic) {
+        // the rounding mode is baked into the captured kernels
+        (void)hipStreamSynchronize(srv->stream);
+        drop_graph(srv->graphs[0]);
+        drop_graph(srv->graphs[1]);
+    }
+    srv->stochastic = st;
     return VLB_OK;
 }
 
@@ -472,28 +673,55 @@ vlb_status vlb_server_submit(vlb_server *srv, const vlb_request *req, uint64_t *
             return sfail(srv, VLB_EINVAL, "vlb_server_submit: mask values >= 64 are reserved");
     // solid end layers on non-periodic axes
     const int n3[3] = {d.nx, d.ny, d.nz};
+    auto at = [&](int x, int y, int z) -> uint8_t & {
+        return rq.mask[x + static_cast<size_t>(d.nx) * (y + static_cast<size_t>(d.ny) * z)];
+    };
     for (int ax = 0; ax < 3; ++ax) {
         if (d.periodic[ax])
             continue;
-        for (int z = 0; z < d.nz; ++z)
-            for (int y = 0; y < d.ny; ++y)
-                for (int x = 0; x < d.nx; ++x) {
-                    const int c[3] = {x, y, z};
-                    if ((c[ax] == 0 || c[ax] == n3[ax] - 1) &&
-                        rq.mask[x + static_cast<size_t>(d.nx) * (y + static_cast<size_t>(d.ny) * z)] == 0)
+        const int a1 = (ax + 1) % 3, a2 = (ax + 2) % 3;
+        for (int side = 0; side < 2; ++side)
+            for (int j2 = 0; j2 < n3[a2]; ++j2)
+                for (int j1 = 0; j1 < n3[a1]; ++j1) {
+                    int c[3];
+                    c[ax] = side ? n3[ax] - 1 : 0;
+                    c[a1] = j1;
+                    c[a2] = j2;
+                    if (at(c[0], c[1], c[2]) == 0)
                         return sfail(srv, VLB_EINVAL,
                                      "vlb_server_submit: non-periodic axis without solid end layers");
                 }
     }
-    // fixed spheres become solid cells at rest
+    // fixed spheres become solid cells at rest: |x - c|^2 < r^2 over the
+    // sphere's bounding box (wrapped on periodic axes, clipped otherwise)
     for (int k = 0; k < req->n_spheres; ++k) {
         const double *sp = req->spheres + 4 * k;
-        for (int z = 0; z < d.nz; ++z)
-            for (int y = 0; y < d.ny; ++y)
-                for (int x = 0; x < d.nx; ++x) {
-                    const int c[3] = {x, y, z};
+        if (!(sp[3] > 0.0) || !std::isfinite(sp[3]) || !std::isfinite(sp[0]) ||
+            !std::isfinite(sp[1]) || !std::isfinite(sp[2]))
+            return sfail(srv, VLB_EINVAL, "vlb_server_submit: invalid sphere");
+        int lo[3], hi[3];
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = static_cast<int>(std::floor(sp[a] - sp[3])) - 1;
+            hi[a] = static_cast<int>(std::ceil(sp[a] + sp[3])) + 1;
+            if (!d.periodic[a] || hi[a] - lo[a] + 1 >= n3[a]) {
+                // clipped (or the box covers the whole periodic axis: scan it once)
+                if (d.periodic[a]) {
+                    lo[a] = 0;
+                    hi[a] = n3[a] - 1;
+                } else {
+                    lo[a] = std::max(lo[a], 0);
+                    hi[a] = std::min(hi[a], n3[a] - 1);
+                }
+            }
+        }
+        for (int zz = lo[2]; zz <= hi[2]; ++zz)
+            for (int yy = lo[1]; yy <= hi[1]; ++yy)
+                for (int xx = lo[0]; xx <= hi[0]; ++xx) {
+                    const int raw[3] = {xx, yy, zz};
+                    int c[3];
                     double dd[3];
                     for (int a = 0; a < 3; ++a) {
+                        c[a] = ((raw[a] % n3[a]) + n3[a]) % n3[a];
                         dd[a] = static_cast<double>(c[a]) - sp[a];
                         if (d.periodic[a]) {
                             const double L = static_cast<double>(n3[a]);
@@ -506,7 +734,7 @@ vlb_status vlb_server_submit(vlb_server *srv, const vlb_request *req, uint64_t *
                         d2 = dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2];
                     }
                     if (d2 < sp[3] * sp[3])
-                        rq.mask[x + static_cast<size_t>(d.nx) * (y + static_cast<size_t>(d.ny) * z)] = 1;
+                        at(c[0], c[1], c[2]) = 1;
                 }
     }
     rq.params = req->params;
@@ -524,51 +752,43 @@ vlb_status vlb_server_pump(vlb_server *srv, int32_t wait)
 {
     if (!srv)
         return VLB_EINVAL;
-    if (srv->in_flight) {
-        if (wait) {
-            SCHK(srv, hipEventSynchronize(srv->done_event), "pump wait");
-        } else {
-            const hipError_t q = hipEventQuery(srv->done_event);
-            if (q == hipErrorNotReady)
-                return VLB_OK;
-            SCHK(srv, q, "pump query");
-        }
-        srv->in_flight = false;
+    const uint64_t completed_before = srv->n_completed;
+    vlb_status st = reap(srv, false);
+    if (st != VLB_OK)
+        return st;
+    if (wait && srv->n_completed == completed_before && srv->n_launched > srv->n_completed) {
+        if ((st = reap(srv, true)) != VLB_OK)
+            return st;
+    } else if (srv->n_launched - srv->n_completed >= 2) {
+        return VLB_OK;
     }
-    // step counters of the running solves
-    const uint32_t ns = static_cast<uint32_t>(srv->slots.size());
-    std::vector<uint32_t> steps(ns, 0);
-    if (ns) {
-        SCHK(srv, hipMemcpyAsync(steps.data(), srv->d_steps, ns * sizeof(uint32_t),
-                                 hipMemcpyDeviceToHost, srv->stream),
-             "step readback");
-        SCHK(srv, hipStreamSynchronize(srv->stream), "step readback");
-    }
-    // retire finished (or cancelled) solves
-    std::vector<Slot> keep;
-    std::vector<uint32_t> keep_steps;
-    bool changed = false;
-    for (uint32_t s = 0; s < ns; ++s) {
-        Slot &sl = srv->slots[s];
-        Request &rq = srv->requests[sl.ticket];
-        if (rq.state == VLB_REQ_CANCELLED || steps[s] >= sl.target) {
-            if (rq.state != VLB_REQ_CANCELLED) {
-                vlb_status st = collect(srv, sl, rq);
-                if (st != VLB_OK) {
-                    rq.state = VLB_REQ_FAILED;
-                    rq.error = srv->err;
-                }
-            }
-            srv->used -= sl.bytes;
-            free_slot(sl);
-            changed = true;
-        } else {
+    release_quarantine(srv);
+    // retire solves whose last replay has completed, and cancelled ones
+    std::vector<Slot> keep, done, dropped;
+    for (Slot &sl : srv->slots) {
+        const Request &rq = srv->requests[sl.ticket];
+        if (rq.state == VLB_REQ_CANCELLED)
+            dropped.push_back(sl);
+        else if (sl.last_launch < srv->n_completed)
+            done.push_back(sl);
+        else
             keep.push_back(sl);
-            keep_steps.push_back(steps[s]);
-        }
     }
     srv->slots.swap(keep);
+    const vlb_status cst = collect(srv, done);
+    for (const Slot &sl : done)
+        retire(srv, sl);
+    for (const Slot &sl : dropped) {
+        Request &rq = srv->requests[sl.ticket];
+        rq.mask.clear();
+        rq.mask.shrink_to_fit();
+        retire(srv, sl);
+    }
+    if (cst != VLB_OK)
+        return cst;
+    release_quarantine(srv);
     // admit from the queue while slots and memory allow (FIFO, no overtaking)
+    std::vector<Slot> zero_step;
     while (!srv->queue.empty() && static_cast<int>(srv->slots.size()) < srv->max_slots) {
         Request &rq = srv->requests[srv->queue.front()];
         if (rq.state == VLB_REQ_CANCELLED) {
@@ -577,43 +797,60 @@ vlb_status vlb_server_pump(vlb_server *srv, int32_t wait)
         }
         if (srv->used + footprint(rq.dims) > srv->budget)
             break;
-        vlb_status st = admit(srv, rq);
+        bool no_room = false;
+        st = admit(srv, rq, no_room);
+        if (no_room)
+            break;  // no free range yet: wait for retirements
+        srv->queue.pop_front();
         if (st != VLB_OK) {
-            if (st == VLB_ENOMEM && !srv->slots.empty())
-                break;  // try again once memory frees up
             rq.state = VLB_REQ_FAILED;
             rq.error = srv->err;
-            srv->queue.pop_front();
             continue;
         }
-        srv->queue.pop_front();
-        keep_steps.push_back(0);
-        changed = true;
         if (rq.steps == 0) {
-            // nothing to advance: retire at the next round
+            // nothing to advance: the result is the initial state
+            zero_step.push_back(srv->slots.back());
+            srv->slots.pop_back();
+            srv->new_ids.pop_back();
         }
     }
-    if (changed || srv->tables_dirty) {
-        vlb_status st = rebuild_tables(srv, keep_steps);
-        if (st != VLB_OK)
-            return st;
+    if (!zero_step.empty()) {
+        const vlb_status zst = collect(srv, zero_step);
+        for (const Slot &sl : zero_step)
+            retire(srv, sl);
+        if (zst != VLB_OK)
+            return zst;
     }
     srv->stats.running = static_cast<int64_t>(srv->slots.size());
     srv->stats.queued = static_cast<int64_t>(srv->queue.size());
     srv->stats.bytes_in_use = srv->used;
-    if (srv->slots.empty())
-        return VLB_OK;
-    vlb_status st = ensure_graph(srv);
-    if (st != VLB_OK)
-        return st;
-    SCHK(srv, hipGraphLaunch(srv->graph_exec, srv->stream), "graph launch");
-    SCHK(srv, hipEventRecord(srv->done_event, srv->stream), "event");
-    srv->in_flight = true;
-    srv->stats.launches += 1;
-    uint64_t cells = 0;
-    for (size_t s = 0; s < srv->slots.size(); ++s)
-        cells += srv->slots[s].g.N;
-    srv->stats.cell_steps_launched += cells * static_cast<uint64_t>(srv->k_steps);
+    // keep up to two replays in flight while some solve still has steps that
+    // no replay has been issued for
+    while (srv->n_launched - srv->n_completed < 2) {
+        uint64_t cells = 0;
+        for (const Slot &sl : srv->slots)
+            if (sl.last_launch >= srv->n_launched)
+                cells += sl.g.N;
+        if (cells == 0)
+            break;
+        if (srv->tables_dirty && (st = rebuild_tables(srv)) != VLB_OK)
+            return st;
+        if (srv->admitted_since_launch) {
+            SCHK(srv, hipEventRecord(srv->io_done, srv->io), "admission event");
+            SCHK(srv, hipStreamWaitEvent(srv->stream, srv->io_done, 0), "admission wait");
+            srv->admitted_since_launch = false;
+        }
+        // this set's previous replay (two back) has completed
+        const uint32_t which = static_cast<uint32_t>(srv->n_launched & 1u);
+        vlb_server::GraphSet &gs = srv->graphs[which];
+        if ((st = ensure_graph(srv, gs)) != VLB_OK)
+            return st;
+        SCHK(srv, hipGraphLaunch(gs.exec, srv->stream), "graph launch");
+        SCHK(srv, hipEventRecord(srv->launch_done[which], srv->stream), "event");
+        srv->n_launched += 1;
+        srv->stats.launches += 1;
+        srv->stats.cell_steps_launched += cells * static_cast<uint64_t>(srv->k_steps);
+    }
     return VLB_OK;
 }
 
@@ -681,18 +918,26 @@ void vlb_server_destroy(vlb_server *srv)
         return;
     if (srv->stream)
         (void)hipStreamSynchronize(srv->stream);
-    for (Slot &sl : srv->slots)
-        free_slot(sl);
-    if (srv->graph_exec)
-        (void)hipGraphExecDestroy(srv->graph_exec);
-    if (srv->graph)
-        (void)hipGraphDestroy(srv->graph);
-    void *p[] = {srv->d_table, srv->d_solves, srv->d_block_solve, srv->d_steps};
+    if (srv->io)
+        (void)hipStreamSynchronize(srv->io);
+    drop_graph(srv->graphs[0]);
+    drop_graph(srv->graphs[1]);
+    void *p[] = {srv->arena, srv->d_table, srv->d_solves, srv->d_block_solve, srv->d_steps,
+                 srv->d_result};
     for (void *q : p)
         if (q)
             (void)hipFree(q);
-    if (srv->done_event)
-        (void)hipEventDestroy(srv->done_event);
+    void *h[] = {srv->h_table, srv->h_solves, srv->h_block_solve, srv->h_zero, srv->h_result};
+    for (void *q : h)
+        if (q)
+            (void)hipHostFree(q);
+    for (hipEvent_t ev : {srv->launch_done[0], srv->launch_done[1], srv->tables_copied, srv->io_done})
+        if (ev)
+            (void)hipEventDestroy(ev);
+    if (srv->io)
+        (void)hipStreamDestroy(srv->io);
+    if (srv->cap)
+        (void)hipStreamDestroy(srv->cap);
     if (srv->own_stream && srv->stream)
         (void)hipStreamDestroy(srv->stream);
     delete srv;
