@@ -95,6 +95,7 @@ struct vlb_lattice {
     double *d_wall = nullptr;
     Particle *d_parts = nullptr;
     double *d_partials = nullptr;
+    double *d_pforce = nullptr;   // block sums of the obstacle forces
     double *d_out = nullptr;
     int32_t *d_counters = nullptr;
     int n_walls = 0;
@@ -244,7 +245,7 @@ void free_all(vlb_lattice *lat)
         (void)hipStreamSynchronize(lat->stream);
     void *ptrs[] = {lat->d_mask,  lat->d_f[0],     lat->d_f[1],   lat->d_tau[0],     lat->d_tau[1],
                     lat->d_u,     lat->d_wall,     lat->d_parts,  lat->d_partials,   lat->d_out,
-                    lat->d_counters};
+                    lat->d_counters, lat->d_pforce};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -340,7 +341,8 @@ size_t vlb_required_bytes(const vlb_dims *dims, vlb_storage storage, int32_t n_p
     const uint64_t u = 3ull * P * sizeof(float);
     const uint64_t mask = round_up(N, 256);
     const uint64_t small = sizeof(Particle) * vlb::MAX_PARTICLES + 64 * 3 * sizeof(double) +
-                           2048 * 8 * sizeof(double) + 4096;
+                           2048 * 8 * sizeof(double) + 4096 +
+                           vlb::MAX_PARTICLES * vlb::PF_BLOCKS * 12 * sizeof(double);
     (void)n_particles;
     return static_cast<size_t>(pops + tau + u + mask + small);
 }
@@ -433,6 +435,9 @@ vlb_status vlb_create(const vlb_dims *dims, const uint8_t *mask, const double *w
         return bail(e, "partials");
     if ((e = hipMalloc(&lat->d_out, 16 * sizeof(double))) != hipSuccess)
         return bail(e, "out");
+    if ((e = hipMalloc(&lat->d_pforce, static_cast<size_t>(vlb::MAX_PARTICLES) * vlb::PF_BLOCKS *
+                                            12 * sizeof(double))) != hipSuccess)
+        return bail(e, "particle force sums");
     if ((e = hipMalloc(&lat->d_counters, 4 * sizeof(int32_t))) != hipSuccess)
         return bail(e, "counters");
     if ((e = hipMemsetAsync(lat->d_counters, 0, 4 * sizeof(int32_t), lat->stream)) != hipSuccess)
@@ -703,7 +708,7 @@ vlb_status vlb_step(vlb_lattice *lat, int64_t n_steps)
             const int np = static_cast<int>(lat->parts_h.size());
             HIPCHK(lat, vlb::launch_particle_forces(lat->storage, lat->g, lat->d_mask, a.fout, a.tin,
                                                     lat->polymer, lat->inv_scale, lat->d_parts, np,
-                                                    lat->stream),
+                                                    lat->d_pforce, lat->stream),
                    "particle forces");
             HIPCHK(lat, vlb::launch_particle_update(lat->g, lat->d_parts, np, lat->stream),
                    "particle update");
@@ -847,7 +852,7 @@ vlb_status vlb_read_particle(vlb_lattice *lat, int32_t id, double pos[3], double
         HIPCHK(lat, vlb::launch_particle_forces(lat->storage, lat->g, lat->d_mask,
                                                 lat->d_f[lat->cur], lat->d_tau[lat->cur ^ 1],
                                                 lat->polymer, lat->inv_scale, lat->d_parts, np,
-                                                lat->stream),
+                                                lat->d_pforce, lat->stream),
                "particle forces");
         HIPCHK(lat, vlb::launch_particle_update(lat->g, lat->d_parts, np, lat->stream),
                "particle totals");

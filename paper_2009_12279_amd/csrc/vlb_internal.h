@@ -142,10 +142,12 @@ int sums_blocks(const Geom &g);
 hipError_t launch_sums(int storage, const Geom &g, const uint8_t *mask, const void *f,
                        float inv_scale, double *partials, double *out, hipStream_t s);
 // Per-particle momentum exchange + polymer traction over each particle's
-// bounding box (one block per particle, deterministic FP64 reduction).
+// bounding box (PF_BLOCKS blocks per particle, block sums into `partials`,
+// MAX_PARTICLES x PF_BLOCKS x 12 doubles, then a fixed-order FP64 sum).
+constexpr int PF_BLOCKS = 32;
 hipError_t launch_particle_forces(int storage, const Geom &g, const uint8_t *mask, const void *f,
                                   const float *tau_n, int polymer, float inv_scale,
-                                  Particle *parts, int n_parts, hipStream_t s);
+                                  Particle *parts, int n_parts, double *partials, hipStream_t s);
 // Same over wall links of the whole lattice into out[3] (two-stage).
 hipError_t launch_wall_force(int storage, const Geom &g, const uint8_t *mask, const void *f,
                              const float *tau_n, int polymer, float inv_scale, double *partials,

@@ -1311,20 +1311,24 @@ __device__ void link_forces(const Geom &g, const uint8_t *mask, const void *fv, 
         }
 }
 
+// Obstacle forces: PF_BLOCKS blocks per particle (blockIdx.y) share the
+// particle's bounding box; each writes its block sum of the 12 components,
+// and particle_forces_reduce_kernel adds the blocks in a fixed order.
 template <int S>
 __global__ __launch_bounds__(BLOCK) void particle_forces_kernel(Geom g, const uint8_t *mask,
                                                                 const void *fv, const float *tau,
                                                                 int polymer, float inv_scale,
-                                                                Particle *parts)
+                                                                const Particle *parts,
+                                                                double *partials)
 {
     __shared__ double sh[BLOCK / 64];
-    const int p = blockIdx.x;
-    const Particle P = parts[p];
+    const int p = blockIdx.y;
+    const Particle &P = parts[p];
     const uint8_t me = static_cast<uint8_t>(PART0 + p);
     const Box bx = particle_box(g, P, 2);
     const uint32_t vol = static_cast<uint32_t>(bx.ext[0]) * bx.ext[1] * bx.ext[2];
     double acc[12] = {0};
-    for (uint32_t k = threadIdx.x; k < vol; k += BLOCK) {
+    for (uint32_t k = blockIdx.x * BLOCK + threadIdx.x; k < vol; k += PF_BLOCKS * BLOCK) {
         int x, y, z;
         box_cell(g, bx, k, x, y, z);
         const uint32_t n = x + static_cast<uint32_t>(g.nx) * (y + static_cast<uint32_t>(g.ny) * z);
@@ -1333,17 +1337,28 @@ __global__ __launch_bounds__(BLOCK) void particle_forces_kernel(Geom g, const ui
         link_forces<S>(g, mask, fv, tau, polymer, inv_scale, x, y, z, &P,
                        [me](uint8_t m) { return m == me; }, acc);
     }
-    double r[12];
-    for (int k = 0; k < 12; ++k)
-        r[k] = block_sum<BLOCK>(acc[k], sh);
-    if (threadIdx.x == 0) {
-        Particle &Q_ = parts[p];
-        for (int a = 0; a < 3; ++a) {
-            Q_.fmex[a] = r[a];
-            Q_.tmex[a] = r[3 + a];
-            Q_.ftau[a] = r[6 + a];
-            Q_.ttau[a] = r[9 + a];
-        }
+    for (int k = 0; k < 12; ++k) {
+        const double r = block_sum<BLOCK>(acc[k], sh);
+        if (threadIdx.x == 0)
+            partials[(static_cast<size_t>(p) * PF_BLOCKS + blockIdx.x) * 12 + k] = r;
+    }
+}
+
+__global__ void particle_forces_reduce_kernel(Particle *parts, const double *partials, int n_parts)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n_parts)
+        return;
+    double r[12] = {0};
+    for (int b = 0; b < PF_BLOCKS; ++b)
+        for (int k = 0; k < 12; ++k)
+            r[k] += partials[(static_cast<size_t>(p) * PF_BLOCKS + b) * 12 + k];
+    Particle &Q_ = parts[p];
+    for (int a = 0; a < 3; ++a) {
+        Q_.fmex[a] = r[a];
+        Q_.tmex[a] = r[3 + a];
+        Q_.ftau[a] = r[6 + a];
+        Q_.ttau[a] = r[9 + a];
     }
 }
 
@@ -1407,6 +1422,7 @@ __global__ void particle_update_kernel(Geom g, Particle *parts, int n_parts)
 // atomics; phases are separated by barriers.
 
 constexpr int CONV_THREADS = 1024;
+constexpr int CONV_CHECK_BLOCKS = 16;  // blocks per particle of the change check
 
 struct ConvCtx {
     Geom g;
@@ -1462,6 +1478,35 @@ __device__ int fluid_neighbours(const ConvCtx &c, const Nbr &nb)
     return nf;
 }
 
+// Does any cell change owner this step?  Many blocks per moving particle scan
+// its bounding box and raise flag[0]; the conversion kernel does nothing
+// unless it is raised (and clears it).
+__global__ __launch_bounds__(BLOCK) void conversion_check_kernel(Geom g, const Particle *parts,
+                                                                 const uint8_t *mask,
+                                                                 int32_t *flag)
+{
+    const int p = blockIdx.y;
+    const Particle &P = parts[p];
+    bool change = false;
+    if (P.movable) {
+        const uint8_t me = static_cast<uint8_t>(PART0 + p);
+        const Box bx = particle_box(g, P, 2);
+        const uint32_t vol = static_cast<uint32_t>(bx.ext[0]) * bx.ext[1] * bx.ext[2];
+        for (uint32_t k = blockIdx.x * BLOCK + threadIdx.x; k < vol; k += gridDim.x * BLOCK) {
+            int x, y, z;
+            box_cell(g, bx, k, x, y, z);
+            const uint8_t m =
+                mask[x + static_cast<uint32_t>(g.nx) * (y + static_cast<uint32_t>(g.ny) * z)];
+            if (m == 0)
+                change = change || inside_sphere(g, P, x, y, z);
+            else if (m == me)
+                change = change || !inside_sphere(g, P, x, y, z);
+        }
+    }
+    if (__syncthreads_or(change) && threadIdx.x == 0)
+        atomicOr(flag, 1);
+}
+
 template <int S>
 __global__ __launch_bounds__(CONV_THREADS) void conversion_kernel(Geom g, Bound b, uint8_t *mask,
                                                                   void *fv, float *tau, float scale,
@@ -1474,6 +1519,14 @@ __global__ __launch_bounds__(CONV_THREADS) void conversion_kernel(Geom g, Bound 
     __shared__ double sh[CONV_THREADS / 64];
     Particle *parts = const_cast<Particle *>(b.parts);
     T *f = static_cast<T *>(fv);
+    __shared__ int go;
+    if (threadIdx.x == 0) {
+        go = counters[3];
+        counters[3] = 0;
+    }
+    __syncthreads();
+    if (!go)
+        return;
     if (threadIdx.x == 0) {
         int k = 0;
         for (int p = 0; p < b.n_parts; ++p)
@@ -1873,15 +1926,21 @@ hipError_t launch_sums(int storage, const Geom &g, const uint8_t *mask, const vo
 
 hipError_t launch_particle_forces(int storage, const Geom &g, const uint8_t *mask, const void *f,
                                   const float *tau_n, int polymer, float inv_scale,
-                                  Particle *parts, int n_parts, hipStream_t s)
+                                  Particle *parts, int n_parts, double *partials, hipStream_t s)
 {
     if (n_parts <= 0)
         return hipSuccess;
-    return dispatch(storage, [&](auto st) {
-        hipLaunchKernelGGL(particle_forces_kernel<decltype(st)::value>, dim3(n_parts), dim3(BLOCK),
-                           0, s, g, mask, f, tau_n, polymer, inv_scale, parts);
+    hipError_t e = dispatch(storage, [&](auto st) {
+        hipLaunchKernelGGL(particle_forces_kernel<decltype(st)::value>, dim3(PF_BLOCKS, n_parts),
+                           dim3(BLOCK), 0, s, g, mask, f, tau_n, polymer, inv_scale, parts,
+                           partials);
         return hipGetLastError();
     });
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(particle_forces_reduce_kernel, dim3((n_parts + 63) / 64), dim3(64), 0, s,
+                       parts, partials, n_parts);
+    return hipGetLastError();
 }
 
 hipError_t launch_wall_force(int storage, const Geom &g, const uint8_t *mask, const void *f,
@@ -1913,6 +1972,13 @@ hipError_t launch_conversion(int storage, const Geom &g, const Bound &b, uint8_t
                              float *tau, float scale, float inv_scale, int32_t *counters,
                              hipStream_t s)
 {
+    if (b.n_parts > 0) {
+        hipLaunchKernelGGL(conversion_check_kernel, dim3(CONV_CHECK_BLOCKS, b.n_parts), dim3(BLOCK),
+                           0, s, g, b.parts, mask, counters + 3);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
     return dispatch(storage, [&](auto st) {
         hipLaunchKernelGGL(conversion_kernel<decltype(st)::value>, dim3(1), dim3(CONV_THREADS), 0,
                            s, g, b, mask, f, tau, scale, inv_scale, counters);
