@@ -47,6 +47,7 @@ def lib():
         L.or_set_params.restype = I
         L.or_set_params.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                     ctypes.c_double, D]
+        L.or_set_counter_force.argtypes = [P, I]
         L.or_init_equilibrium.argtypes = [P, D]
         L.or_set_populations.argtypes = [P, D]
         L.or_set_stress.argtypes = [P, D]
@@ -195,6 +196,9 @@ class Lattice:
         rc = lib().or_set_params(self._h, eta, beta, lambda_p, magic, _dp(_vec(body_force)))
         if rc != 0:
             raise ValueError("oracle: invalid parameters")
+
+    def set_counter_force(self, on=True):
+        lib().or_set_counter_force(self._h, 1 if on else 0)
 
     def init_equilibrium(self, u=None):
         if u is None:

@@ -359,6 +359,7 @@ struct or_lattice {
     double *wall_vel;
     int n_walls;
     double eta, beta, lambda, magic, g[3];
+    int counter_force;               /* -sum of the free particles' F_ext spread over the fluid */
     double wp, wm, eta_p;
     int polymer;
     double *f, *fnew, *fpost;
@@ -600,8 +601,41 @@ static void credit(or_lattice *L, unsigned char owner, int x, int y, int z, cons
     }
 }
 
-static void fluid_moments(const or_lattice *L, const double *f, const double *fp, long n,
-                          double *rho, double u[3])
+/* Body force density acting on the fluid.  With the counter-force switched
+ * on (Section 4.5, settling sphere in a periodic box), the external forces of
+ * the movable particles are taken back from the fluid, spread evenly over the
+ * cells that are fluid when the step starts, so that the total momentum of
+ * fluid and particles stays constant. */
+static void effective_g(const or_lattice *L, double g[3])
+{
+    for (int a = 0; a < 3; ++a)
+        g[a] = L->g[a];
+    if (!L->counter_force)
+        return;
+    double F[3] = {0.0, 0.0, 0.0};
+    int any = 0;
+    for (int p = 0; p < L->np; ++p) {
+        if (!L->p[p].movable)
+            continue;
+        any = 1;
+        for (int a = 0; a < 3; ++a)
+            F[a] += L->p[p].fext[a];
+    }
+    if (!any)
+        return;
+    long nf = 0;
+    for (long n = 0; n < L->N; ++n)
+        nf += L->mask[n] == 0;
+    if (nf == 0)
+        return;
+    for (int a = 0; a < 3; ++a)
+        g[a] -= F[a] / (double)nf;
+}
+
+void or_set_counter_force(or_lattice *L, int on) { L->counter_force = on ? 1 : 0; }
+
+static void fluid_moments(const or_lattice *L, const double *f, const double *fp, const double g[3],
+                          long n, double *rho, double u[3])
 {
     long N = L->N;
     double r = 0.0, j[3] = {0.0, 0.0, 0.0};
@@ -613,7 +647,7 @@ static void fluid_moments(const or_lattice *L, const double *f, const double *fp
     }
     *rho = r;
     for (int a = 0; a < 3; ++a)
-        u[a] = (j[a] + 0.5 * (L->g[a] + fp[a * N + n])) / r;
+        u[a] = (j[a] + 0.5 * (g[a] + fp[a * N + n])) / r;
 }
 
 static void conversion(or_lattice *L);
@@ -640,6 +674,8 @@ void or_step(or_lattice *L, long n_steps)
         else
             memset(L->fp, 0, sizeof(double) * 3 * N);
         /* S2 + S3: moments and collision on every fluid cell */
+        double geff[3];
+        effective_g(L, geff);
 #pragma omp parallel for schedule(static) num_threads(or_get_threads())
         for (long n = 0; n < N; ++n) {
             if (mask[n] != 0) {
@@ -652,7 +688,7 @@ void or_step(or_lattice *L, long n_steps)
             for (int i = 0; i < Q; ++i)
                 fin[i] = L->f[i * N + n];
             for (int a = 0; a < 3; ++a)
-                F[a] = L->g[a] + L->fp[a * N + n];
+                F[a] = geff[a] + L->fp[a * N + n];
             or_collide_cell(fin, F, L->wp, L->wm, fout, &rho, u);
             for (int i = 0; i < Q; ++i)
                 L->fpost[i * N + n] = fout[i];
@@ -974,10 +1010,12 @@ void or_read_velocity(const or_lattice *L, double *u)
 {
     long N = L->N;
     double *fp = current_force(L);
+    double g[3];
+    effective_g(L, g);
     for (long n = 0; n < N; ++n) {
         double r, un[3] = {0.0, 0.0, 0.0};
         if (L->mask[n] == 0)
-            fluid_moments(L, L->f, fp, n, &r, un);
+            fluid_moments(L, L->f, fp, g, n, &r, un);
         for (int a = 0; a < 3; ++a)
             u[a * N + n] = un[a];
     }

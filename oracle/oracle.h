@@ -60,6 +60,10 @@ void or_destroy(or_lattice *L);
 int or_set_params(or_lattice *L, double eta, double beta, double lambda_p, double magic,
                   const double g[3]);
 /* f = f^eq(1, u) on fluid cells (u = NULL: rest), tau = 0. */
+/* Counter-force (Section 4.5): when on, the summed external force of the
+ * movable particles is subtracted from the body force, spread evenly over
+ * the cells that are fluid at the start of each step. */
+void or_set_counter_force(or_lattice *L, int on);
 void or_init_equilibrium(or_lattice *L, const double *u);
 void or_set_populations(or_lattice *L, const double *f);
 void or_set_stress(or_lattice *L, const double *tau);
