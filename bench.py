@@ -137,27 +137,11 @@ def run_gpu(args):
                 step_achieved=step_achieved, alg=alg, health=health)
 
 
-def run_moving(args):
-    """The settling-sphere box (64x64x256, walls on every axis, one movable
-    sphere r = 6 of density ratio 1.5 under an external force -0.004 along z,
-    beta = 0.5, Wi = 1): the step with momentum exchange, the rigid-body
-    update and the fluid/solid conversion running every step."""
+def _time_lattice(lat, args, stream):
+    """ms per step (HIP events on the lattice's stream) and per-kernel-family
+    times of a second timed pass."""
     import torch
 
-    from paper_2009_12279_amd import inputs, vlb
-
-    torch.cuda.set_device(0)
-    stream = torch.cuda.current_stream(0)
-    shape = (64, 64, 256)
-    eta, r, F = 1.0 / 3.0, 6.0, 0.004
-    lam = r / (F / (6 * np.pi * eta * r))
-    mask = inputs.channel_mask(shape, wall_axes=(0, 1, 2))
-    lat = vlb.Lattice(shape, mask, (0, 0, 0), stream=stream.cuda_stream)
-    lat.set_params(eta=eta, beta=0.5, lambda_p=lam, magic=3.0 / 16.0)
-    lat.add_sphere(center=(31.5, 31.5, 191.5), radius=r, density_ratio=1.5, movable=True,
-                   f_ext=(0.0, 0.0, -F))
-    lat.set_check_interval(0)
-    lat.init_equilibrium()
     lat.step(args.warmup)
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -173,14 +157,64 @@ def run_moving(args):
     k_ms = {"stream_collide": lat.kernel_time_ms(0), "stress_update": lat.kernel_time_ms(1),
             "particles": lat.kernel_time_ms(2)}
     lat.set_timing(False)
+    return ms, {k: round(v, 5) for k, v in k_ms.items()}
+
+
+def run_moving(args):
+    """Moving boundaries: (1) the settling-sphere box (64x64x256, walls on
+    every axis, one movable sphere r = 6 of density ratio 1.5 under an
+    external force -0.004 along z, beta = 0.5, Wi = 1); (2) the paper's
+    rotating settling sphere at its largest box (periodic L = 240 = 30 R,
+    R = 8, eta_n = 1/6, eta_p = eta_n, lambda_p = 6000, F_z = -0.008 taken back
+    from the fluid, torque M_z = 0.07).  Momentum exchange, the rigid-body
+    update and the fluid/solid conversion run every step."""
+    import torch
+
+    from paper_2009_12279_amd import inputs, vlb
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream(0)
+    out = {}
+    # (1) closed box
+    shape = (64, 64, 256)
+    eta, r, F = 1.0 / 3.0, 6.0, 0.004
+    lam = r / (F / (6 * np.pi * eta * r))
+    mask = inputs.channel_mask(shape, wall_axes=(0, 1, 2))
+    lat = vlb.Lattice(shape, mask, (0, 0, 0), stream=stream.cuda_stream)
+    lat.set_params(eta=eta, beta=0.5, lambda_p=lam, magic=3.0 / 16.0)
+    lat.add_sphere(center=(31.5, 31.5, 191.5), radius=r, density_ratio=1.5, movable=True,
+                   f_ext=(0.0, 0.0, -F))
+    lat.set_check_interval(0)
+    lat.init_equilibrium()
+    ms, k_ms = _time_lattice(lat, args, stream)
     p = lat.particle(0)
     lat.close()
     N = int(np.prod(shape))
-    return dict(workload="settling sphere: 64x64x256 closed box, movable sphere r=6, density "
-                         "ratio 1.5, F_z=-0.004, beta=0.5, Wi=1 (lambda_p=%.0f)" % lam,
-                steps=args.steps, ms_per_step=round(ms, 4), mlups=round(N / (ms * 1e-3) / 1e6, 1),
-                kernel_ms={k: round(v, 5) for k, v in k_ms.items()},
-                sphere_z=round(float(p["pos"][2]), 4), sphere_vz=float(p["vel"][2]))
+    out["closed_box"] = dict(
+        workload="settling sphere: 64x64x256 closed box, movable sphere r=6, density ratio 1.5, "
+                 "F_z=-0.004, beta=0.5, Wi=1 (lambda_p=%.0f)" % lam,
+        ms_per_step=round(ms, 4), mlups=round(N / (ms * 1e-3) / 1e6, 1), kernel_ms=k_ms,
+        sphere_z=round(float(p["pos"][2]), 4), sphere_vz=float(p["vel"][2]))
+    # (2) periodic rotating settling sphere, counter-force
+    L = 240
+    shape = (L, L, L)
+    lat = vlb.Lattice(shape, None, (1, 1, 1), stream=stream.cuda_stream)
+    lat.set_params(eta=1.0 / 3.0, beta=0.5, lambda_p=6000.0, magic=3.0 / 16.0)
+    lat.add_sphere(center=(119.5, 119.7, 120.2), radius=8.0, density_ratio=1.0, movable=True,
+                   f_ext=(0.0, 0.0, -0.008), t_ext=(0.0, 0.0, 0.07))
+    lat.set_counter_force(True)
+    lat.set_check_interval(0)
+    lat.init_equilibrium()
+    ms, k_ms = _time_lattice(lat, args, stream)
+    p = lat.particle(0)
+    lat.close()
+    N = L ** 3
+    out["periodic_rotating_sphere"] = dict(
+        workload="rotating settling sphere: periodic 240^3 (L = 30 R), R=8, beta=0.5, "
+                 "lambda_p=6000, F_z=-0.008 with counter-force, M_z=0.07",
+        ms_per_step=round(ms, 4), mlups=round(N / (ms * 1e-3) / 1e6, 1), kernel_ms=k_ms,
+        sphere_vz=float(p["vel"][2]), sphere_wz=float(p["omega"][2]))
+    return out
 
 
 def run_cpu_baseline(args):
@@ -340,7 +374,7 @@ def main():
     ap.add_argument("--serving-k", type=int, default=50)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-moving", action="store_true",
-                    help="skip the settling-sphere (moving boundary) measurement")
+                    help="skip the moving-boundary (settling sphere) measurements")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (torch) so that hardware byte "
                          "counters can be scaled against a kernel of known traffic")

@@ -191,6 +191,13 @@ const char *vlb_last_error(const vlb_lattice *lat);
  * measured).  which: 0 = stream-collide, 1 = stress update, 2 = particles. */
 vlb_status vlb_set_timing(vlb_lattice *lat, int32_t on);
 
+/* Counter-force for periodic systems with free particles (Section 4.5):
+ * when on, every step subtracts the summed external force of the movable
+ * particles from the body force, spread evenly over the cells that are
+ * fluid when the step starts, so that fluid plus particle momentum stays
+ * constant.  Off by default; kept in checkpoints. */
+vlb_status vlb_set_counter_force(vlb_lattice *lat, int32_t on);
+
 /* Rounding of stored values (default VLB_ROUND_STOCHASTIC, seed 0x2009). */
 vlb_status vlb_set_rounding(vlb_lattice *lat, vlb_rounding mode, uint32_t seed);
 double vlb_kernel_time_ms(const vlb_lattice *lat, int32_t which);

@@ -96,6 +96,9 @@ struct vlb_lattice {
     Particle *d_parts = nullptr;
     double *d_partials = nullptr;
     double *d_pforce = nullptr;   // block sums of the obstacle forces
+    uint32_t *d_count = nullptr;  // fluid cells (counter-force)
+    double *d_g3 = nullptr;       // body force under counter-force
+    bool counter_force = false;
     double *d_out = nullptr;
     int32_t *d_counters = nullptr;
     int n_walls = 0;
@@ -245,7 +248,7 @@ void free_all(vlb_lattice *lat)
         (void)hipStreamSynchronize(lat->stream);
     void *ptrs[] = {lat->d_mask,  lat->d_f[0],     lat->d_f[1],   lat->d_tau[0],     lat->d_tau[1],
                     lat->d_u,     lat->d_wall,     lat->d_parts,  lat->d_partials,   lat->d_out,
-                    lat->d_counters, lat->d_pforce};
+                    lat->d_counters, lat->d_pforce, lat->d_count, lat->d_g3};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -438,6 +441,12 @@ vlb_status vlb_create(const vlb_dims *dims, const uint8_t *mask, const double *w
     if ((e = hipMalloc(&lat->d_pforce, static_cast<size_t>(vlb::MAX_PARTICLES) * vlb::PF_BLOCKS *
                                             12 * sizeof(double))) != hipSuccess)
         return bail(e, "particle force sums");
+    if ((e = hipMalloc(&lat->d_count, sizeof(uint32_t))) != hipSuccess)
+        return bail(e, "fluid count");
+    if ((e = hipMemsetAsync(lat->d_count, 0, sizeof(uint32_t), lat->stream)) != hipSuccess)
+        return bail(e, "fluid count");
+    if ((e = hipMalloc(&lat->d_g3, 3 * sizeof(double))) != hipSuccess)
+        return bail(e, "body force");
     if ((e = hipMalloc(&lat->d_counters, 4 * sizeof(int32_t))) != hipSuccess)
         return bail(e, "counters");
     if ((e = hipMemsetAsync(lat->d_counters, 0, 4 * sizeof(int32_t), lat->stream)) != hipSuccess)
@@ -658,6 +667,14 @@ vlb_status vlb_step(vlb_lattice *lat, int64_t n_steps)
     a.wm = lat->wm;
     for (int k = 0; k < 3; ++k)
         a.g3[k] = lat->params.body_force[k];
+    const bool counter = lat->counter_force && lat->any_movable;
+    a.g3_dev = counter ? lat->d_g3 : nullptr;
+    const int n_parts = static_cast<int>(lat->parts_h.size());
+    if (counter && n_steps > 0)
+        HIPCHK(lat, vlb::launch_body_force(lat->g, lat->d_mask, lat->d_parts, n_parts,
+                                           lat->params.body_force, lat->d_count, lat->d_g3,
+                                           lat->stream),
+               "counter-force");
     a.polymer = lat->polymer;
     if (lat->polymer) {
         a.eta_p_lam = lat->params.beta * lat->params.eta / lat->params.lambda_p;
@@ -716,6 +733,11 @@ vlb_status vlb_step(vlb_lattice *lat, int64_t n_steps)
                                                a.tout, lat->scale, lat->inv_scale,
                                                lat->d_counters, lat->stream),
                    "conversion");
+            if (counter)
+                HIPCHK(lat, vlb::launch_body_force(lat->g, lat->d_mask, lat->d_parts, n_parts,
+                                                   lat->params.body_force, lat->d_count,
+                                                   lat->d_g3, lat->stream),
+                       "counter-force");
             lat->mask_h_valid = false;
         }
         if (ev)
@@ -757,15 +779,48 @@ vlb_status vlb_sync(vlb_lattice *lat)
 
 int64_t vlb_step_count(const vlb_lattice *lat) { return lat ? lat->step : -1; }
 
+// Body force seen by the next step, as floats for the moment readout: the
+// counter-force takes the movable particles' external forces back from the
+// cells that are fluid now.
+vlb_status read_body_force(vlb_lattice *lat, float gv[3])
+{
+    double g[3] = {lat->params.body_force[0], lat->params.body_force[1],
+                   lat->params.body_force[2]};
+    if (lat->counter_force && lat->any_movable) {
+        vlb_status st = sync_mask_host(lat);
+        if (st != VLB_OK)
+            return st;
+        double F[3] = {0.0, 0.0, 0.0};
+        bool any = false;
+        for (const Particle &P : lat->parts_h) {
+            if (!P.movable)
+                continue;
+            any = true;
+            for (int a = 0; a < 3; ++a)
+                F[a] += P.fext[a];
+        }
+        uint64_t nf = 0;
+        for (uint8_t m : lat->mask_h)
+            nf += m == 0;
+        if (any && nf)
+            for (int a = 0; a < 3; ++a)
+                g[a] -= F[a] / static_cast<double>(nf);
+    }
+    for (int a = 0; a < 3; ++a)
+        gv[a] = static_cast<float>(g[a]);
+    return VLB_OK;
+}
+
 vlb_status vlb_read_density(vlb_lattice *lat, double *rho)
 {
     if (!lat)
         return VLB_EINVAL;
     if (!rho)
         return fail(lat, VLB_EINVAL, "vlb_read_density: NULL output");
-    const float gv[3] = {static_cast<float>(lat->params.body_force[0]),
-                         static_cast<float>(lat->params.body_force[1]),
-                         static_cast<float>(lat->params.body_force[2])};
+    float gv[3];
+    vlb_status gst = read_body_force(lat, gv);
+    if (gst != VLB_OK)
+        return gst;
     return read_via_scratch(
         lat, static_cast<size_t>(lat->g.N) * sizeof(double), rho,
         [&](double *d) {
@@ -782,9 +837,10 @@ vlb_status vlb_read_velocity(vlb_lattice *lat, double *u)
         return VLB_EINVAL;
     if (!u)
         return fail(lat, VLB_EINVAL, "vlb_read_velocity: NULL output");
-    const float gv[3] = {static_cast<float>(lat->params.body_force[0]),
-                         static_cast<float>(lat->params.body_force[1]),
-                         static_cast<float>(lat->params.body_force[2])};
+    float gv[3];
+    vlb_status gst = read_body_force(lat, gv);
+    if (gst != VLB_OK)
+        return gst;
     return read_via_scratch(
         lat, 3 * static_cast<size_t>(lat->g.N) * sizeof(double), u,
         [&](double *d) {
@@ -950,7 +1006,7 @@ vlb_status vlb_set_check_interval(vlb_lattice *lat, int64_t steps)
 // checkpoint
 
 namespace {
-constexpr uint64_t kMagic = 0x32304B434C424C56ull;  // "VLBLCK02"
+constexpr uint64_t kMagic = 0x33304B434C424C56ull;  // "VLBLCK03"
 
 struct FileHeader {
     uint64_t magic;
@@ -962,6 +1018,8 @@ struct FileHeader {
     int32_t any_movable;
     int32_t rounding;  // vlb_rounding of stored values
     uint32_t seed;     // seed of the stochastic-rounding stream
+    int32_t counter_force;
+    int32_t reserved;
 };
 }  // namespace
 
@@ -1016,6 +1074,7 @@ vlb_status vlb_save(vlb_lattice *lat, const char *path)
     h.any_movable = lat->any_movable;
     h.rounding = lat->rounding;
     h.seed = lat->seed;
+    h.counter_force = lat->counter_force ? 1 : 0;
     bool ok = std::fwrite(&h, sizeof h, 1, fp) == 1;
     ok = ok && std::fwrite(lat->wall_h.data(), sizeof(double), 64 * 3, fp) == 64 * 3;
     ok = ok && (parts.empty() || std::fwrite(parts.data(), sizeof(Particle), parts.size(), fp) ==
@@ -1094,6 +1153,7 @@ vlb_status vlb_load(const char *path, void *stream, vlb_lattice **out)
     lat->step = h.step;
     lat->rounding = h.rounding == VLB_ROUND_NEAREST ? VLB_ROUND_NEAREST : VLB_ROUND_STOCHASTIC;
     lat->seed = h.seed;
+    lat->counter_force = h.counter_force != 0;
     lat->scale = h.scale;
     lat->inv_scale = 1.f / h.scale;
     hipError_t e = hipMemcpyAsync(lat->d_mask, mask.data(), N, hipMemcpyHostToDevice, lat->stream);
@@ -1131,6 +1191,14 @@ void vlb_destroy(vlb_lattice *lat)
 const char *vlb_last_error(const vlb_lattice *lat)
 {
     return lat ? lat->err.c_str() : g_create_error.c_str();
+}
+
+vlb_status vlb_set_counter_force(vlb_lattice *lat, int32_t on)
+{
+    if (!lat)
+        return VLB_EINVAL;
+    lat->counter_force = on != 0;
+    return VLB_OK;
 }
 
 vlb_status vlb_set_rounding(vlb_lattice *lat, vlb_rounding mode, uint32_t seed)

@@ -82,6 +82,7 @@ struct StepArgs {
     float *u_p[3];
     double wp, wm;           // omega+, omega-
     double g3[3];            // body force density
+    const double *g3_dev;    // body force read on the device instead (counter-force), or null
     double eta_p_lam, inv_lam;
     float scale, inv_scale;  // storage scale s and 1/s
     int32_t polymer;
@@ -111,6 +112,12 @@ struct BatchTable {
 };
 
 // Host-side launchers (vlb_kernels.hip).
+// Counter-force: count the cells that are fluid now into *count, then
+// g_out = g - (sum of the movable particles' F_ext) / count (g when none is
+// movable), resetting *count.
+hipError_t launch_body_force(const Geom &g, const uint8_t *mask, const Particle *parts,
+                             int n_parts, const double body_force[3], uint32_t *count,
+                             double *g_out, hipStream_t s);
 hipError_t launch_lb_step(int storage, const StepArgs &a, hipStream_t s);
 // n_steps batched steps (stream-collide, stress update, counter advance per
 // step) over every solve of the table; grid of max_blocks blocks.

@@ -532,9 +532,20 @@ __device__ __forceinline__ void lb_cell(const A &a, uint32_t n, uint32_t step)
             }
         }
     }
-    const R Fx = static_cast<R>(a.g3[0]) + static_cast<R>(Fp[0]);
-    const R Fy = static_cast<R>(a.g3[1]) + static_cast<R>(Fp[1]);
-    const R Fz = static_cast<R>(a.g3[2]) + static_cast<R>(Fp[2]);
+    // body force: the device value under the counter-force (uniform branch)
+    double g3[3];
+    if (a.g3_dev) {
+        g3[0] = a.g3_dev[0];
+        g3[1] = a.g3_dev[1];
+        g3[2] = a.g3_dev[2];
+    } else {
+        g3[0] = a.g3[0];
+        g3[1] = a.g3[1];
+        g3[2] = a.g3[2];
+    }
+    const R Fx = static_cast<R>(g3[0]) + static_cast<R>(Fp[0]);
+    const R Fy = static_cast<R>(g3[1]) + static_cast<R>(Fp[1]);
+    const R Fz = static_cast<R>(g3[2]) + static_cast<R>(Fp[2]);
 
     // moments in deviation form from opposite-pair sums and differences:
     // rho = 1 + h_0 + sum (h_i + h_o), rho u = sum c_i (h_i - h_o) + F/2
@@ -757,6 +768,57 @@ __global__ __launch_bounds__(BLOCK) FV_OCCUPANCY void fv_step_kernel(StepArgs a)
     if (n >= a.g.N)
         return;
     fv_cell<SR>(a, n, a.step);
+}
+
+// ---------------------------------------------------------------------------
+// Counter-force for periodic systems with free particles (Section 4.5): the
+// fluid cells are counted at the start of the step, then the movable
+// particles' external forces are spread evenly over them.
+
+__global__ __launch_bounds__(BLOCK) void fluid_count_kernel(Geom g, const uint8_t *mask,
+                                                            uint32_t *count)
+{
+    // 16 mask bytes per load (the mask allocation is 256-byte aligned); the
+    // last N % 16 bytes by the first thread
+    const uint32_t nvec = g.N / 16u;
+    const uint4 *m4 = reinterpret_cast<const uint4 *>(mask);
+    uint32_t c = 0;
+    for (uint32_t k = blockIdx.x * BLOCK + threadIdx.x; k < nvec; k += gridDim.x * BLOCK) {
+        const uint4 v = m4[k];
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                c += ((w[q] >> (8 * b)) & 0xffu) == 0u ? 1u : 0u;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        for (uint32_t n = nvec * 16u; n < g.N; ++n)
+            c += mask[n] == 0 ? 1u : 0u;
+    // integer sums: the result does not depend on the order
+    for (int off = 32; off > 0; off >>= 1)
+        c += __shfl_down(c, off, 64);
+    if ((threadIdx.x & 63) == 0 && c)
+        atomicAdd(count, c);
+}
+
+__global__ void body_force_kernel(const Particle *parts, int n_parts, double g0, double g1,
+                                  double g2, uint32_t *count, double *g_out)
+{
+    double F[3] = {0.0, 0.0, 0.0};
+    bool any = false;
+    for (int p = 0; p < n_parts; ++p) {
+        if (!parts[p].movable)
+            continue;
+        any = true;
+        for (int a = 0; a < 3; ++a)
+            F[a] += parts[p].fext[a];
+    }
+    const uint32_t nf = *count;
+    const double g[3] = {g0, g1, g2};
+    for (int a = 0; a < 3; ++a)
+        g_out[a] = (any && nf) ? g[a] - F[a] / static_cast<double>(nf) : g[a];
+    *count = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1803,7 +1865,9 @@ hipError_t launch_fv_step(int storage, const StepArgs &a, hipStream_t s, int til
     uint32_t zc = z_chunk ? z_chunk : 16u;
     while (!force && zc > 4 && tiles_xy * ((a.g.nz + zc - 1) / zc) < 2048)
         zc /= 2;
-    const bool rows_fill = a.g.nx % FV_TX == 0 || a.g.nx >= 4 * FV_TX;
+    // at most an eighth of the tile lanes beyond the end of the rows
+    const uint32_t lanes_x = ((a.g.nx + FV_TX - 1) / FV_TX) * FV_TX;
+    const bool rows_fill = 8u * (lanes_x - a.g.nx) <= lanes_x;
     if ((tile_rows == 4 || tile_rows == 8) &&
         (force || (rows_fill && tiles_xy * ((a.g.nz + zc - 1) / zc) >= 1024))) {
         const uint32_t tiles = tiles_xy * ((a.g.nz + zc - 1) / zc);
@@ -1956,6 +2020,21 @@ hipError_t launch_wall_force(int storage, const Geom &g, const uint8_t *mask, co
     if (e != hipSuccess)
         return e;
     hipLaunchKernelGGL(sums_final_kernel, dim3(1), dim3(BLOCK), 0, s, partials, nb, 3, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_body_force(const Geom &g, const uint8_t *mask, const Particle *parts,
+                             int n_parts, const double body_force[3], uint32_t *count,
+                             double *g_out, hipStream_t s)
+{
+    const uint32_t vec_blocks = blocks_for(g.N / 16u + 1u);
+    const uint32_t blocks = vec_blocks < 1024u ? vec_blocks : 1024u;
+    hipLaunchKernelGGL(fluid_count_kernel, dim3(blocks), dim3(BLOCK), 0, s, g, mask, count);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(body_force_kernel, dim3(1), dim3(1), 0, s, parts, n_parts, body_force[0],
+                       body_force[1], body_force[2], count, g_out);
     return hipGetLastError();
 }
 

@@ -96,6 +96,7 @@ SIGNATURES = [
     ("vlb_set_timing", ctypes.c_int, [_P, ctypes.c_int32]),
     ("vlb_kernel_time_ms", ctypes.c_double, [_P, ctypes.c_int32]),
     ("vlb_set_rounding", ctypes.c_int, [_P, ctypes.c_int, ctypes.c_uint32]),
+    ("vlb_set_counter_force", ctypes.c_int, [_P, ctypes.c_int32]),
     ("vlb_server_create", ctypes.c_int, [ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32, _P,
                                          ctypes.POINTER(_P)]),
     ("vlb_server_set_rounding", ctypes.c_int, [_P, ctypes.c_int]),
@@ -322,6 +323,10 @@ def vlb_kernel_time_ms(h, which):
 ROUNDING = {"nearest": 0, "stochastic": 1}
 
 
+def vlb_set_counter_force(h, on=True):
+    return _check(lib().vlb_set_counter_force(h, 1 if on else 0), h)
+
+
 def vlb_set_rounding(h, mode="stochastic", seed=0x2009):
     return _check(lib().vlb_set_rounding(h, ROUNDING[mode], int(seed) & 0xFFFFFFFF), h)
 
@@ -434,6 +439,9 @@ class Lattice:
 
     def set_rounding(self, mode="stochastic", seed=0x2009):
         vlb_set_rounding(self._h, mode, seed)
+
+    def set_counter_force(self, on=True):
+        vlb_set_counter_force(self._h, on)
 
 
 # ---- serving ------------------------------------------------------------------
