@@ -48,6 +48,8 @@ def lib():
         L.or_set_params.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                     ctypes.c_double, D]
         L.or_set_counter_force.argtypes = [P, I]
+        L.or_set_giesekus.restype = I
+        L.or_set_giesekus.argtypes = [P, ctypes.c_double]
         L.or_init_equilibrium.argtypes = [P, D]
         L.or_set_populations.argtypes = [P, D]
         L.or_set_stress.argtypes = [P, D]
@@ -73,7 +75,7 @@ def lib():
         L.or_collide_cell.argtypes = [D, D, ctypes.c_double, ctypes.c_double, D, D, D]
         L.or_rates.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, D, D]
         L.or_fv_apply.argtypes = [I, I, I, ctypes.c_char_p, D, D, ctypes.c_double,
-                                  ctypes.c_double, D]
+                                  ctypes.c_double, ctypes.c_double, D]
         L.or_polymer_force.argtypes = [I, I, I, ctypes.c_char_p, D, D]
         L.or_set_threads.argtypes = [I]
         L.or_get_threads.restype = I
@@ -130,8 +132,9 @@ def rates(eta, beta, magic):
     return a.value, b.value
 
 
-def fv_apply(mask, tau, u, eta_p, lambda_p):
-    """One finite-volume stress update with a prescribed velocity field.
+def fv_apply(mask, tau, u, eta_p, lambda_p, alpha=0.0):
+    """One finite-volume stress update with a prescribed velocity field
+    (alpha > 0: Giesekus source term).
 
     mask: uint8 [nz, ny, nx]; tau: [6, nz, ny, nx]; u: [3, nz, ny, nx]."""
     nz, ny, nx = mask.shape
@@ -140,7 +143,7 @@ def fv_apply(mask, tau, u, eta_p, lambda_p):
     uu = np.ascontiguousarray(u, dtype=np.float64)
     out = np.zeros_like(t)
     lib().or_fv_apply(nx, ny, nz, m.tobytes(), _dp(t), _dp(uu), float(eta_p), float(lambda_p),
-                      _dp(out))
+                      float(alpha), _dp(out))
     return out
 
 
@@ -199,6 +202,10 @@ class Lattice:
 
     def set_counter_force(self, on=True):
         lib().or_set_counter_force(self._h, 1 if on else 0)
+
+    def set_giesekus(self, alpha):
+        if lib().or_set_giesekus(self._h, float(alpha)) != 0:
+            raise ValueError("oracle: Giesekus mobility must lie in [0, 1/2]")
 
     def init_equilibrium(self, u=None):
         if u is None:

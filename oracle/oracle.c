@@ -277,7 +277,7 @@ static double face_overlap(const double u[3], const int e[3])
 }
 
 void or_fv_apply(int nx, int ny, int nz, const unsigned char *mask, const double *tau_in,
-                 const double *u, double eta_p, double lambda_p, double *tau_out)
+                 const double *u, double eta_p, double lambda_p, double alpha, double *tau_out)
 {
     long N = (long)nx * ny * nz;
 #pragma omp parallel for schedule(static) num_threads(or_get_threads())
@@ -310,6 +310,17 @@ void or_fv_apply(int nx, int ny, int nz, const unsigned char *mask, const double
                         for (int k = 0; k < 3; ++k)
                             s += t[i][k] * G[k][j] + t[k][j] * G[k][i];
                         s += eta_p / lambda_p * (G[i][j] + G[j][i]) - t[i][j] / lambda_p;
+                        /* Giesekus (Section 2.2 lists it among the models the
+                         * scheme extends to): the quadratic relaxation term
+                         * -(alpha / eta_p) (tau . tau) of tau + lambda tau^del
+                         * + (alpha lambda / eta_p) tau . tau = eta_p (grad u +
+                         * grad u^T); alpha = 0 is Oldroyd-B */
+                        if (alpha != 0.0) {
+                            double tt = 0.0;
+                            for (int k = 0; k < 3; ++k)
+                                tt += t[i][k] * t[k][j];
+                            s -= alpha / eta_p * tt;
+                        }
                         S[i][j] = s;
                     }
                 /* face fluxes: what leaves through each fluid face minus what enters */
@@ -360,6 +371,7 @@ struct or_lattice {
     int n_walls;
     double eta, beta, lambda, magic, g[3];
     int counter_force;               /* -sum of the free particles' F_ext spread over the fluid */
+    double alpha;                    /* Giesekus mobility (0: Oldroyd-B) */
     double wp, wm, eta_p;
     int polymer;
     double *f, *fnew, *fpost;
@@ -634,6 +646,14 @@ static void effective_g(const or_lattice *L, double g[3])
 
 void or_set_counter_force(or_lattice *L, int on) { L->counter_force = on ? 1 : 0; }
 
+int or_set_giesekus(or_lattice *L, double alpha)
+{
+    if (!(alpha >= 0.0 && alpha <= 0.5))
+        return -1;
+    L->alpha = alpha;
+    return 0;
+}
+
 static void fluid_moments(const or_lattice *L, const double *f, const double *fp, const double g[3],
                           long n, double *rho, double u[3])
 {
@@ -763,7 +783,7 @@ void or_step(or_lattice *L, long n_steps)
                 }
         /* S5: finite-volume stress update with tau^n and u^n */
         if (L->polymer)
-            or_fv_apply(nx, ny, nz, mask, L->tau, L->u, L->eta_p, L->lambda, L->taunew);
+            or_fv_apply(nx, ny, nz, mask, L->tau, L->u, L->eta_p, L->lambda, L->alpha, L->taunew);
         else
             memset(L->taunew, 0, sizeof(double) * 6 * N);
         /* S6: particles, symplectic Euler */

@@ -45,9 +45,10 @@ void or_rates(double eta, double beta, double magic, double *omega_plus, double 
 /* One explicit finite-volume update of the stress (Section 3.3) with a
  * prescribed velocity field u (3*N; at solid cells it is the boundary
  * velocity).  tau_out = tau_in + fluxes + source on fluid cells; solid cells
- * copy tau_in. */
+ * copy tau_in.  alpha > 0 adds the Giesekus term -(alpha/eta_p) tau.tau to
+ * the source. */
 void or_fv_apply(int nx, int ny, int nz, const unsigned char *mask, const double *tau_in,
-                 const double *u, double eta_p, double lambda_p, double *tau_out);
+                 const double *u, double eta_p, double lambda_p, double alpha, double *tau_out);
 
 /* The discrete polymer force of Section 3.3 for a stress field (fluid cells). */
 void or_polymer_force(int nx, int ny, int nz, const unsigned char *mask, const double *tau,
@@ -64,6 +65,9 @@ int or_set_params(or_lattice *L, double eta, double beta, double lambda_p, doubl
  * movable particles is subtracted from the body force, spread evenly over
  * the cells that are fluid at the start of each step. */
 void or_set_counter_force(or_lattice *L, int on);
+/* Giesekus model with mobility alpha in [0, 1/2] (0 = Oldroyd-B, the
+ * default); -1 for alpha out of range. */
+int or_set_giesekus(or_lattice *L, double alpha);
 void or_init_equilibrium(or_lattice *L, const double *u);
 void or_set_populations(or_lattice *L, const double *f);
 void or_set_stress(or_lattice *L, const double *tau);

@@ -180,3 +180,48 @@ def test_polymer_force_telescopes_to_boundary_faces(orc):
             if mask[p[2], p[1], p[0]]:
                 expect += s * t[a, :, zz, yy, xx]
     np.testing.assert_allclose(total, expect, rtol=1e-12, atol=1e-12)
+
+
+def test_giesekus_steady_shear_matches_the_constitutive_equations(orc):
+    """Giesekus (Section 2.2 names it among the models the scheme extends
+    to): in steady simple shear u_x = g y the stress solves the algebraic
+    equations that tau + lam tau^del + (alpha lam / eta_p) tau.tau =
+    eta_p (grad u + grad u^T) reduces to, written out by component:
+        xx: t_xx - 2 W t_xy + a (t_xx^2 + t_xy^2) = 0
+        yy: t_yy + a (t_xy^2 + t_yy^2) = 0
+        xy: t_xy - W t_yy + a t_xy (t_xx + t_yy) = W,   t_zz = 0,
+    with tau = (eta_p / lam) t and W = lam g.  The explicit FV update with a
+    prescribed shear relaxes to that solution; alpha = 0 stays Oldroyd-B
+    and alpha > 0 thins the shear stress and turns tau_yy negative."""
+    from scipy.optimize import fsolve
+
+    nx, ny, nz = 3, 12, 3
+    mask = np.zeros((nz, ny, nx), np.uint8)
+    mask[:, 0, :] = 1
+    mask[:, -1, :] = 1
+    gam, eta_p, lam = 2e-3, 0.25, 400.0
+    W = lam * gam
+    u = np.zeros((3, nz, ny, nx))
+    u[0] = (gam * np.arange(ny, dtype=float))[None, :, None]
+    for a in (0.0, 0.1, 0.3, 0.5):
+        def eqs(v):
+            txx, tyy, txy = v
+            return [txx - 2 * W * txy + a * (txx ** 2 + txy ** 2),
+                    tyy + a * (txy ** 2 + tyy ** 2),
+                    txy - W * tyy + a * txy * (txx + tyy) - W]
+        sol = fsolve(eqs, [2 * W * W, 0.0, W], xtol=1e-12)
+        assert np.max(np.abs(eqs(sol))) < 1e-12
+        expect = eta_p / lam * sol
+        tau = np.zeros((6, nz, ny, nx))
+        for _ in range(12000):
+            tau = orc.fv_apply(mask, tau, u, eta_p, lam, alpha=a)
+        inner = tau[:, :, 2:-2, :]
+        np.testing.assert_allclose(inner[0], expect[0], rtol=1e-9)
+        np.testing.assert_allclose(inner[1], expect[1], rtol=1e-9, atol=1e-15)
+        np.testing.assert_allclose(inner[3], expect[2], rtol=1e-9)
+        np.testing.assert_allclose(inner[[2, 4, 5]], 0.0, atol=1e-30)
+        if a == 0.0:
+            np.testing.assert_allclose(expect, [2 * lam * eta_p * gam ** 2, 0.0, eta_p * gam],
+                                       rtol=1e-12, atol=1e-20)
+        else:
+            assert expect[2] < eta_p * gam and expect[1] < 0
