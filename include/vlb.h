@@ -191,6 +191,13 @@ const char *vlb_last_error(const vlb_lattice *lat);
  * measured).  which: 0 = stream-collide, 1 = stress update, 2 = particles. */
 vlb_status vlb_set_timing(vlb_lattice *lat, int32_t on);
 
+/* Giesekus constitutive law (Section 2.2 names it among the models the
+ * method extends to): the stress update's source gains -(alpha / eta_p)
+ * tau.tau, from tau + lambda tau^del + (alpha lambda / eta_p) tau.tau =
+ * eta_p (grad u + grad u^T).  alpha in [0, 1/2] (VLB_EINVAL otherwise);
+ * 0, the default, is Oldroyd-B.  Kept in checkpoints. */
+vlb_status vlb_set_giesekus(vlb_lattice *lat, double alpha);
+
 /* Counter-force for periodic systems with free particles (Section 4.5):
  * when on, every step subtracts the summed external force of the movable
  * particles from the body force, spread evenly over the cells that are

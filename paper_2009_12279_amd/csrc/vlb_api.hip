@@ -99,6 +99,7 @@ struct vlb_lattice {
     uint32_t *d_count = nullptr;  // fluid cells (counter-force)
     double *d_g3 = nullptr;       // body force under counter-force
     bool counter_force = false;
+    double alpha = 0.0;           // Giesekus mobility
     double *d_out = nullptr;
     int32_t *d_counters = nullptr;
     int n_walls = 0;
@@ -679,6 +680,7 @@ vlb_status vlb_step(vlb_lattice *lat, int64_t n_steps)
     if (lat->polymer) {
         a.eta_p_lam = lat->params.beta * lat->params.eta / lat->params.lambda_p;
         a.inv_lam = 1.0 / lat->params.lambda_p;
+        a.gk = static_cast<float>(lat->alpha / (lat->params.beta * lat->params.eta));
     }
     a.stochastic = lat->rounding == VLB_ROUND_STOCHASTIC ? 1 : 0;
     a.seed = lat->seed;
@@ -1006,7 +1008,7 @@ vlb_status vlb_set_check_interval(vlb_lattice *lat, int64_t steps)
 // checkpoint
 
 namespace {
-constexpr uint64_t kMagic = 0x33304B434C424C56ull;  // "VLBLCK03"
+constexpr uint64_t kMagic = 0x34304B434C424C56ull;  // "VLBLCK04"
 
 struct FileHeader {
     uint64_t magic;
@@ -1020,6 +1022,7 @@ struct FileHeader {
     uint32_t seed;     // seed of the stochastic-rounding stream
     int32_t counter_force;
     int32_t reserved;
+    double alpha;
 };
 }  // namespace
 
@@ -1075,6 +1078,7 @@ vlb_status vlb_save(vlb_lattice *lat, const char *path)
     h.rounding = lat->rounding;
     h.seed = lat->seed;
     h.counter_force = lat->counter_force ? 1 : 0;
+    h.alpha = lat->alpha;
     bool ok = std::fwrite(&h, sizeof h, 1, fp) == 1;
     ok = ok && std::fwrite(lat->wall_h.data(), sizeof(double), 64 * 3, fp) == 64 * 3;
     ok = ok && (parts.empty() || std::fwrite(parts.data(), sizeof(Particle), parts.size(), fp) ==
@@ -1154,6 +1158,7 @@ vlb_status vlb_load(const char *path, void *stream, vlb_lattice **out)
     lat->rounding = h.rounding == VLB_ROUND_NEAREST ? VLB_ROUND_NEAREST : VLB_ROUND_STOCHASTIC;
     lat->seed = h.seed;
     lat->counter_force = h.counter_force != 0;
+    lat->alpha = (h.alpha >= 0.0 && h.alpha <= 0.5) ? h.alpha : 0.0;
     lat->scale = h.scale;
     lat->inv_scale = 1.f / h.scale;
     hipError_t e = hipMemcpyAsync(lat->d_mask, mask.data(), N, hipMemcpyHostToDevice, lat->stream);
@@ -1191,6 +1196,16 @@ void vlb_destroy(vlb_lattice *lat)
 const char *vlb_last_error(const vlb_lattice *lat)
 {
     return lat ? lat->err.c_str() : g_create_error.c_str();
+}
+
+vlb_status vlb_set_giesekus(vlb_lattice *lat, double alpha)
+{
+    if (!lat)
+        return VLB_EINVAL;
+    if (!(alpha >= 0.0 && alpha <= 0.5))
+        return fail(lat, VLB_EINVAL, "vlb_set_giesekus: alpha must lie in [0, 1/2]");
+    lat->alpha = alpha;
+    return VLB_OK;
 }
 
 vlb_status vlb_set_counter_force(vlb_lattice *lat, int32_t on)

@@ -85,6 +85,7 @@ struct StepArgs {
     const double *g3_dev;    // body force read on the device instead (counter-force), or null
     double eta_p_lam, inv_lam;
     float scale, inv_scale;  // storage scale s and 1/s
+    float gk;                // Giesekus alpha / eta_p (0: Oldroyd-B)
     int32_t polymer;
     int32_t remap;           // XCD-aware block order (0 off, 1 ranges, 2 y-slabs)
     uint32_t slab_blocks;    // remap 2: blocks per XCD per z-plane

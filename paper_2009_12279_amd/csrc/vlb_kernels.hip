@@ -708,6 +708,7 @@ __device__ __forceinline__ void fv_compute(const A &a, const Geom &g, uint32_t n
     const int PI[6] = {0, 1, 2, 0, 0, 1};
     const int PJ[6] = {0, 1, 2, 1, 2, 2};
     const float epl = static_cast<float>(a.eta_p_lam), il = static_cast<float>(a.inv_lam);
+    const float gk = a.gk;
     Rng rng(n, step, a.seed ^ 0x5bd1e995u);
     uint32_t r = 0;
 #pragma unroll
@@ -717,7 +718,15 @@ __device__ __forceinline__ void fv_compute(const A &a, const Geom &g, uint32_t n
 #pragma unroll
         for (int k = 0; k < 3; ++k)
             sdot += T3[i][k] * G[k][j] + T3[k][j] * G[k][i];
-        const float inc = in_sum[c] - out_tot * t0[c] + sdot + epl * (G[i][j] + G[j][i]) - t0[c] * il;
+        float inc = in_sum[c] - out_tot * t0[c] + sdot + epl * (G[i][j] + G[j][i]) - t0[c] * il;
+        if (gk != 0.f) {
+            // Giesekus: -(alpha / eta_p) (tau . tau)_ij
+            float tt = 0.f;
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                tt += T3[i][k] * T3[k][j];
+            inc -= gk * tt;
+        }
         const double v = static_cast<double>(t0[c]) + static_cast<double>(inc);
         if (!(c & 1))
             r = rng.next32();

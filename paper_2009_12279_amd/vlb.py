@@ -97,6 +97,7 @@ SIGNATURES = [
     ("vlb_kernel_time_ms", ctypes.c_double, [_P, ctypes.c_int32]),
     ("vlb_set_rounding", ctypes.c_int, [_P, ctypes.c_int, ctypes.c_uint32]),
     ("vlb_set_counter_force", ctypes.c_int, [_P, ctypes.c_int32]),
+    ("vlb_set_giesekus", ctypes.c_int, [_P, ctypes.c_double]),
     ("vlb_server_create", ctypes.c_int, [ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32, _P,
                                          ctypes.POINTER(_P)]),
     ("vlb_server_set_rounding", ctypes.c_int, [_P, ctypes.c_int]),
@@ -323,6 +324,10 @@ def vlb_kernel_time_ms(h, which):
 ROUNDING = {"nearest": 0, "stochastic": 1}
 
 
+def vlb_set_giesekus(h, alpha):
+    return _check(lib().vlb_set_giesekus(h, float(alpha)), h)
+
+
 def vlb_set_counter_force(h, on=True):
     return _check(lib().vlb_set_counter_force(h, 1 if on else 0), h)
 
@@ -442,6 +447,9 @@ class Lattice:
 
     def set_counter_force(self, on=True):
         vlb_set_counter_force(self._h, on)
+
+    def set_giesekus(self, alpha):
+        vlb_set_giesekus(self._h, alpha)
 
 
 # ---- serving ------------------------------------------------------------------

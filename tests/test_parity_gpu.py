@@ -213,3 +213,44 @@ def test_tiled_stress_update_equals_per_cell_and_oracle(seed, shape, periodic, m
     for mode in ("-4", "-8"):
         for a, b in zip(results[mode], results["0"]):
             np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("steps", [1, 30])
+def test_giesekus_random_lattice(steps):
+    """Giesekus source (alpha = 0.3) on a random lattice with moving walls and
+    a sphere: GPU against the oracle."""
+    case = random_case(21, (10, 9, 8), (1, 0, 1), True, ((4.6, 4.3, 3.9), 2.0))
+    # a few times larger than usual so that tau.tau matters, yet well below
+    # eta_p / lambda, where the conformation I + (lambda / eta_p) tau would
+    # stop being positive definite and the Giesekus term would blow up
+    case.tau0 = case.tau0 * 5.0
+    log(f"[parity] giesekus random lattice, {steps} steps")
+    g, o = build(case)
+    g.set_giesekus(0.3)
+    o.set_giesekus(0.3)
+    g.step(steps)
+    o.step(steps)
+    e = compare(g, o, case)
+    log(f"[parity]   errors {e}")
+    tol = 2e-6 if steps == 1 else 1e-5
+    for k in ("f", "u", "tau", "rho"):
+        assert e[k][0] < tol, (k, e[k])
+
+
+def test_giesekus_channel():
+    """The 4x64x4 channel with the Giesekus law (alpha = 0.2), 5000 steps."""
+    shape = (4, 64, 4)
+    mask = inputs.channel_mask(shape, wall_axes=(1,))
+    case = Case("channel-giesekus", shape, mask, (1, 0, 1), None,
+                dict(eta=1 / 3, beta=0.5, lambda_p=1000.0, magic=-1.0, body_force=(1e-5, 0, 0)))
+    log("[parity] giesekus channel 4x64x4 5000 steps")
+    g, o = build(case)
+    g.set_giesekus(0.2)
+    o.set_giesekus(0.2)
+    g.step(5000)
+    o.step(5000)
+    e = compare(g, o, case, what=("u", "tau"))
+    log(f"[parity]   errors {e}")
+    assert e["u"][0] < 1e-5 and e["tau"][0] < 1e-5
+    # shear thinning shows: tau_yy < 0 in the bulk, unlike Oldroyd-B
+    assert o.stress()[1][:, 10:-10, :].max() < 0
