@@ -635,6 +635,7 @@ __global__ __launch_bounds__(BLOCK) LB_OCCUPANCY void lb_step_kernel(StepArgs a)
 
 __device__ __forceinline__ float face_overlap(const float u[3], int k, int s)
 {
+#pragma clang fp contract(on)
     const float ue = s * u[k];
     if (ue <= 0.f)
         return 0.f;
@@ -653,6 +654,10 @@ __device__ __forceinline__ void fv_compute(const A &a, const Geom &g, uint32_t n
                                            float un[3][2][3], const float tn[3][2][6],
                                            uint32_t solid)
 {
+    // Contraction only within an expression (and spelled out with fmaf where
+    // it matters), so that every kernel this is inlined into computes the
+    // same bits.
+#pragma clang fp contract(on)
     float G[3][3];
     float in_sum[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     float out_tot = 0.f;
@@ -669,7 +674,7 @@ __device__ __forceinline__ void fv_compute(const A &a, const Geom &g, uint32_t n
             out_tot += out;
 #pragma unroll
             for (int c = 0; c < 6; ++c)
-                in_sum[c] += in * tn[k][side][c];
+                in_sum[c] = fmaf(in, tn[k][side][c], in_sum[c]);
 #pragma unroll
             for (int j = 0; j < 3; ++j)
                 un[k][side][j] = sol ? 0.f : un[k][side][j];
@@ -717,15 +722,17 @@ __device__ __forceinline__ void fv_compute(const A &a, const Geom &g, uint32_t n
         float sdot = 0.f;
 #pragma unroll
         for (int k = 0; k < 3; ++k)
-            sdot += T3[i][k] * G[k][j] + T3[k][j] * G[k][i];
-        float inc = in_sum[c] - out_tot * t0[c] + sdot + epl * (G[i][j] + G[j][i]) - t0[c] * il;
+            sdot = fmaf(T3[k][j], G[k][i], fmaf(T3[i][k], G[k][j], sdot));
+        float inc = fmaf(-out_tot, t0[c], in_sum[c]) + sdot;
+        inc = fmaf(epl, G[i][j] + G[j][i], inc);
+        inc = fmaf(-t0[c], il, inc);
         if (gk != 0.f) {
             // Giesekus: -(alpha / eta_p) (tau . tau)_ij
             float tt = 0.f;
 #pragma unroll
             for (int k = 0; k < 3; ++k)
-                tt += T3[i][k] * T3[k][j];
-            inc -= gk * tt;
+                tt = fmaf(T3[i][k], T3[k][j], tt);
+            inc = fmaf(-gk, tt, inc);
         }
         const double v = static_cast<double>(t0[c]) + static_cast<double>(inc);
         if (!(c & 1))
