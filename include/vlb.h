@@ -112,6 +112,23 @@ size_t vlb_required_bytes(const vlb_dims *dims, vlb_storage storage, int32_t n_p
 vlb_status vlb_create(const vlb_dims *dims, const uint8_t *mask, const double *wall_velocity,
                       int32_t n_walls, vlb_storage storage, void *stream, vlb_lattice **out);
 
+/* Caller-owned state.  The large state arrays can live in device memory the
+ * caller allocates and owns (torch tensors, a pool): VLB_NBUF buffers, in
+ * this order: 0 mask (uint8), 1-2 the two population buffers, 3-4 the two
+ * stress buffers (FP32), 5 the velocity (FP32), each at least the size
+ * vlb_buffer_sizes gives and 256-byte aligned, on the current device.  The
+ * caller keeps them alive until vlb_destroy, which does not free them.  The
+ * library still allocates its small tables itself.
+ * Errors: VLB_EINVAL (bad dims or storage, a buffer missing, too small or
+ * misaligned), and as vlb_create. */
+#define VLB_NBUF 6
+vlb_status vlb_buffer_sizes(const vlb_dims *dims, vlb_storage storage, size_t sizes[VLB_NBUF]);
+vlb_status vlb_create_with_buffers(const vlb_dims *dims, const uint8_t *mask,
+                                   const double *wall_velocity, int32_t n_walls,
+                                   vlb_storage storage, void *stream,
+                                   void *const buffers[VLB_NBUF], const size_t sizes[VLB_NBUF],
+                                   vlb_lattice **out);
+
 /* Set eta, beta, lambda_p, magic and the body force (Section 2.3, 3.1):
  * omega+ = 1/(3 (1-beta) eta + 1/2); omega- from magic.  VLB_EINVAL when
  * eta <= 0, beta outside [0,1), lambda_p < 1 with beta > 0, or a rate

@@ -88,6 +88,7 @@ struct vlb_lattice {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int device = 0;
+    bool external_state = false;  // state buffers owned by the caller
     uint8_t *d_mask = nullptr;
     void *d_f[2] = {nullptr, nullptr};
     float *d_tau[2] = {nullptr, nullptr};
@@ -247,9 +248,13 @@ void free_all(vlb_lattice *lat)
 {
     if (lat->stream)
         (void)hipStreamSynchronize(lat->stream);
-    void *ptrs[] = {lat->d_mask,  lat->d_f[0],     lat->d_f[1],   lat->d_tau[0],     lat->d_tau[1],
-                    lat->d_u,     lat->d_wall,     lat->d_parts,  lat->d_partials,   lat->d_out,
-                    lat->d_counters, lat->d_pforce, lat->d_count, lat->d_g3};
+    void *state[] = {lat->d_mask, lat->d_f[0], lat->d_f[1], lat->d_tau[0], lat->d_tau[1], lat->d_u};
+    if (!lat->external_state)
+        for (void *p : state)
+            if (p)
+                (void)hipFree(p);
+    void *ptrs[] = {lat->d_wall,     lat->d_parts,  lat->d_partials, lat->d_out,
+                    lat->d_counters, lat->d_pforce, lat->d_count,    lat->d_g3};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -351,8 +356,20 @@ size_t vlb_required_bytes(const vlb_dims *dims, vlb_storage storage, int32_t n_p
     return static_cast<size_t>(pops + tau + u + mask + small);
 }
 
-vlb_status vlb_create(const vlb_dims *dims, const uint8_t *mask, const double *wall_velocity,
-                      int32_t n_walls, vlb_storage storage, void *stream, vlb_lattice **out)
+namespace {
+
+// sizes of the caller-providable state buffers (VLB_NBUF entries)
+void state_sizes(uint64_t N, uint64_t P, size_t es, size_t sizes[VLB_NBUF])
+{
+    sizes[0] = static_cast<size_t>(round_up(N, 256));
+    sizes[1] = sizes[2] = static_cast<size_t>(vlb::Q * P * es);
+    sizes[3] = sizes[4] = static_cast<size_t>(6 * P * sizeof(float));
+    sizes[5] = static_cast<size_t>(3 * P * sizeof(float));
+}
+
+vlb_status create_impl(const vlb_dims *dims, const uint8_t *mask, const double *wall_velocity,
+                       int32_t n_walls, vlb_storage storage, void *stream,
+                       void *const *buffers, const size_t *buffer_sizes, vlb_lattice **out)
 {
     if (!out)
         return fail(nullptr, VLB_EINVAL, "vlb_create: out is NULL");
@@ -372,6 +389,18 @@ vlb_status vlb_create(const vlb_dims *dims, const uint8_t *mask, const double *w
     if (!end_layers_solid(dims, mask))
         return fail(nullptr, VLB_EINVAL,
                     "vlb_create: a non-periodic axis needs solid first and last layers");
+    if (buffers) {
+        if (!buffer_sizes)
+            return fail(nullptr, VLB_EINVAL, "vlb_create_with_buffers: sizes is NULL");
+        size_t need[VLB_NBUF];
+        state_sizes(N, round_up(N, kPlaneAlign) + plane_pad(), storage_bytes(storage), need);
+        for (int k = 0; k < VLB_NBUF; ++k)
+            if (!buffers[k] || buffer_sizes[k] < need[k] ||
+                reinterpret_cast<uintptr_t>(buffers[k]) % 256 != 0)
+                return fail(nullptr, VLB_EINVAL,
+                            "vlb_create_with_buffers: buffer " + std::to_string(k) +
+                                " missing, too small or not 256-byte aligned");
+    }
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
         return fail(nullptr, VLB_EDEVICE, "vlb_create: no HIP device");
@@ -414,20 +443,33 @@ vlb_status vlb_create(const vlb_dims *dims, const uint8_t *mask, const double *w
     }
     const uint64_t P = lat->g.plane;
     const size_t es = storage_bytes(storage);
-    if ((e = hipMalloc(&lat->d_mask, round_up(N, 256))) != hipSuccess)
-        return bail(e, "mask");
+    if (buffers) {
+        // caller-owned state (e.g. torch tensors), checked on entry
+        lat->external_state = true;
+        lat->d_mask = static_cast<uint8_t *>(buffers[0]);
+        lat->d_f[0] = buffers[1];
+        lat->d_f[1] = buffers[2];
+        lat->d_tau[0] = static_cast<float *>(buffers[3]);
+        lat->d_tau[1] = static_cast<float *>(buffers[4]);
+        lat->d_u = static_cast<float *>(buffers[5]);
+    } else {
+        if ((e = hipMalloc(&lat->d_mask, round_up(N, 256))) != hipSuccess)
+            return bail(e, "mask");
+        for (int b = 0; b < 2; ++b) {
+            if ((e = hipMalloc(&lat->d_f[b], vlb::Q * P * es)) != hipSuccess)
+                return bail(e, "populations");
+            if ((e = hipMalloc(&lat->d_tau[b], 6 * P * sizeof(float))) != hipSuccess)
+                return bail(e, "stress");
+        }
+        if ((e = hipMalloc(&lat->d_u, 3 * P * sizeof(float))) != hipSuccess)
+            return bail(e, "velocity");
+    }
     for (int b = 0; b < 2; ++b) {
-        if ((e = hipMalloc(&lat->d_f[b], vlb::Q * P * es)) != hipSuccess)
-            return bail(e, "populations");
-        if ((e = hipMalloc(&lat->d_tau[b], 6 * P * sizeof(float))) != hipSuccess)
-            return bail(e, "stress");
         if ((e = hipMemsetAsync(lat->d_tau[b], 0, 6 * P * sizeof(float), lat->stream)) != hipSuccess)
             return bail(e, "stress");
         if ((e = hipMemsetAsync(lat->d_f[b], 0, vlb::Q * P * es, lat->stream)) != hipSuccess)
             return bail(e, "populations");
     }
-    if ((e = hipMalloc(&lat->d_u, 3 * P * sizeof(float))) != hipSuccess)
-        return bail(e, "velocity");
     if ((e = hipMemsetAsync(lat->d_u, 0, 3 * P * sizeof(float), lat->stream)) != hipSuccess)
         return bail(e, "velocity");
     if ((e = hipMalloc(&lat->d_wall, 64 * 3 * sizeof(double))) != hipSuccess)
@@ -473,6 +515,35 @@ vlb_status vlb_create(const vlb_dims *dims, const uint8_t *mask, const double *w
     }
     *out = lat;
     return VLB_OK;
+}
+
+}  // namespace
+
+vlb_status vlb_create(const vlb_dims *dims, const uint8_t *mask, const double *wall_velocity,
+                      int32_t n_walls, vlb_storage storage, void *stream, vlb_lattice **out)
+{
+    return create_impl(dims, mask, wall_velocity, n_walls, storage, stream, nullptr, nullptr, out);
+}
+
+vlb_status vlb_buffer_sizes(const vlb_dims *dims, vlb_storage storage, size_t sizes[VLB_NBUF])
+{
+    if (!sizes || check_dims(dims) != VLB_OK ||
+        (storage != VLB_STORE_F32 && storage != VLB_STORE_F16 && storage != VLB_STORE_BF16))
+        return VLB_EINVAL;
+    const uint64_t N = static_cast<uint64_t>(dims->nx) * dims->ny * dims->nz;
+    state_sizes(N, round_up(N, kPlaneAlign) + plane_pad(), storage_bytes(storage), sizes);
+    return VLB_OK;
+}
+
+vlb_status vlb_create_with_buffers(const vlb_dims *dims, const uint8_t *mask,
+                                   const double *wall_velocity, int32_t n_walls,
+                                   vlb_storage storage, void *stream,
+                                   void *const buffers[VLB_NBUF], const size_t sizes[VLB_NBUF],
+                                   vlb_lattice **out)
+{
+    if (!buffers)
+        return fail(nullptr, VLB_EINVAL, "vlb_create_with_buffers: buffers is NULL");
+    return create_impl(dims, mask, wall_velocity, n_walls, storage, stream, buffers, sizes, out);
 }
 
 vlb_status vlb_set_params(vlb_lattice *lat, const vlb_params *p)

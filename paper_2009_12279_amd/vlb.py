@@ -70,6 +70,13 @@ SIGNATURES = [
     ("vlb_required_bytes", ctypes.c_size_t, [ctypes.POINTER(vlb_dims), ctypes.c_int, ctypes.c_int32]),
     ("vlb_create", ctypes.c_int, [ctypes.POINTER(vlb_dims), ctypes.c_char_p, _D, ctypes.c_int32,
                                   ctypes.c_int, _P, ctypes.POINTER(_P)]),
+    ("vlb_buffer_sizes", ctypes.c_int, [ctypes.POINTER(vlb_dims), ctypes.c_int,
+                                        ctypes.POINTER(ctypes.c_size_t)]),
+    ("vlb_create_with_buffers", ctypes.c_int, [ctypes.POINTER(vlb_dims), ctypes.c_char_p, _D,
+                                               ctypes.c_int32, ctypes.c_int, _P,
+                                               ctypes.POINTER(ctypes.c_void_p),
+                                               ctypes.POINTER(ctypes.c_size_t),
+                                               ctypes.POINTER(_P)]),
     ("vlb_set_params", ctypes.c_int, [_P, ctypes.POINTER(vlb_params)]),
     ("vlb_init_equilibrium", ctypes.c_int, [_P, _D]),
     ("vlb_set_populations", ctypes.c_int, [_P, _D]),
@@ -120,6 +127,13 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"libvlb.so not built at {LIB_PATH}; run __graft_entry__.build()")
+        # One HIP runtime per process: torch ships its own libamdhip64 under
+        # the same soname, so it is loaded first and libvlb binds to it; the
+        # other order leaves torch without a usable device.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         for name, res, args in SIGNATURES:
             fn = getattr(L, name)
@@ -181,6 +195,42 @@ def vlb_create(shape, mask, periodic=(1, 1, 1), wall_velocity=None, storage="f32
     st = lib().vlb_create(ctypes.byref(d), m.tobytes(), None if wv is None else _dp(wv), nw,
                           STORAGE[storage], None if stream is None else _P(int(stream)),
                           ctypes.byref(h))
+    _check(st, None)
+    return h
+
+
+NBUF = 6
+
+
+def vlb_buffer_sizes(shape, periodic=(1, 1, 1), storage="f32"):
+    """Bytes of the caller-providable state buffers (mask, 2 x populations,
+    2 x stress, velocity)."""
+    d = make_dims(shape, periodic)
+    sizes = (ctypes.c_size_t * NBUF)()
+    _check(lib().vlb_buffer_sizes(ctypes.byref(d), STORAGE[storage], sizes), None)
+    return [int(v) for v in sizes]
+
+
+def vlb_create_with_buffers(shape, mask, buffers, sizes, periodic=(1, 1, 1), wall_velocity=None,
+                            storage="f32", stream=None):
+    """vlb_create with caller-owned device buffers (pointers as integers)."""
+    nx, ny, nz = shape
+    m = np.ascontiguousarray(mask, dtype=np.uint8)
+    if m.shape != (nz, ny, nx):
+        raise ValueError("mask must be shaped [nz, ny, nx]")
+    d = make_dims(shape, periodic)
+    wv = None
+    nw = 0
+    if wall_velocity is not None:
+        wv = np.ascontiguousarray(wall_velocity, dtype=np.float64).reshape(-1)
+        nw = wv.size // 3
+    bufs = (ctypes.c_void_p * NBUF)(*[int(b) for b in buffers])
+    szs = (ctypes.c_size_t * NBUF)(*[int(v) for v in sizes])
+    h = _P()
+    st = lib().vlb_create_with_buffers(ctypes.byref(d), m.tobytes(),
+                                       None if wv is None else _dp(wv), nw, STORAGE[storage],
+                                       None if stream is None else _P(int(stream)), bufs, szs,
+                                       ctypes.byref(h))
     _check(st, None)
     return h
 
@@ -342,15 +392,27 @@ class Lattice:
     """One lattice on the current HIP device (owner of the C handle)."""
 
     def __init__(self, shape, mask=None, periodic=(1, 1, 1), wall_velocity=None, storage="f32",
-                 stream=None, _handle=None):
+                 stream=None, _handle=None, torch_buffers=False):
+        """torch_buffers=True keeps the state in torch-allocated device tensors
+        (held by this object) instead of library allocations."""
         self.shape = tuple(int(s) for s in shape)
         nx, ny, nz = self.shape
+        self._buffers = None
         if _handle is not None:
             self._h = _handle
             return
         if mask is None:
             mask = np.zeros((nz, ny, nx), dtype=np.uint8)
-        self._h = vlb_create(self.shape, mask, periodic, wall_velocity, storage, stream)
+        if torch_buffers:
+            import torch
+
+            sizes = vlb_buffer_sizes(self.shape, periodic, storage)
+            # torch's caching allocator hands out 512-byte aligned blocks
+            self._buffers = [torch.empty(n, dtype=torch.uint8, device="cuda") for n in sizes]
+            self._h = vlb_create_with_buffers(self.shape, mask, [b.data_ptr() for b in self._buffers],
+                                              sizes, periodic, wall_velocity, storage, stream)
+        else:
+            self._h = vlb_create(self.shape, mask, periodic, wall_velocity, storage, stream)
 
     @classmethod
     def load(cls, path, shape, stream=None):
@@ -360,6 +422,7 @@ class Lattice:
         if getattr(self, "_h", None):
             vlb_destroy(self._h)
             self._h = None
+        self._buffers = None  # caller-owned state goes after the lattice
 
     def __del__(self):
         try:

@@ -87,3 +87,29 @@ def test_create_without_device_reports_device_error():
         pytest.skip("a HIP device is present")
     _expect_status(lambda: vlb.vlb_create((4, 4, 4), np.zeros((4, 4, 4), np.uint8)),
                    vlb.VLB_EDEVICE)
+
+
+def test_buffer_sizes_match_the_state_layout():
+    shape = (64, 32, 16)
+    s32 = vlb.vlb_buffer_sizes(shape, storage="f32")
+    s16 = vlb.vlb_buffer_sizes(shape, storage="f16")
+    N = 64 * 32 * 16
+    assert s32[0] >= N and s32[0] % 256 == 0
+    assert s32[1] == s32[2] and s32[3] == s32[4]
+    P = s32[5] // 12  # velocity: 3 FP32 planes of P elements
+    assert P >= N and s32[1] == 19 * P * 4 and s32[3] == 6 * P * 4
+    assert s16[1] == 19 * P * 2 and s16[3] == s32[3]
+    assert sum(s32) <= vlb.vlb_required_bytes(shape, storage="f32")
+
+
+def test_create_with_buffers_checks_them_on_the_host():
+    shape = (8, 8, 8)
+    mask = np.zeros((8, 8, 8), np.uint8)
+    sizes = vlb.vlb_buffer_sizes(shape)
+    fake = [256 * (k + 1) << 20 for k in range(vlb.NBUF)]  # never dereferenced
+    with pytest.raises(vlb.VlbError) as ei:
+        vlb.vlb_create_with_buffers(shape, mask, fake, [n - 1 for n in sizes])
+    assert ei.value.status == vlb.VLB_EINVAL
+    with pytest.raises(vlb.VlbError) as ei:
+        vlb.vlb_create_with_buffers(shape, mask, [p + 4 for p in fake], sizes)
+    assert ei.value.status == vlb.VLB_EINVAL

@@ -109,3 +109,24 @@ def test_stepping_an_unset_lattice_and_bad_particle_ids():
     L.step(2)
     assert L.step_count == 2
     L.close()
+
+
+def test_torch_owned_state_gives_the_same_bits():
+    """The state in torch-allocated device tensors (vlb_create_with_buffers)
+    evolves exactly as in library allocations."""
+    out = []
+    for tb in (False, True):
+        log(f"[lattice] torch buffers={tb}")
+        shape = (20, 18, 26)
+        mask = inputs.channel_mask(shape, wall_axes=(0, 1, 2))
+        L = vlb.Lattice(shape, mask, (0, 0, 0), torch_buffers=tb)
+        L.set_params(eta=1 / 6, beta=0.5, lambda_p=40.0, magic=3 / 16, body_force=(2e-6, 0, 0))
+        L.add_sphere(center=(9.5, 8.7, 13.2), radius=3.4, density_ratio=5.0, movable=True,
+                     f_ext=(8e-3, 0.0, -2e-2))
+        L.set_check_interval(0)
+        L.init_equilibrium()
+        L.step(150)
+        out.append((L.populations(), L.stress(), L.mask(), L.particle(0)["pos"]))
+        L.close()
+    for a, b in zip(*out):
+        np.testing.assert_array_equal(a, b)
