@@ -50,6 +50,8 @@ def lib():
         L.or_set_counter_force.argtypes = [P, I]
         L.or_set_giesekus.restype = I
         L.or_set_giesekus.argtypes = [P, ctypes.c_double]
+        L.or_set_fene_p.restype = I
+        L.or_set_fene_p.argtypes = [P, ctypes.c_double]
         L.or_init_equilibrium.argtypes = [P, D]
         L.or_set_populations.argtypes = [P, D]
         L.or_set_stress.argtypes = [P, D]
@@ -75,7 +77,7 @@ def lib():
         L.or_collide_cell.argtypes = [D, D, ctypes.c_double, ctypes.c_double, D, D, D]
         L.or_rates.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, D, D]
         L.or_fv_apply.argtypes = [I, I, I, ctypes.c_char_p, D, D, ctypes.c_double,
-                                  ctypes.c_double, ctypes.c_double, D]
+                                  ctypes.c_double, ctypes.c_double, ctypes.c_double, D]
         L.or_polymer_force.argtypes = [I, I, I, ctypes.c_char_p, D, D]
         L.or_set_threads.argtypes = [I]
         L.or_get_threads.restype = I
@@ -132,7 +134,7 @@ def rates(eta, beta, magic):
     return a.value, b.value
 
 
-def fv_apply(mask, tau, u, eta_p, lambda_p, alpha=0.0):
+def fv_apply(mask, tau, u, eta_p, lambda_p, alpha=0.0, L2=0.0):
     """One finite-volume stress update with a prescribed velocity field
     (alpha > 0: Giesekus source term).
 
@@ -143,7 +145,7 @@ def fv_apply(mask, tau, u, eta_p, lambda_p, alpha=0.0):
     uu = np.ascontiguousarray(u, dtype=np.float64)
     out = np.zeros_like(t)
     lib().or_fv_apply(nx, ny, nz, m.tobytes(), _dp(t), _dp(uu), float(eta_p), float(lambda_p),
-                      float(alpha), _dp(out))
+                      float(alpha), float(L2), _dp(out))
     return out
 
 
@@ -206,6 +208,10 @@ class Lattice:
     def set_giesekus(self, alpha):
         if lib().or_set_giesekus(self._h, float(alpha)) != 0:
             raise ValueError("oracle: Giesekus mobility must lie in [0, 1/2]")
+
+    def set_fene_p(self, L2):
+        if lib().or_set_fene_p(self._h, float(L2)) != 0:
+            raise ValueError("oracle: FENE-P needs L^2 > 3 (or 0 for off)")
 
     def init_equilibrium(self, u=None):
         if u is None:

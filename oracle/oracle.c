@@ -276,8 +276,20 @@ static double face_overlap(const double u[3], const int e[3])
     return v;
 }
 
+/* FENE-P (Peterlin closure), in the stored variable T = (eta_p/lambda)(A - I)
+ * of the conformation A: f = (L^2 - 3) / (L^2 - tr A), tr A = 3 + (lambda /
+ * eta_p) tr T.  L2 <= 0: not FENE-P (f = 1). */
+static double fene_f(double L2, double eta_p, double lambda_p, const double t[3][3])
+{
+    if (!(L2 > 0.0))
+        return 1.0;
+    double trA_minus_3 = lambda_p / eta_p * (t[0][0] + t[1][1] + t[2][2]);
+    return (L2 - 3.0) / (L2 - 3.0 - trA_minus_3);
+}
+
 void or_fv_apply(int nx, int ny, int nz, const unsigned char *mask, const double *tau_in,
-                 const double *u, double eta_p, double lambda_p, double alpha, double *tau_out)
+                 const double *u, double eta_p, double lambda_p, double alpha, double L2,
+                 double *tau_out)
 {
     long N = (long)nx * ny * nz;
 #pragma omp parallel for schedule(static) num_threads(or_get_threads())
@@ -303,13 +315,25 @@ void or_fv_apply(int nx, int ny, int nz, const unsigned char *mask, const double
                 }
                 /* Oldroyd-B source: sum_k tau_ik G_kj + sum_k tau_kj G_ki
                  * + eta_p/lambda (G_ij + G_ji) - tau_ij/lambda */
+                const double fp_ = fene_f(L2, eta_p, lambda_p, t);
                 double S[3][3];
                 for (int i = 0; i < 3; ++i)
                     for (int j = 0; j < 3; ++j) {
                         double s = 0.0;
                         for (int k = 0; k < 3; ++k)
                             s += t[i][k] * G[k][j] + t[k][j] * G[k][i];
-                        s += eta_p / lambda_p * (G[i][j] + G[j][i]) - t[i][j] / lambda_p;
+                        s += eta_p / lambda_p * (G[i][j] + G[j][i]);
+                        if (L2 > 0.0) {
+                            /* FENE-P: the conformation A = I + (lambda/eta_p) T relaxes as
+                             * -(f A - I)/lambda, which for T reads
+                             * -(f/lambda) T - (eta_p/lambda^2)(f - 1) I (Section 2.2 names
+                             * FENE-P as the model the scheme extends to) */
+                            s -= fp_ * t[i][j] / lambda_p;
+                            if (i == j)
+                                s -= eta_p / (lambda_p * lambda_p) * (fp_ - 1.0);
+                        } else {
+                            s -= t[i][j] / lambda_p;
+                        }
                         /* Giesekus (Section 2.2 lists it among the models the
                          * scheme extends to): the quadratic relaxation term
                          * -(alpha / eta_p) (tau . tau) of tau + lambda tau^del
@@ -372,6 +396,8 @@ struct or_lattice {
     double eta, beta, lambda, magic, g[3];
     int counter_force;               /* -sum of the free particles' F_ext spread over the fluid */
     double alpha;                    /* Giesekus mobility (0: Oldroyd-B) */
+    double L2;                       /* FENE-P extensibility L^2 (0: not FENE-P) */
+    double *stress;                  /* polymer stress of the stored state (6*N) */
     double wp, wm, eta_p;
     int polymer;
     double *f, *fnew, *fpost;
@@ -412,6 +438,7 @@ or_lattice *or_create(int nx, int ny, int nz, const int periodic[3], const unsig
     L->fpost = (double *)calloc((size_t)Q * N, sizeof(double));
     L->tau = (double *)calloc((size_t)6 * N, sizeof(double));
     L->taunew = (double *)calloc((size_t)6 * N, sizeof(double));
+    L->stress = (double *)calloc((size_t)6 * N, sizeof(double));
     L->rho = (double *)calloc((size_t)N, sizeof(double));
     L->u = (double *)calloc((size_t)3 * N, sizeof(double));
     L->fp = (double *)calloc((size_t)3 * N, sizeof(double));
@@ -433,6 +460,7 @@ void or_destroy(or_lattice *L)
     free(L->fpost);
     free(L->tau);
     free(L->taunew);
+    free(L->stress);
     free(L->rho);
     free(L->u);
     free(L->fp);
@@ -651,7 +679,39 @@ int or_set_giesekus(or_lattice *L, double alpha)
     if (!(alpha >= 0.0 && alpha <= 0.5))
         return -1;
     L->alpha = alpha;
+    if (alpha > 0.0)
+        L->L2 = 0.0;
     return 0;
+}
+
+int or_set_fene_p(or_lattice *L, double L2)
+{
+    if (!(L2 == 0.0 || L2 > 3.0))
+        return -1;
+    L->L2 = L2;
+    if (L2 > 0.0)
+        L->alpha = 0.0;
+    return 0;
+}
+
+/* Polymer stress of the stored state: the state itself, or for FENE-P
+ * tau = (eta_p/lambda)(f A - I) = f T + (eta_p/lambda)(f - 1) I. */
+static void state_stress(const or_lattice *L, const double *state, double *out)
+{
+    long N = L->N;
+    if (!(L->L2 > 0.0)) {
+        memcpy(out, state, sizeof(double) * 6 * N);
+        return;
+    }
+    for (long n = 0; n < N; ++n) {
+        double t[3][3];
+        tau_get(state, N, n, t);
+        double f = fene_f(L->L2, L->eta_p, L->lambda, t);
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j)
+                t[i][j] = f * t[i][j] + (i == j ? L->eta_p / L->lambda * (f - 1.0) : 0.0);
+        tau_put(out, N, n, t);
+    }
 }
 
 static void fluid_moments(const or_lattice *L, const double *f, const double *fp, const double g[3],
@@ -688,9 +748,11 @@ void or_step(or_lattice *L, long n_steps)
                     for (int a = 0; a < 3; ++a)
                         L->ub[a * N + n] = ub[a];
                 }
-        /* S1: polymer force from tau^n */
-        if (L->polymer)
-            or_polymer_force(nx, ny, nz, mask, L->tau, L->fp);
+        /* S1: polymer force from tau^n (the stress of the stored state) */
+        if (L->polymer) {
+            state_stress(L, L->tau, L->stress);
+            or_polymer_force(nx, ny, nz, mask, L->stress, L->fp);
+        }
         else
             memset(L->fp, 0, sizeof(double) * 3 * N);
         /* S2 + S3: moments and collision on every fluid cell */
@@ -764,7 +826,7 @@ void or_step(or_lattice *L, long n_steps)
                     }
                     if (L->polymer) {
                         double t[3][3];
-                        tau_get(L->tau, N, n, t);
+                        tau_get(L->stress, N, n, t);
                         for (int k = 0; k < 6; ++k) {
                             long m = nbr(nx, ny, nz, x, y, z, FACE[k]);
                             if (mask[m] == 0)
@@ -783,7 +845,8 @@ void or_step(or_lattice *L, long n_steps)
                 }
         /* S5: finite-volume stress update with tau^n and u^n */
         if (L->polymer)
-            or_fv_apply(nx, ny, nz, mask, L->tau, L->u, L->eta_p, L->lambda, L->alpha, L->taunew);
+            or_fv_apply(nx, ny, nz, mask, L->tau, L->u, L->eta_p, L->lambda, L->alpha, L->L2,
+                        L->taunew);
         else
             memset(L->taunew, 0, sizeof(double) * 6 * N);
         /* S6: particles, symplectic Euler */
@@ -1001,7 +1064,7 @@ static void conversion(or_lattice *L)
 
 void or_read_populations(const or_lattice *L, double *f) { memcpy(f, L->f, sizeof(double) * Q * L->N); }
 
-void or_read_stress(const or_lattice *L, double *tau) { memcpy(tau, L->tau, sizeof(double) * 6 * L->N); }
+void or_read_stress(const or_lattice *L, double *tau) { state_stress(L, L->tau, tau); }
 
 void or_read_mask(const or_lattice *L, unsigned char *mask) { memcpy(mask, L->mask, L->N); }
 
@@ -1009,8 +1072,12 @@ static double *current_force(const or_lattice *L)
 {
     long N = L->N;
     double *fp = (double *)calloc((size_t)3 * N, sizeof(double));
-    if (L->polymer)
-        or_polymer_force(L->n[0], L->n[1], L->n[2], L->mask, L->tau, fp);
+    if (L->polymer) {
+        double *st = (double *)malloc(sizeof(double) * 6 * N);
+        state_stress(L, L->tau, st);
+        or_polymer_force(L->n[0], L->n[1], L->n[2], L->mask, st, fp);
+        free(st);
+    }
     return fp;
 }
 

@@ -46,9 +46,12 @@ void or_rates(double eta, double beta, double magic, double *omega_plus, double 
  * prescribed velocity field u (3*N; at solid cells it is the boundary
  * velocity).  tau_out = tau_in + fluxes + source on fluid cells; solid cells
  * copy tau_in.  alpha > 0 adds the Giesekus term -(alpha/eta_p) tau.tau to
- * the source. */
+ * the source; L2 > 0 makes it FENE-P in the stored variable
+ * T = (eta_p/lambda)(A - I) (relaxation -(f/lambda) T - (eta_p/lambda^2)(f-1) I,
+ * f = (L2 - 3) / (L2 - tr A)). */
 void or_fv_apply(int nx, int ny, int nz, const unsigned char *mask, const double *tau_in,
-                 const double *u, double eta_p, double lambda_p, double alpha, double *tau_out);
+                 const double *u, double eta_p, double lambda_p, double alpha, double L2,
+                 double *tau_out);
 
 /* The discrete polymer force of Section 3.3 for a stress field (fluid cells). */
 void or_polymer_force(int nx, int ny, int nz, const unsigned char *mask, const double *tau,
@@ -68,6 +71,11 @@ void or_set_counter_force(or_lattice *L, int on);
 /* Giesekus model with mobility alpha in [0, 1/2] (0 = Oldroyd-B, the
  * default); -1 for alpha out of range. */
 int or_set_giesekus(or_lattice *L, double alpha);
+/* FENE-P with extensibility L2 = L^2 > 3 (0 = off; the last of Giesekus and
+ * FENE-P set wins).  The stored stress variable becomes
+ * T = (eta_p/lambda)(A - I); or_set_stress sets T, or_read_stress returns
+ * the polymer stress tau = f T + (eta_p/lambda)(f - 1) I. */
+int or_set_fene_p(or_lattice *L, double L2);
 void or_init_equilibrium(or_lattice *L, const double *u);
 void or_set_populations(or_lattice *L, const double *f);
 void or_set_stress(or_lattice *L, const double *tau);

@@ -225,3 +225,42 @@ def test_giesekus_steady_shear_matches_the_constitutive_equations(orc):
                                        rtol=1e-12, atol=1e-20)
         else:
             assert expect[2] < eta_p * gam and expect[1] < 0
+
+
+def test_fene_p_steady_shear_matches_the_conformation_solution(orc):
+    """FENE-P (Section 2.2 names it as the model the scheme extends to), in
+    the stored variable T = (eta_p/lam)(A - I).  In steady simple shear the
+    conformation equation A^del = -(f A - I)/lam with f = (L^2-3)/(L^2-tr A)
+    gives, by component, A_yy = A_zz = 1/f, A_xy = W/f^2 and
+    A_xx = 1/f + 2 W^2/f^3 (W = lam g), with f the root of
+    f (L^2 - 3/f - 2 W^2/f^3) = L^2 - 3.  The explicit FV update with a
+    prescribed shear relaxes to exactly that; huge L^2 is Oldroyd-B."""
+    from scipy.optimize import brentq
+
+    nx, ny, nz = 3, 12, 3
+    mask = np.zeros((nz, ny, nx), np.uint8)
+    mask[:, 0, :] = 1
+    mask[:, -1, :] = 1
+    gam, eta_p, lam = 2e-3, 0.25, 400.0
+    W = lam * gam
+    u = np.zeros((3, nz, ny, nx))
+    u[0] = (gam * np.arange(ny, dtype=float))[None, :, None]
+    for L2 in (10.0, 50.0):
+        f = brentq(lambda f: f * (L2 - 3 / f - 2 * W ** 2 / f ** 3) - (L2 - 3), 1.0, 50.0,
+                   xtol=1e-15)
+        T = np.zeros((6, nz, ny, nx))
+        for _ in range(20000):
+            T = orc.fv_apply(mask, T, u, eta_p, lam, L2=L2)
+        A = T[:, :, 2:-2, :] * (lam / eta_p)  # A - I
+        np.testing.assert_allclose(A[1] + 1, 1 / f, rtol=1e-9)
+        np.testing.assert_allclose(A[2] + 1, 1 / f, rtol=1e-9)
+        np.testing.assert_allclose(A[3], W / f ** 2, rtol=1e-9)
+        np.testing.assert_allclose(A[0] + 1, 1 / f + 2 * W ** 2 / f ** 3, rtol=1e-9)
+        np.testing.assert_allclose(A[[4, 5]], 0.0, atol=1e-30)
+        assert f > 1.01  # the finite extensibility matters at this W
+    T_ob = np.zeros((6, nz, ny, nx))
+    T_fe = np.zeros((6, nz, ny, nx))
+    for _ in range(300):
+        T_ob = orc.fv_apply(mask, T_ob, u, eta_p, lam)
+        T_fe = orc.fv_apply(mask, T_fe, u, eta_p, lam, L2=1e12)
+    np.testing.assert_allclose(T_fe, T_ob, rtol=1e-8, atol=1e-9 * np.abs(T_ob).max())
