@@ -215,6 +215,16 @@ vlb_status vlb_set_timing(vlb_lattice *lat, int32_t on);
  * 0, the default, is Oldroyd-B.  Kept in checkpoints. */
 vlb_status vlb_set_giesekus(vlb_lattice *lat, double alpha);
 
+/* FENE-P constitutive law (Section 2.2 names it as the model the method
+ * extends to), with the Peterlin closure f = (L^2 - 3) / (L^2 - tr A) of the
+ * conformation A.  The stored stress variable becomes T = (eta_p/lambda)
+ * (A - I), which relaxes as -(f/lambda) T - (eta_p/lambda^2)(f - 1) I; the
+ * polymer force, the traction on obstacles and vlb_read_stress use the
+ * polymer stress f T + (eta_p/lambda)(f - 1) I; vlb_set_stress sets T.
+ * L2 = L^2 > 3, or 0 for off (VLB_EINVAL otherwise); the last of
+ * vlb_set_giesekus and vlb_set_fene_p wins.  Kept in checkpoints. */
+vlb_status vlb_set_fene_p(vlb_lattice *lat, double L2);
+
 /* Counter-force for periodic systems with free particles (Section 4.5):
  * when on, every step subtracts the summed external force of the movable
  * particles from the body force, spread evenly over the cells that are

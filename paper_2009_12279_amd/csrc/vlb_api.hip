@@ -101,6 +101,18 @@ struct vlb_lattice {
     double *d_g3 = nullptr;       // body force under counter-force
     bool counter_force = false;
     double alpha = 0.0;           // Giesekus mobility
+    double L2 = 0.0;              // FENE-P extensibility (0: off)
+    vlb::StressMap stress_map() const
+    {
+        vlb::StressMap m;
+        if (L2 > 0.0 && polymer) {
+            const double eta_p = params.beta * params.eta;
+            m.c = static_cast<float>(params.lambda_p / eta_p);
+            m.l2m3 = static_cast<float>(L2 - 3.0);
+            m.epl = static_cast<float>(eta_p / params.lambda_p);
+        }
+        return m;
+    }
     double *d_out = nullptr;
     int32_t *d_counters = nullptr;
     int n_walls = 0;
@@ -752,6 +764,7 @@ vlb_status vlb_step(vlb_lattice *lat, int64_t n_steps)
         a.eta_p_lam = lat->params.beta * lat->params.eta / lat->params.lambda_p;
         a.inv_lam = 1.0 / lat->params.lambda_p;
         a.gk = static_cast<float>(lat->alpha / (lat->params.beta * lat->params.eta));
+        a.sm = lat->stress_map();
     }
     a.stochastic = lat->rounding == VLB_ROUND_STOCHASTIC ? 1 : 0;
     a.seed = lat->seed;
@@ -798,7 +811,7 @@ vlb_status vlb_step(vlb_lattice *lat, int64_t n_steps)
             const int np = static_cast<int>(lat->parts_h.size());
             HIPCHK(lat, vlb::launch_particle_forces(lat->storage, lat->g, lat->d_mask, a.fout, a.tin,
                                                     lat->polymer, lat->inv_scale, lat->d_parts, np,
-                                                    lat->d_pforce, lat->stream),
+                                                    lat->d_pforce, lat->stream, lat->stress_map()),
                    "particle forces");
             HIPCHK(lat, vlb::launch_particle_update(lat->g, lat->d_parts, np, lat->stream),
                    "particle update");
@@ -899,7 +912,8 @@ vlb_status vlb_read_density(vlb_lattice *lat, double *rho)
         [&](double *d) {
             return vlb::launch_read_moments(lat->storage, lat->g, lat->bound(), lat->d_mask,
                                             lat->d_f[lat->cur], lat->d_tau[lat->cur], lat->polymer,
-                                            gv, lat->inv_scale, d, nullptr, lat->stream);
+                                            gv, lat->inv_scale, d, nullptr, lat->stream,
+                                            lat->stress_map());
         },
         "vlb_read_density");
 }
@@ -919,7 +933,8 @@ vlb_status vlb_read_velocity(vlb_lattice *lat, double *u)
         [&](double *d) {
             return vlb::launch_read_moments(lat->storage, lat->g, lat->bound(), lat->d_mask,
                                             lat->d_f[lat->cur], lat->d_tau[lat->cur], lat->polymer,
-                                            gv, lat->inv_scale, nullptr, d, lat->stream);
+                                            gv, lat->inv_scale, nullptr, d, lat->stream,
+                                            lat->stress_map());
         },
         "vlb_read_velocity");
 }
@@ -934,7 +949,7 @@ vlb_status vlb_read_stress(vlb_lattice *lat, double *tau)
         lat, 6 * static_cast<size_t>(lat->g.N) * sizeof(double), tau,
         [&](double *d) {
             return vlb::launch_read_stress(lat->g, lat->d_mask, lat->d_tau[lat->cur], d,
-                                           lat->stream);
+                                           lat->stream, lat->stress_map());
         },
         "vlb_read_stress");
 }
@@ -981,7 +996,7 @@ vlb_status vlb_read_particle(vlb_lattice *lat, int32_t id, double pos[3], double
         HIPCHK(lat, vlb::launch_particle_forces(lat->storage, lat->g, lat->d_mask,
                                                 lat->d_f[lat->cur], lat->d_tau[lat->cur ^ 1],
                                                 lat->polymer, lat->inv_scale, lat->d_parts, np,
-                                                lat->d_pforce, lat->stream),
+                                                lat->d_pforce, lat->stream, lat->stress_map()),
                "particle forces");
         HIPCHK(lat, vlb::launch_particle_update(lat->g, lat->d_parts, np, lat->stream),
                "particle totals");
@@ -1034,7 +1049,7 @@ vlb_status vlb_read_wall_force(vlb_lattice *lat, double force[3])
     }
     HIPCHK(lat, vlb::launch_wall_force(lat->storage, lat->g, lat->d_mask, lat->d_f[lat->cur],
                                        lat->d_tau[lat->cur ^ 1], lat->polymer, lat->inv_scale,
-                                       lat->d_partials, lat->d_out, lat->stream),
+                                       lat->d_partials, lat->d_out, lat->stream, lat->stress_map()),
            "wall force");
     HIPCHK(lat, hipMemcpyAsync(force, lat->d_out, 3 * sizeof(double), hipMemcpyDeviceToHost,
                                lat->stream),
@@ -1079,7 +1094,7 @@ vlb_status vlb_set_check_interval(vlb_lattice *lat, int64_t steps)
 // checkpoint
 
 namespace {
-constexpr uint64_t kMagic = 0x34304B434C424C56ull;  // "VLBLCK04"
+constexpr uint64_t kMagic = 0x35304B434C424C56ull;  // "VLBLCK05"
 
 struct FileHeader {
     uint64_t magic;
@@ -1094,6 +1109,7 @@ struct FileHeader {
     int32_t counter_force;
     int32_t reserved;
     double alpha;
+    double L2;
 };
 }  // namespace
 
@@ -1150,6 +1166,7 @@ vlb_status vlb_save(vlb_lattice *lat, const char *path)
     h.seed = lat->seed;
     h.counter_force = lat->counter_force ? 1 : 0;
     h.alpha = lat->alpha;
+    h.L2 = lat->L2;
     bool ok = std::fwrite(&h, sizeof h, 1, fp) == 1;
     ok = ok && std::fwrite(lat->wall_h.data(), sizeof(double), 64 * 3, fp) == 64 * 3;
     ok = ok && (parts.empty() || std::fwrite(parts.data(), sizeof(Particle), parts.size(), fp) ==
@@ -1230,6 +1247,7 @@ vlb_status vlb_load(const char *path, void *stream, vlb_lattice **out)
     lat->seed = h.seed;
     lat->counter_force = h.counter_force != 0;
     lat->alpha = (h.alpha >= 0.0 && h.alpha <= 0.5) ? h.alpha : 0.0;
+    lat->L2 = (h.L2 > 3.0 && std::isfinite(h.L2)) ? h.L2 : 0.0;
     lat->scale = h.scale;
     lat->inv_scale = 1.f / h.scale;
     hipError_t e = hipMemcpyAsync(lat->d_mask, mask.data(), N, hipMemcpyHostToDevice, lat->stream);
@@ -1276,6 +1294,20 @@ vlb_status vlb_set_giesekus(vlb_lattice *lat, double alpha)
     if (!(alpha >= 0.0 && alpha <= 0.5))
         return fail(lat, VLB_EINVAL, "vlb_set_giesekus: alpha must lie in [0, 1/2]");
     lat->alpha = alpha;
+    if (alpha > 0.0)
+        lat->L2 = 0.0;
+    return VLB_OK;
+}
+
+vlb_status vlb_set_fene_p(vlb_lattice *lat, double L2)
+{
+    if (!lat)
+        return VLB_EINVAL;
+    if (!(L2 == 0.0 || (L2 > 3.0 && std::isfinite(L2))))
+        return fail(lat, VLB_EINVAL, "vlb_set_fene_p: need L^2 > 3 (or 0 for off)");
+    lat->L2 = L2;
+    if (L2 > 0.0)
+        lat->alpha = 0.0;
     return VLB_OK;
 }
 

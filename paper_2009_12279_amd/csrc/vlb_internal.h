@@ -63,6 +63,15 @@ struct Bound {
     int32_t moving;          // any moving wall or movable particle
 };
 
+// Map from the stored stress variable to the polymer stress.  Identity for
+// Oldroyd-B and Giesekus (l2m3 = 0).  FENE-P stores T = (eta_p/lambda)(A - I)
+// of the conformation A; with g1 = f - 1 = c tr T / (l2m3 - c tr T),
+// c = lambda/eta_p, l2m3 = L^2 - 3, the stress is T + g1 T + epl g1 I,
+// epl = eta_p/lambda.
+struct StressMap {
+    float c = 0.f, l2m3 = 0.f, epl = 0.f;
+};
+
 struct StepArgs {
     Geom g;
     Bound b;
@@ -86,6 +95,7 @@ struct StepArgs {
     double eta_p_lam, inv_lam;
     float scale, inv_scale;  // storage scale s and 1/s
     float gk;                // Giesekus alpha / eta_p (0: Oldroyd-B)
+    StressMap sm;            // stored variable -> polymer stress (FENE-P)
     int32_t polymer;
     int32_t remap;           // XCD-aware block order (0 off, 1 ranges, 2 y-slabs)
     uint32_t slab_blocks;    // remap 2: blocks per XCD per z-plane
@@ -138,11 +148,12 @@ hipError_t launch_set_stress(const Geom &g, const uint8_t *mask, const double *t
                              float *tau, hipStream_t s);
 hipError_t launch_read_moments(int storage, const Geom &g, const Bound &b, const uint8_t *mask,
                                const void *f, const float *tau, int polymer, const float gvec[3],
-                               float inv_scale, double *rho_out, double *u_out, hipStream_t s);
+                               float inv_scale, double *rho_out, double *u_out, hipStream_t s,
+                               const StressMap &sm = StressMap{});
 hipError_t launch_read_populations(int storage, const Geom &g, const uint8_t *mask, const void *f,
                                    float inv_scale, double *out, hipStream_t s);
 hipError_t launch_read_stress(const Geom &g, const uint8_t *mask, const float *tau, double *out,
-                              hipStream_t s);
+                              hipStream_t s, const StressMap &sm = StressMap{});
 // FP64 population mass/momentum + health (max speed, non-finite count):
 // partial sums per block into `partials` (nblocks x 6), then a final pass
 // into out[6] = {mass_dev, px, py, pz, max_speed, non_finite}.
@@ -155,11 +166,12 @@ hipError_t launch_sums(int storage, const Geom &g, const uint8_t *mask, const vo
 constexpr int PF_BLOCKS = 32;
 hipError_t launch_particle_forces(int storage, const Geom &g, const uint8_t *mask, const void *f,
                                   const float *tau_n, int polymer, float inv_scale,
-                                  Particle *parts, int n_parts, double *partials, hipStream_t s);
+                                  Particle *parts, int n_parts, double *partials, hipStream_t s,
+                                  const StressMap &sm = StressMap{});
 // Same over wall links of the whole lattice into out[3] (two-stage).
 hipError_t launch_wall_force(int storage, const Geom &g, const uint8_t *mask, const void *f,
                              const float *tau_n, int polymer, float inv_scale, double *partials,
-                             double *out, hipStream_t s);
+                             double *out, hipStream_t s, const StressMap &sm = StressMap{});
 // Totals, symplectic Euler for movable particles.
 hipError_t launch_particle_update(const Geom &g, Particle *parts, int n_parts, hipStream_t s);
 // Fluid/solid conversion around every movable particle.

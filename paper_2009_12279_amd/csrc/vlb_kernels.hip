@@ -393,6 +393,22 @@ __constant__ int8_t kCX[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 
 __constant__ int8_t kCY[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
 __constant__ int8_t kCZ[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
 
+// Polymer stress component `comp` of cell m from the stored variable, in
+// FP64 (readouts, obstacle forces): the identity, or for FENE-P
+// T (1 + g1) + epl g1 I with g1 = f - 1 = c tr T / (l2m3 - c tr T).
+__device__ __forceinline__ double mapped_stress(const StressMap &sm, const float *tau,
+                                                uint64_t plane, uint32_t m, int comp)
+{
+    const double t = tau[comp * plane + m];
+    if (!(sm.l2m3 > 0.f))
+        return t;
+    const double c = sm.c;
+    const double tr = static_cast<double>(tau[m]) + static_cast<double>(tau[plane + m]) +
+                      static_cast<double>(tau[2 * plane + m]);
+    const double g1 = c * tr / (static_cast<double>(sm.l2m3) - c * tr);
+    return t * (1.0 + g1) + (comp < 3 ? static_cast<double>(sm.epl) * g1 : 0.0);
+}
+
 // Field-wise copies of the geometry and boundary descriptors, for argument
 // blocks that live in the constant address space (the implicit copy
 // constructor cannot bind to those).
@@ -468,7 +484,7 @@ __device__ void reflect_links(const A &a, typename Store<S>::T *fout, uint32_t n
 
 // Stream-collide of cell n of the lattice described by `a`, at step `step`
 // (the step only seeds the rounding stream).
-template <int S, bool SR, class A>
+template <int S, bool SR, bool FENE, class A>
 __device__ __forceinline__ void lb_cell(const A &a, uint32_t n, uint32_t step)
 {
     const Geom g = geom_copy(a.g);
@@ -497,6 +513,7 @@ __device__ __forceinline__ void lb_cell(const A &a, uint32_t n, uint32_t step)
     // stress of the face neighbours and of the cell itself (for the
     // constant extrapolation into solid neighbours)
     float tn[3][2][3], town[6];
+    float tdg[3][2][2];  // FENE-P: the other two diagonal entries of each face neighbour
     if (a.polymer) {
 #pragma unroll
         for (int c = 0; c < 6; ++c)
@@ -510,6 +527,10 @@ __device__ __forceinline__ void lb_cell(const A &a, uint32_t n, uint32_t step)
 #pragma unroll
                 for (int j = 0; j < 3; ++j)
                     tn[k][side][j] = *elem(a.tin_p[TROW[k][j]], m);
+                if (FENE) {
+                    tdg[k][side][0] = *elem(a.tin_p[(k + 1) % 3], m);
+                    tdg[k][side][1] = *elem(a.tin_p[(k + 2) % 3], m);
+                }
             }
     }
     auto pop = [&](int i) -> float { return f[i]; };
@@ -521,6 +542,27 @@ __device__ __forceinline__ void lb_cell(const A &a, uint32_t n, uint32_t step)
     // FP32 (a difference of stresses, small next to the populations)
     float Fp[3] = {0.f, 0.f, 0.f};
     if (a.polymer) {
+        if (FENE) {
+            // polymer stress from the stored variable: T (1 + g1) + epl g1 I,
+            // g1 = c tr T / (l2m3 - c tr T), at this cell and its neighbours
+            const float c = a.sm.c, l2m3 = a.sm.l2m3, epl = a.sm.epl;
+            const float tr0 = town[0] + town[1] + town[2];
+            const float g0 = c * tr0 / (l2m3 - c * tr0);
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+#pragma unroll
+                for (int side = 0; side < 2; ++side) {
+                    const float tr = tn[k][side][k] + tdg[k][side][0] + tdg[k][side][1];
+                    const float g1 = c * tr / (l2m3 - c * tr);
+#pragma unroll
+                    for (int j = 0; j < 3; ++j)
+                        tn[k][side][j] = fmaf(tn[k][side][j], g1, tn[k][side][j]) +
+                                         (j == k ? epl * g1 : 0.f);
+                }
+#pragma unroll
+            for (int q = 0; q < 6; ++q)
+                town[q] = fmaf(town[q], g0, town[q]) + (q < 3 ? epl * g0 : 0.f);
+        }
         // face bits of `links`: +x 1, -x 2, +y 3, -y 4, +z 5, -z 6
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
@@ -619,13 +661,13 @@ __device__ __forceinline__ void lb_cell(const A &a, uint32_t n, uint32_t step)
     }
 }
 
-template <int S, bool SR>
+template <int S, bool SR, bool FENE>
 __global__ __launch_bounds__(BLOCK) LB_OCCUPANCY void lb_step_kernel(StepArgs a)
 {
     const uint32_t n = block_id(a.remap, a.slab_blocks) * BLOCK + threadIdx.x;
     if (n >= a.g.N)
         return;
-    lb_cell<S, SR>(a, n, a.step);
+    lb_cell<S, SR, FENE>(a, n, a.step);
 }
 
 // ---------------------------------------------------------------------------
@@ -714,6 +756,14 @@ __device__ __forceinline__ void fv_compute(const A &a, const Geom &g, uint32_t n
     const int PJ[6] = {0, 1, 2, 1, 2, 2};
     const float epl = static_cast<float>(a.eta_p_lam), il = static_cast<float>(a.inv_lam);
     const float gk = a.gk;
+    // FENE-P: relaxation -(1 + g0) T / lambda - epl g0 / lambda I of the stored
+    // variable, g0 = f - 1 from this cell's trace
+    const float fl2m3 = a.sm.l2m3;
+    float g0 = 0.f;
+    if (fl2m3 > 0.f) {
+        const float fc = a.sm.c, tr = t0[0] + t0[1] + t0[2];
+        g0 = fc * tr / (fl2m3 - fc * tr);
+    }
     Rng rng(n, step, a.seed ^ 0x5bd1e995u);
     uint32_t r = 0;
 #pragma unroll
@@ -726,6 +776,11 @@ __device__ __forceinline__ void fv_compute(const A &a, const Geom &g, uint32_t n
         float inc = fmaf(-out_tot, t0[c], in_sum[c]) + sdot;
         inc = fmaf(epl, G[i][j] + G[j][i], inc);
         inc = fmaf(-t0[c], il, inc);
+        if (fl2m3 > 0.f) {
+            inc = fmaf(-t0[c] * g0, il, inc);
+            if (c < 3)
+                inc = fmaf(-epl * g0, il, inc);
+        }
         if (gk != 0.f) {
             // Giesekus: -(alpha / eta_p) (tau . tau)_ij
             float tt = 0.f;
@@ -1023,7 +1078,7 @@ __global__ __launch_bounds__(BLOCK) void lb_batch_kernel(const BatchTable *__res
     const uint32_t n = (b - bs.first_block) * BLOCK + threadIdx.x;
     if (n >= a.g.N)
         return;
-    lb_cell<ST_F32, SR>(a, n, step);
+    lb_cell<ST_F32, SR, false>(a, n, step);
 }
 
 template <bool SR>
@@ -1120,7 +1175,8 @@ __global__ __launch_bounds__(BLOCK) void read_moments_kernel(Geom g, Bound b, co
                                                              const void *fv, const float *tau,
                                                              int polymer, float gx, float gy,
                                                              float gz, float inv_scale,
-                                                             double *rho_out, double *u_out)
+                                                             double *rho_out, double *u_out,
+                                                             StressMap sm)
 {
     using St = Store<S>;
     using T = typename St::T;
@@ -1155,12 +1211,11 @@ __global__ __launch_bounds__(BLOCK) void read_moments_kernel(Geom g, Bound b, co
             const uint32_t ip = nb.at(k == 0, k == 1, k == 2);
             const uint32_t im = nb.at(-(k == 0), -(k == 1), -(k == 2));
             const uint32_t sp = mask[ip] != 0 ? n : ip;
-            const uint32_t sm = mask[im] != 0 ? n : im;
+            const uint32_t sm_ = mask[im] != 0 ? n : im;
 #pragma unroll
-            for (int jj = 0; jj < 3; ++jj) {
-                const uint64_t c = static_cast<uint64_t>(TROW[k][jj]) * g.plane;
-                F[jj] += 0.5 * (static_cast<double>(tau[c + sp]) - static_cast<double>(tau[c + sm]));
-            }
+            for (int jj = 0; jj < 3; ++jj)
+                F[jj] += 0.5 * (mapped_stress(sm, tau, g.plane, sp, TROW[k][jj]) -
+                                mapped_stress(sm, tau, g.plane, sm_, TROW[k][jj]));
         }
     }
     const double rho = 1.0 + drho;
@@ -1197,7 +1252,8 @@ __global__ __launch_bounds__(BLOCK) void read_pops_kernel(Geom g, const uint8_t 
 }
 
 __global__ __launch_bounds__(BLOCK) void read_tau_kernel(Geom g, const uint8_t *mask,
-                                                         const float *tau, double *out)
+                                                         const float *tau, double *out,
+                                                         StressMap sm)
 {
     const uint32_t n = blockIdx.x * BLOCK + threadIdx.x;
     if (n >= g.N)
@@ -1205,7 +1261,7 @@ __global__ __launch_bounds__(BLOCK) void read_tau_kernel(Geom g, const uint8_t *
     const bool fl = mask[n] == 0;
 #pragma unroll
     for (int c = 0; c < 6; ++c)
-        out[static_cast<uint64_t>(c) * g.N + n] = fl ? static_cast<double>(tau[c * g.plane + n]) : 0.0;
+        out[static_cast<uint64_t>(c) * g.N + n] = fl ? mapped_stress(sm, tau, g.plane, n, c) : 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1334,7 +1390,7 @@ __device__ __forceinline__ void box_cell(const Geom &g, const Box &bx, uint32_t 
 template <int S, class Match>
 __device__ void link_forces(const Geom &g, const uint8_t *mask, const void *fv, const float *tau,
                             int polymer, float inv_scale, int x, int y, int z, const Particle *P,
-                            Match owner_match, double acc[12])
+                            Match owner_match, double acc[12], const StressMap &sm)
 {
     using St = Store<S>;
     using T = typename St::T;
@@ -1375,7 +1431,7 @@ __device__ void link_forces(const Geom &g, const uint8_t *mask, const void *fv, 
             double dF[3];
 #pragma unroll
             for (int j = 0; j < 3; ++j)
-                dF[j] = -s * static_cast<double>(tau[TROW[k][j] * g.plane + n]);
+                dF[j] = -s * mapped_stress(sm, tau, g.plane, n, TROW[k][j]);
             acc[6] += dF[0];
             acc[7] += dF[1];
             acc[8] += dF[2];
@@ -1397,7 +1453,7 @@ __global__ __launch_bounds__(BLOCK) void particle_forces_kernel(Geom g, const ui
                                                                 const void *fv, const float *tau,
                                                                 int polymer, float inv_scale,
                                                                 const Particle *parts,
-                                                                double *partials)
+                                                                double *partials, StressMap sm)
 {
     __shared__ double sh[BLOCK / 64];
     const int p = blockIdx.y;
@@ -1413,7 +1469,7 @@ __global__ __launch_bounds__(BLOCK) void particle_forces_kernel(Geom g, const ui
         if (mask[n] != 0)
             continue;
         link_forces<S>(g, mask, fv, tau, polymer, inv_scale, x, y, z, &P,
-                       [me](uint8_t m) { return m == me; }, acc);
+                       [me](uint8_t m) { return m == me; }, acc, sm);
     }
     for (int k = 0; k < 12; ++k) {
         const double r = block_sum<BLOCK>(acc[k], sh);
@@ -1444,7 +1500,7 @@ template <int S>
 __global__ __launch_bounds__(BLOCK) void wall_force_kernel(Geom g, const uint8_t *mask,
                                                            const void *fv, const float *tau,
                                                            int polymer, float inv_scale,
-                                                           double *partials)
+                                                           double *partials, StressMap sm)
 {
     __shared__ double sh[BLOCK / 64];
     double acc[12] = {0};
@@ -1454,7 +1510,7 @@ __global__ __launch_bounds__(BLOCK) void wall_force_kernel(Geom g, const uint8_t
         int x, y, z;
         coords(g, n, x, y, z);
         link_forces<S>(g, mask, fv, tau, polymer, inv_scale, x, y, z, nullptr,
-                       [](uint8_t m) { return m != 0 && m < PART0; }, acc);
+                       [](uint8_t m) { return m != 0 && m < PART0; }, acc, sm);
     }
     for (int a = 0; a < 3; ++a) {
         const double r = block_sum<BLOCK>(acc[a] + acc[6 + a], sh);
@@ -1857,10 +1913,19 @@ hipError_t launch_lb_step(int storage, const StepArgs &a, hipStream_t s)
 {
     return dispatch(storage, [&](auto st) {
         constexpr int S = decltype(st)::value;
-        if (a.stochastic)
-            hipLaunchKernelGGL((lb_step_kernel<S, true>), dim3(blocks_for(a.g.N)), dim3(BLOCK), 0, s, a);
-        else
-            hipLaunchKernelGGL((lb_step_kernel<S, false>), dim3(blocks_for(a.g.N)), dim3(BLOCK), 0, s, a);
+        const dim3 grid(blocks_for(a.g.N)), block(BLOCK);
+        const bool fene = a.polymer && a.sm.l2m3 > 0.f;
+        if (fene) {
+            if (a.stochastic)
+                hipLaunchKernelGGL((lb_step_kernel<S, true, true>), grid, block, 0, s, a);
+            else
+                hipLaunchKernelGGL((lb_step_kernel<S, false, true>), grid, block, 0, s, a);
+        } else {
+            if (a.stochastic)
+                hipLaunchKernelGGL((lb_step_kernel<S, true, false>), grid, block, 0, s, a);
+            else
+                hipLaunchKernelGGL((lb_step_kernel<S, false, false>), grid, block, 0, s, a);
+        }
         return hipGetLastError();
     });
 }
@@ -1955,12 +2020,13 @@ hipError_t launch_set_stress(const Geom &g, const uint8_t *mask, const double *t
 
 hipError_t launch_read_moments(int storage, const Geom &g, const Bound &b, const uint8_t *mask,
                                const void *f, const float *tau, int polymer, const float gvec[3],
-                               float inv_scale, double *rho_out, double *u_out, hipStream_t s)
+                               float inv_scale, double *rho_out, double *u_out, hipStream_t s,
+                               const StressMap &sm)
 {
     return dispatch(storage, [&](auto st) {
         hipLaunchKernelGGL(read_moments_kernel<decltype(st)::value>, dim3(blocks_for(g.N)),
                            dim3(BLOCK), 0, s, g, b, mask, f, tau, polymer, gvec[0], gvec[1],
-                           gvec[2], inv_scale, rho_out, u_out);
+                           gvec[2], inv_scale, rho_out, u_out, sm);
         return hipGetLastError();
     });
 }
@@ -1976,10 +2042,10 @@ hipError_t launch_read_populations(int storage, const Geom &g, const uint8_t *ma
 }
 
 hipError_t launch_read_stress(const Geom &g, const uint8_t *mask, const float *tau, double *out,
-                              hipStream_t s)
+                              hipStream_t s, const StressMap &sm)
 {
     hipLaunchKernelGGL(read_tau_kernel, dim3(blocks_for(g.N)), dim3(BLOCK), 0, s, g, mask, tau,
-                       out);
+                       out, sm);
     return hipGetLastError();
 }
 
@@ -2006,14 +2072,15 @@ hipError_t launch_sums(int storage, const Geom &g, const uint8_t *mask, const vo
 
 hipError_t launch_particle_forces(int storage, const Geom &g, const uint8_t *mask, const void *f,
                                   const float *tau_n, int polymer, float inv_scale,
-                                  Particle *parts, int n_parts, double *partials, hipStream_t s)
+                                  Particle *parts, int n_parts, double *partials, hipStream_t s,
+                                  const StressMap &sm)
 {
     if (n_parts <= 0)
         return hipSuccess;
     hipError_t e = dispatch(storage, [&](auto st) {
         hipLaunchKernelGGL(particle_forces_kernel<decltype(st)::value>, dim3(PF_BLOCKS, n_parts),
                            dim3(BLOCK), 0, s, g, mask, f, tau_n, polymer, inv_scale, parts,
-                           partials);
+                           partials, sm);
         return hipGetLastError();
     });
     if (e != hipSuccess)
@@ -2025,12 +2092,12 @@ hipError_t launch_particle_forces(int storage, const Geom &g, const uint8_t *mas
 
 hipError_t launch_wall_force(int storage, const Geom &g, const uint8_t *mask, const void *f,
                              const float *tau_n, int polymer, float inv_scale, double *partials,
-                             double *out, hipStream_t s)
+                             double *out, hipStream_t s, const StressMap &sm)
 {
     const int nb = sums_blocks(g);
     hipError_t e = dispatch(storage, [&](auto st) {
         hipLaunchKernelGGL(wall_force_kernel<decltype(st)::value>, dim3(nb), dim3(BLOCK), 0, s, g,
-                           mask, f, tau_n, polymer, inv_scale, partials);
+                           mask, f, tau_n, polymer, inv_scale, partials, sm);
         return hipGetLastError();
     });
     if (e != hipSuccess)

@@ -105,6 +105,7 @@ SIGNATURES = [
     ("vlb_set_rounding", ctypes.c_int, [_P, ctypes.c_int, ctypes.c_uint32]),
     ("vlb_set_counter_force", ctypes.c_int, [_P, ctypes.c_int32]),
     ("vlb_set_giesekus", ctypes.c_int, [_P, ctypes.c_double]),
+    ("vlb_set_fene_p", ctypes.c_int, [_P, ctypes.c_double]),
     ("vlb_server_create", ctypes.c_int, [ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32, _P,
                                          ctypes.POINTER(_P)]),
     ("vlb_server_set_rounding", ctypes.c_int, [_P, ctypes.c_int]),
@@ -378,6 +379,10 @@ def vlb_set_giesekus(h, alpha):
     return _check(lib().vlb_set_giesekus(h, float(alpha)), h)
 
 
+def vlb_set_fene_p(h, L2):
+    return _check(lib().vlb_set_fene_p(h, float(L2)), h)
+
+
 def vlb_set_counter_force(h, on=True):
     return _check(lib().vlb_set_counter_force(h, 1 if on else 0), h)
 
@@ -513,6 +518,9 @@ class Lattice:
 
     def set_giesekus(self, alpha):
         vlb_set_giesekus(self._h, alpha)
+
+    def set_fene_p(self, L2):
+        vlb_set_fene_p(self._h, L2)
 
 
 # ---- serving ------------------------------------------------------------------

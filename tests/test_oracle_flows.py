@@ -262,3 +262,23 @@ def test_counter_force_keeps_total_momentum_constant(orc):
     _, pf = L2.sums()
     led = pf + M * L2.particle(0)["vel"] + L2.pending_conversion()
     np.testing.assert_allclose(led - pf0, 5 * fext, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("model", ["giesekus", "fene_p"])
+def test_momentum_balance_holds_for_other_constitutive_laws(orc, model):
+    """The exact momentum balance of the fixed-geometry lattice (polymer force
+    telescoping to the traction on the obstacles) holds unchanged when the
+    stress comes from the Giesekus or FENE-P law."""
+    L, m, g = _fixed_geometry(orc, 3)
+    if model == "giesekus":
+        L.set_giesekus(0.3)
+    else:
+        L.set_fene_p(10.0)
+    Nf = int((m == 0).sum())
+    _, p0 = L.sums()
+    for _ in range(10):
+        L.step(1)
+        _, p1 = L.sums()
+        obstacles = L.wall_force() + L.particle(0)["force"]
+        np.testing.assert_allclose(p1 - p0 + obstacles, Nf * g, rtol=0, atol=1e-13)
+        p0 = p1

@@ -254,3 +254,46 @@ def test_giesekus_channel():
     assert e["u"][0] < 1e-5 and e["tau"][0] < 1e-5
     # shear thinning shows: tau_yy < 0 in the bulk, unlike Oldroyd-B
     assert o.stress()[1][:, 10:-10, :].max() < 0
+
+
+@pytest.mark.parametrize("steps", [1, 30])
+def test_fene_p_random_lattice(steps):
+    """FENE-P (L^2 = 10) on a random lattice with moving walls and a sphere:
+    stored variable, polymer stress, populations, and the forces on the
+    sphere and walls, GPU against the oracle."""
+    case = random_case(22, (10, 9, 8), (1, 0, 1), True, ((4.6, 4.3, 3.9), 2.0))
+    case.tau0 = case.tau0 * 5.0
+    log(f"[parity] fene-p random lattice, {steps} steps")
+    g, o = build(case)
+    g.set_fene_p(10.0)
+    o.set_fene_p(10.0)
+    g.step(steps)
+    o.step(steps)
+    e = compare(g, o, case)
+    log(f"[parity]   errors {e}")
+    tol = 2e-6 if steps == 1 else 1e-5
+    for k in ("f", "u", "tau", "rho"):
+        assert e[k][0] < tol, (k, e[k])
+    pg, po = g.particle(0), o.particle(0)
+    np.testing.assert_allclose(pg["force"], po["force"], rtol=0,
+                               atol=1e-5 * np.abs(po["force"]).max())
+    wo = o.wall_force()
+    np.testing.assert_allclose(g.wall_force(), wo, rtol=0, atol=1e-5 * np.abs(wo).max() + 1e-12)
+
+
+def test_fene_p_channel():
+    """The 4x64x4 channel with FENE-P (L^2 = 20, lambda = 2000), 5000 steps
+    (the peak stress is a few percent below Oldroyd-B's by then)."""
+    shape = (4, 64, 4)
+    mask = inputs.channel_mask(shape, wall_axes=(1,))
+    case = Case("channel-fene-p", shape, mask, (1, 0, 1), None,
+                dict(eta=1 / 3, beta=0.5, lambda_p=2000.0, magic=-1.0, body_force=(1e-5, 0, 0)))
+    log("[parity] fene-p channel 4x64x4 5000 steps")
+    g, o = build(case)
+    g.set_fene_p(20.0)
+    o.set_fene_p(20.0)
+    g.step(5000)
+    o.step(5000)
+    e = compare(g, o, case, what=("u", "tau"))
+    log(f"[parity]   errors {e}")
+    assert e["u"][0] < 1e-5 and e["tau"][0] < 1e-5
