@@ -380,7 +380,7 @@ def main():
                          "counters can be scaled against a kernel of known traffic")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: runs on one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU slab decomposition is a design note, not built)", file=sys.stderr)
         sys.exit(2)
     rank = int(os.environ.get("RANK", "0"))
