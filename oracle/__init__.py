@@ -79,6 +79,9 @@ def lib():
         L.or_fv_apply.argtypes = [I, I, I, ctypes.c_char_p, D, D, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_double, ctypes.c_double, D]
         L.or_polymer_force.argtypes = [I, I, I, ctypes.c_char_p, D, D]
+        L.or_polymer_force_ext.argtypes = [I, I, I, ctypes.c_char_p, D, I, D]
+        L.or_set_extrapolation.restype = I
+        L.or_set_extrapolation.argtypes = [P, I]
         L.or_set_threads.argtypes = [I]
         L.or_get_threads.restype = I
         _lib = L
@@ -149,12 +152,14 @@ def fv_apply(mask, tau, u, eta_p, lambda_p, alpha=0.0, L2=0.0):
     return out
 
 
-def polymer_force(mask, tau):
+def polymer_force(mask, tau, order=0):
+    """Discrete polymer force; `order` of the extrapolation into solid face
+    neighbours (0 constant, 1 linear)."""
     nz, ny, nx = mask.shape
     m = np.ascontiguousarray(mask, dtype=np.uint8)
     t = np.ascontiguousarray(tau, dtype=np.float64)
     out = np.zeros((3,) + mask.shape)
-    lib().or_polymer_force(nx, ny, nz, m.tobytes(), _dp(t), _dp(out))
+    lib().or_polymer_force_ext(nx, ny, nz, m.tobytes(), _dp(t), int(order), _dp(out))
     return out
 
 
@@ -208,6 +213,10 @@ class Lattice:
     def set_giesekus(self, alpha):
         if lib().or_set_giesekus(self._h, float(alpha)) != 0:
             raise ValueError("oracle: Giesekus mobility must lie in [0, 1/2]")
+
+    def set_extrapolation(self, order):
+        if lib().or_set_extrapolation(self._h, int(order)) != 0:
+            raise ValueError("oracle: extrapolation order must be 0 or 1")
 
     def set_fene_p(self, L2):
         if lib().or_set_fene_p(self._h, float(L2)) != 0:

@@ -227,8 +227,39 @@ static void tau_put(double *tau, long N, long n, double t[3][3])
 /* ------------------------------------------------------------------ */
 /* Section 3.3: polymer force and finite-volume stress update */
 
+/* Stress taken for a solid face neighbour of fluid cell n in direction k
+ * (Section 3.3, extrapolation into boundary nodes): this cell's stress
+ * (constant, order 0), or with order 1 the linear extrapolation
+ * 2 tau(n) - tau(n - e_k) when the cell behind n is fluid (else constant). */
+static void boundary_stress(int nx, int ny, int nz, const unsigned char *mask, const double *tau,
+                            long N, int x, int y, int z, int k, int order, double tb[3][3])
+{
+    long n = cell(nx, ny, x, y, z);
+    tau_get(tau, N, n, tb);
+    if (order < 1)
+        return;
+    int back[3] = {-FACE[k][0], -FACE[k][1], -FACE[k][2]};
+    long b = nbr(nx, ny, nz, x, y, z, back);
+    if (mask[b] != 0)
+        return;
+    double tm[3][3];
+    tau_get(tau, N, b, tm);
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            tb[i][j] = 2.0 * tb[i][j] - tm[i][j];
+}
+
+void or_polymer_force_ext(int nx, int ny, int nz, const unsigned char *mask, const double *tau,
+                          int order, double *fp);
+
 void or_polymer_force(int nx, int ny, int nz, const unsigned char *mask, const double *tau,
                       double *fp)
+{
+    or_polymer_force_ext(nx, ny, nz, mask, tau, 0, fp);
+}
+
+void or_polymer_force_ext(int nx, int ny, int nz, const unsigned char *mask, const double *tau,
+                          int order, double *fp)
 {
     long N = (long)nx * ny * nz;
 #pragma omp parallel for schedule(static) num_threads(or_get_threads())
@@ -249,7 +280,7 @@ void or_polymer_force(int nx, int ny, int nz, const unsigned char *mask, const d
                         if (mask[m] == 0)
                             tau_get(tau, N, m, tn);
                         else
-                            tau_get(tau, N, n, tn);
+                            boundary_stress(nx, ny, nz, mask, tau, N, x, y, z, k, order, tn);
                         for (int a = 0; a < 3; ++a) {
                             if (FACE[k][a] == 0)
                                 continue;
@@ -397,6 +428,7 @@ struct or_lattice {
     int counter_force;               /* -sum of the free particles' F_ext spread over the fluid */
     double alpha;                    /* Giesekus mobility (0: Oldroyd-B) */
     double L2;                       /* FENE-P extensibility L^2 (0: not FENE-P) */
+    int extrap;                      /* stress extrapolation into solid nodes: 0 constant, 1 linear */
     double *stress;                  /* polymer stress of the stored state (6*N) */
     double wp, wm, eta_p;
     int polymer;
@@ -684,6 +716,14 @@ int or_set_giesekus(or_lattice *L, double alpha)
     return 0;
 }
 
+int or_set_extrapolation(or_lattice *L, int order)
+{
+    if (order < 0 || order > 1)
+        return -1;
+    L->extrap = order;
+    return 0;
+}
+
 int or_set_fene_p(or_lattice *L, double L2)
 {
     if (!(L2 == 0.0 || L2 > 3.0))
@@ -751,7 +791,7 @@ void or_step(or_lattice *L, long n_steps)
         /* S1: polymer force from tau^n (the stress of the stored state) */
         if (L->polymer) {
             state_stress(L, L->tau, L->stress);
-            or_polymer_force(nx, ny, nz, mask, L->stress, L->fp);
+            or_polymer_force_ext(nx, ny, nz, mask, L->stress, L->extrap, L->fp);
         }
         else
             memset(L->fp, 0, sizeof(double) * 3 * N);
@@ -831,11 +871,14 @@ void or_step(or_lattice *L, long n_steps)
                             long m = nbr(nx, ny, nz, x, y, z, FACE[k]);
                             if (mask[m] == 0)
                                 continue;
+                            /* the face value the polymer force used at this face */
+                            double tb[3][3];
+                            boundary_stress(nx, ny, nz, mask, L->stress, N, x, y, z, k, L->extrap, tb);
                             double dF[3];
                             for (int jj = 0; jj < 3; ++jj) {
                                 double s = 0.0;
                                 for (int a = 0; a < 3; ++a)
-                                    s += FACE[k][a] * t[a][jj];
+                                    s += FACE[k][a] * 0.5 * (t[a][jj] + tb[a][jj]);
                                 dF[jj] = -s;
                             }
                             credit(L, mask[m], wrap(x + FACE[k][0], nx), wrap(y + FACE[k][1], ny),
@@ -1075,7 +1118,7 @@ static double *current_force(const or_lattice *L)
     if (L->polymer) {
         double *st = (double *)malloc(sizeof(double) * 6 * N);
         state_stress(L, L->tau, st);
-        or_polymer_force(L->n[0], L->n[1], L->n[2], L->mask, st, fp);
+        or_polymer_force_ext(L->n[0], L->n[1], L->n[2], L->mask, st, L->extrap, fp);
         free(st);
     }
     return fp;

@@ -56,6 +56,11 @@ void or_fv_apply(int nx, int ny, int nz, const unsigned char *mask, const double
 /* The discrete polymer force of Section 3.3 for a stress field (fluid cells). */
 void or_polymer_force(int nx, int ny, int nz, const unsigned char *mask, const double *tau,
                       double *fp_out);
+/* Same with the extrapolation into solid face neighbours of order 0
+ * (constant, as above) or 1 (linear through the cell behind, constant when
+ * that cell is solid). */
+void or_polymer_force_ext(int nx, int ny, int nz, const unsigned char *mask, const double *tau,
+                          int order, double *fp);
 
 or_lattice *or_create(int nx, int ny, int nz, const int periodic[3], const unsigned char *mask,
                       const double *wall_vel, int n_walls);
@@ -76,6 +81,10 @@ int or_set_giesekus(or_lattice *L, double alpha);
  * T = (eta_p/lambda)(A - I); or_set_stress sets T, or_read_stress returns
  * the polymer stress tau = f T + (eta_p/lambda)(f - 1) I. */
 int or_set_fene_p(or_lattice *L, double L2);
+/* Stress extrapolation into solid face neighbours (Section 3.3): 0 constant
+ * (default), 1 linear; the traction on obstacles uses the same face values.
+ * -1 for other orders. */
+int or_set_extrapolation(or_lattice *L, int order);
 void or_init_equilibrium(or_lattice *L, const double *u);
 void or_set_populations(or_lattice *L, const double *f);
 void or_set_stress(or_lattice *L, const double *tau);

@@ -282,3 +282,18 @@ def test_momentum_balance_holds_for_other_constitutive_laws(orc, model):
         obstacles = L.wall_force() + L.particle(0)["force"]
         np.testing.assert_allclose(p1 - p0 + obstacles, Nf * g, rtol=0, atol=1e-13)
         p0 = p1
+
+
+def test_momentum_balance_holds_with_linear_extrapolation(orc):
+    """The traction on obstacles uses the face values the polymer force used,
+    so the exact momentum balance also holds with linear extrapolation."""
+    L, m, g = _fixed_geometry(orc, 4)
+    L.set_extrapolation(1)
+    Nf = int((m == 0).sum())
+    _, p0 = L.sums()
+    for _ in range(10):
+        L.step(1)
+        _, p1 = L.sums()
+        obstacles = L.wall_force() + L.particle(0)["force"]
+        np.testing.assert_allclose(p1 - p0 + obstacles, Nf * g, rtol=0, atol=1e-13)
+        p0 = p1

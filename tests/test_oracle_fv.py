@@ -264,3 +264,33 @@ def test_fene_p_steady_shear_matches_the_conformation_solution(orc):
         T_ob = orc.fv_apply(mask, T_ob, u, eta_p, lam)
         T_fe = orc.fv_apply(mask, T_fe, u, eta_p, lam, L2=1e12)
     np.testing.assert_allclose(T_fe, T_ob, rtol=1e-8, atol=1e-9 * np.abs(T_ob).max())
+
+
+def test_linear_extrapolation_reproduces_the_divergence_next_to_walls(orc):
+    """With linear extrapolation into solid neighbours (Section 3.3 offers it
+    beside the constant one) the discrete force of a linear stress field is
+    its divergence also in cells next to a wall (two fluid layers behind
+    them), where constant extrapolation is off by half a gradient."""
+    rng = np.random.default_rng(15)
+    nx, ny, nz = 7, 10, 9
+    mask = np.zeros((nz, ny, nx), np.uint8)
+    mask[:, 0, :] = 1
+    mask[:, -1, :] = 1
+    A = rng.standard_normal(6)
+    B = rng.standard_normal((6, 3))
+    B[:, 0] = 0.0  # x periodic: no x gradient
+    B[:, 2] = 0.0  # z periodic: no z gradient
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    tau = np.stack([A[k] + B[k, 1] * y for k in range(6)])
+    t3 = np.zeros((3, 3, 3))
+    for k, (i, j) in enumerate(TAU_PAIRS):
+        t3[i, j] = t3[j, i] = B[k]
+    div = np.array([sum(t3[k, j, k] for k in range(3)) for j in range(3)])
+    lin = orc.polymer_force(mask, tau, order=1)
+    const = orc.polymer_force(mask, tau, order=0)
+    fluid = mask == 0
+    for j in range(3):
+        np.testing.assert_allclose(lin[j][fluid], div[j], rtol=1e-12, atol=1e-12)
+    # constant extrapolation: the wall rows see half the normal gradient
+    wall_rows = const[:, :, [1, -2], :]
+    assert np.max(np.abs(wall_rows[1] - div[1])) > 0.1 * np.abs(div[1])
