@@ -225,6 +225,14 @@ vlb_status vlb_set_giesekus(vlb_lattice *lat, double alpha);
  * vlb_set_giesekus and vlb_set_fene_p wins.  Kept in checkpoints. */
 vlb_status vlb_set_fene_p(vlb_lattice *lat, double L2);
 
+/* Extrapolation of the stress into solid face neighbours for the polymer
+ * force (Section 3.3): 0 takes the fluid cell's own stress (the default), 1
+ * extrapolates linearly through the cell behind it, 2 tau(x) - tau(x - e),
+ * falling back to the own stress where that cell is solid.  The traction on
+ * obstacles uses the same face values, so momentum stays balanced.
+ * VLB_EINVAL for other orders.  Kept in checkpoints. */
+vlb_status vlb_set_stress_extrapolation(vlb_lattice *lat, int32_t order);
+
 /* Counter-force for periodic systems with free particles (Section 4.5):
  * when on, every step subtracts the summed external force of the movable
  * particles from the body force, spread evenly over the cells that are

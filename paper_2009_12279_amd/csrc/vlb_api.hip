@@ -102,9 +102,11 @@ struct vlb_lattice {
     bool counter_force = false;
     double alpha = 0.0;           // Giesekus mobility
     double L2 = 0.0;              // FENE-P extensibility (0: off)
+    int extrap = 0;               // stress extrapolation into solid neighbours
     vlb::StressMap stress_map() const
     {
         vlb::StressMap m;
+        m.extrap = extrap;
         if (L2 > 0.0 && polymer) {
             const double eta_p = params.beta * params.eta;
             m.c = static_cast<float>(params.lambda_p / eta_p);
@@ -1094,7 +1096,7 @@ vlb_status vlb_set_check_interval(vlb_lattice *lat, int64_t steps)
 // checkpoint
 
 namespace {
-constexpr uint64_t kMagic = 0x35304B434C424C56ull;  // "VLBLCK05"
+constexpr uint64_t kMagic = 0x36304B434C424C56ull;  // "VLBLCK06"
 
 struct FileHeader {
     uint64_t magic;
@@ -1107,7 +1109,7 @@ struct FileHeader {
     int32_t rounding;  // vlb_rounding of stored values
     uint32_t seed;     // seed of the stochastic-rounding stream
     int32_t counter_force;
-    int32_t reserved;
+    int32_t extrap;
     double alpha;
     double L2;
 };
@@ -1167,6 +1169,7 @@ vlb_status vlb_save(vlb_lattice *lat, const char *path)
     h.counter_force = lat->counter_force ? 1 : 0;
     h.alpha = lat->alpha;
     h.L2 = lat->L2;
+    h.extrap = lat->extrap;
     bool ok = std::fwrite(&h, sizeof h, 1, fp) == 1;
     ok = ok && std::fwrite(lat->wall_h.data(), sizeof(double), 64 * 3, fp) == 64 * 3;
     ok = ok && (parts.empty() || std::fwrite(parts.data(), sizeof(Particle), parts.size(), fp) ==
@@ -1248,6 +1251,7 @@ vlb_status vlb_load(const char *path, void *stream, vlb_lattice **out)
     lat->counter_force = h.counter_force != 0;
     lat->alpha = (h.alpha >= 0.0 && h.alpha <= 0.5) ? h.alpha : 0.0;
     lat->L2 = (h.L2 > 3.0 && std::isfinite(h.L2)) ? h.L2 : 0.0;
+    lat->extrap = h.extrap == 1 ? 1 : 0;
     lat->scale = h.scale;
     lat->inv_scale = 1.f / h.scale;
     hipError_t e = hipMemcpyAsync(lat->d_mask, mask.data(), N, hipMemcpyHostToDevice, lat->stream);
@@ -1296,6 +1300,16 @@ vlb_status vlb_set_giesekus(vlb_lattice *lat, double alpha)
     lat->alpha = alpha;
     if (alpha > 0.0)
         lat->L2 = 0.0;
+    return VLB_OK;
+}
+
+vlb_status vlb_set_stress_extrapolation(vlb_lattice *lat, int32_t order)
+{
+    if (!lat)
+        return VLB_EINVAL;
+    if (order < 0 || order > 1)
+        return fail(lat, VLB_EINVAL, "vlb_set_stress_extrapolation: order must be 0 or 1");
+    lat->extrap = order;
     return VLB_OK;
 }
 

@@ -70,6 +70,9 @@ struct Bound {
 // epl = eta_p/lambda.
 struct StressMap {
     float c = 0.f, l2m3 = 0.f, epl = 0.f;
+    // extrapolation into a solid face neighbour: 0 this cell's stress, 1 linear
+    // through the cell behind (constant where that cell is solid)
+    int32_t extrap = 0;
 };
 
 struct StepArgs {

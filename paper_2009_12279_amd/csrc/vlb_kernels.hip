@@ -564,13 +564,28 @@ __device__ __forceinline__ void lb_cell(const A &a, uint32_t n, uint32_t step)
                 town[q] = fmaf(town[q], g0, town[q]) + (q < 3 ? epl * g0 : 0.f);
         }
         // face bits of `links`: +x 1, -x 2, +y 3, -y 4, +z 5, -z 6
+        if (a.sm.extrap && ((links >> 1) & 63u)) {
+            // linear extrapolation into solid face neighbours (rare path)
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const bool sp = (links >> (2 * k + 1)) & 1u, sm = (links >> (2 * k + 2)) & 1u;
+            for (int k = 0; k < 3; ++k) {
+                const bool sp = (links >> (2 * k + 1)) & 1u, sm = (links >> (2 * k + 2)) & 1u;
 #pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                const float own = town[TROW[k][j]];
-                Fp[j] += 0.5f * ((sp ? own : tn[k][0][j]) - (sm ? own : tn[k][1][j]));
+                for (int j = 0; j < 3; ++j) {
+                    const float own = town[TROW[k][j]];
+                    const float vp = sp ? (sm ? own : 2.f * own - tn[k][1][j]) : tn[k][0][j];
+                    const float vm = sm ? (sp ? own : 2.f * own - tn[k][0][j]) : tn[k][1][j];
+                    Fp[j] += 0.5f * (vp - vm);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const bool sp = (links >> (2 * k + 1)) & 1u, sm = (links >> (2 * k + 2)) & 1u;
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    const float own = town[TROW[k][j]];
+                    Fp[j] += 0.5f * ((sp ? own : tn[k][0][j]) - (sm ? own : tn[k][1][j]));
+                }
             }
         }
     }
@@ -1210,12 +1225,19 @@ __global__ __launch_bounds__(BLOCK) void read_moments_kernel(Geom g, Bound b, co
         for (int k = 0; k < 3; ++k) {
             const uint32_t ip = nb.at(k == 0, k == 1, k == 2);
             const uint32_t im = nb.at(-(k == 0), -(k == 1), -(k == 2));
-            const uint32_t sp = mask[ip] != 0 ? n : ip;
-            const uint32_t sm_ = mask[im] != 0 ? n : im;
+            const bool solp = mask[ip] != 0, solm = mask[im] != 0;
 #pragma unroll
-            for (int jj = 0; jj < 3; ++jj)
-                F[jj] += 0.5 * (mapped_stress(sm, tau, g.plane, sp, TROW[k][jj]) -
-                                mapped_stress(sm, tau, g.plane, sm_, TROW[k][jj]));
+            for (int jj = 0; jj < 3; ++jj) {
+                const double own = mapped_stress(sm, tau, g.plane, n, TROW[k][jj]);
+                const double tp = solp ? own : mapped_stress(sm, tau, g.plane, ip, TROW[k][jj]);
+                const double tm = solm ? own : mapped_stress(sm, tau, g.plane, im, TROW[k][jj]);
+                double vp = tp, vm = tm;
+                if (sm.extrap && solp && !solm)
+                    vp = 2.0 * own - tm;
+                if (sm.extrap && solm && !solp)
+                    vm = 2.0 * own - tp;
+                F[jj] += 0.5 * (vp - vm);
+            }
         }
     }
     const double rho = 1.0 + drho;
@@ -1428,10 +1450,18 @@ __device__ void link_forces(const Geom &g, const uint8_t *mask, const void *fv, 
             const uint32_t m = nb.at(cx, cy, cz);
             if (!owner_match(mask[m]))
                 continue;
+            // the face value the polymer force used: this cell's stress, or
+            // with linear extrapolation the mean of it and 2 tau(n) - tau(behind)
+            const uint32_t bk = nb.at(-cx, -cy, -cz);
+            const bool lin = sm.extrap && mask[bk] == 0;
             double dF[3];
 #pragma unroll
-            for (int j = 0; j < 3; ++j)
-                dF[j] = -s * mapped_stress(sm, tau, g.plane, n, TROW[k][j]);
+            for (int j = 0; j < 3; ++j) {
+                const double own = mapped_stress(sm, tau, g.plane, n, TROW[k][j]);
+                const double face =
+                    lin ? 1.5 * own - 0.5 * mapped_stress(sm, tau, g.plane, bk, TROW[k][j]) : own;
+                dF[j] = -s * face;
+            }
             acc[6] += dF[0];
             acc[7] += dF[1];
             acc[8] += dF[2];

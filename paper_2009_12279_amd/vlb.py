@@ -106,6 +106,7 @@ SIGNATURES = [
     ("vlb_set_counter_force", ctypes.c_int, [_P, ctypes.c_int32]),
     ("vlb_set_giesekus", ctypes.c_int, [_P, ctypes.c_double]),
     ("vlb_set_fene_p", ctypes.c_int, [_P, ctypes.c_double]),
+    ("vlb_set_stress_extrapolation", ctypes.c_int, [_P, ctypes.c_int32]),
     ("vlb_server_create", ctypes.c_int, [ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32, _P,
                                          ctypes.POINTER(_P)]),
     ("vlb_server_set_rounding", ctypes.c_int, [_P, ctypes.c_int]),
@@ -383,6 +384,10 @@ def vlb_set_fene_p(h, L2):
     return _check(lib().vlb_set_fene_p(h, float(L2)), h)
 
 
+def vlb_set_stress_extrapolation(h, order):
+    return _check(lib().vlb_set_stress_extrapolation(h, int(order)), h)
+
+
 def vlb_set_counter_force(h, on=True):
     return _check(lib().vlb_set_counter_force(h, 1 if on else 0), h)
 
@@ -521,6 +526,9 @@ class Lattice:
 
     def set_fene_p(self, L2):
         vlb_set_fene_p(self._h, L2)
+
+    def set_extrapolation(self, order):
+        vlb_set_stress_extrapolation(self._h, order)
 
 
 # ---- serving ------------------------------------------------------------------

@@ -297,3 +297,27 @@ def test_fene_p_channel():
     e = compare(g, o, case, what=("u", "tau"))
     log(f"[parity]   errors {e}")
     assert e["u"][0] < 1e-5 and e["tau"][0] < 1e-5
+
+
+@pytest.mark.parametrize("steps", [1, 30])
+def test_linear_extrapolation_random_lattice(steps):
+    """Linear stress extrapolation into solid neighbours on a random lattice
+    with moving walls and a sphere, GPU against the oracle (fields and the
+    forces on sphere and walls)."""
+    case = random_case(23, (10, 9, 8), (1, 0, 1), True, ((4.6, 4.3, 3.9), 2.0))
+    log(f"[parity] linear extrapolation random lattice, {steps} steps")
+    g, o = build(case)
+    g.set_extrapolation(1)
+    o.set_extrapolation(1)
+    g.step(steps)
+    o.step(steps)
+    e = compare(g, o, case)
+    log(f"[parity]   errors {e}")
+    tol = 2e-6 if steps == 1 else 1e-5
+    for k in ("f", "u", "tau", "rho"):
+        assert e[k][0] < tol, (k, e[k])
+    pg, po = g.particle(0), o.particle(0)
+    np.testing.assert_allclose(pg["force"], po["force"], rtol=0,
+                               atol=1e-5 * np.abs(po["force"]).max())
+    wo = o.wall_force()
+    np.testing.assert_allclose(g.wall_force(), wo, rtol=0, atol=1e-5 * np.abs(wo).max() + 1e-12)
