@@ -18,7 +18,7 @@ def flags():
         f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
         # no packed FP32 instructions anywhere in the device code
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-        "-munsafe-fp-atomics" if False else "-fno-gpu-rdc",
+        "-fno-gpu-rdc",
         "-Wall", "-Wno-unused-result",
         "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
     ]
