@@ -227,11 +227,21 @@ vlb_status vlb_set_fene_p(vlb_lattice *lat, double L2);
 
 /* Extrapolation of the stress into solid face neighbours for the polymer
  * force (Section 3.3): 0 takes the fluid cell's own stress (the default), 1
- * extrapolates linearly through the cell behind it, 2 tau(x) - tau(x - e),
- * falling back to the own stress where that cell is solid.  The traction on
+ * extrapolates linearly through the cell behind it, as
+ * 2 tau(x) - tau(x - e), falling back to the own stress where that cell is
+ * solid.  The traction on
  * obstacles uses the same face values, so momentum stays balanced.
  * VLB_EINVAL for other orders.  Kept in checkpoints. */
 vlb_status vlb_set_stress_extrapolation(vlb_lattice *lat, int32_t order);
+
+/* Wall velocity that varies along a wall (Section 3.1 velocity boundary
+ * condition; the regularized lid of the lid-driven cavity, Section 4.3).
+ * u: 3*N doubles, the x, y and z planes in cell order, copied.  When set,
+ * every wall cell (mask 1..63) moves with its own entry and the per-id
+ * table is ignored; entries of other cells are not read.  NULL frees the
+ * field and returns to the table.  Synchronises the lattice's stream.
+ * Errors: VLB_EINVAL (non-finite value), VLB_ENOMEM.  Kept in checkpoints. */
+vlb_status vlb_set_wall_velocity_field(vlb_lattice *lat, const double *u);
 
 /* Counter-force for periodic systems with free particles (Section 4.5):
  * when on, every step subtracts the summed external force of the movable

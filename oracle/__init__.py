@@ -81,6 +81,7 @@ def lib():
         L.or_polymer_force.argtypes = [I, I, I, ctypes.c_char_p, D, D]
         L.or_polymer_force_ext.argtypes = [I, I, I, ctypes.c_char_p, D, I, D]
         L.or_set_extrapolation.restype = I
+        L.or_set_wall_velocity_field.argtypes = [P, D]
         L.or_set_extrapolation.argtypes = [P, I]
         L.or_set_threads.argtypes = [I]
         L.or_get_threads.restype = I
@@ -213,6 +214,17 @@ class Lattice:
     def set_giesekus(self, alpha):
         if lib().or_set_giesekus(self._h, float(alpha)) != 0:
             raise ValueError("oracle: Giesekus mobility must lie in [0, 1/2]")
+
+    def set_wall_velocity_field(self, u):
+        """Per-cell wall velocity, shape (3, nz, ny, nx); None returns to
+        the per-id table."""
+        if u is None:
+            lib().or_set_wall_velocity_field(self._h, None)
+        else:
+            u = np.ascontiguousarray(u, dtype=np.float64)
+            nx, ny, nz = self.shape
+            assert u.shape == (3, nz, ny, nx)
+            lib().or_set_wall_velocity_field(self._h, _dp(u))
 
     def set_extrapolation(self, order):
         if lib().or_set_extrapolation(self._h, int(order)) != 0:

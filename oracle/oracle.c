@@ -424,6 +424,7 @@ struct or_lattice {
     unsigned char *mask;
     double *wall_vel;
     int n_walls;
+    double *wall_field;              /* per-cell wall velocity (3*N) or NULL */
     double eta, beta, lambda, magic, g[3];
     int counter_force;               /* -sum of the free particles' F_ext spread over the fluid */
     double alpha;                    /* Giesekus mobility (0: Oldroyd-B) */
@@ -487,6 +488,7 @@ void or_destroy(or_lattice *L)
         return;
     free(L->mask);
     free(L->wall_vel);
+    free(L->wall_field);
     free(L->f);
     free(L->fnew);
     free(L->fpost);
@@ -627,7 +629,10 @@ static void boundary_velocity(const or_lattice *L, long n, int x, int y, int z, 
     if (m == 0)
         return;
     if (m < PART0) {
-        if (m <= L->n_walls)
+        if (L->wall_field)
+            for (int a = 0; a < 3; ++a)
+                ub[a] = L->wall_field[a * L->N + n];
+        else if (m <= L->n_walls)
             for (int a = 0; a < 3; ++a)
                 ub[a] = L->wall_vel[3 * (m - 1) + a];
         return;
@@ -714,6 +719,16 @@ int or_set_giesekus(or_lattice *L, double alpha)
     if (alpha > 0.0)
         L->L2 = 0.0;
     return 0;
+}
+
+void or_set_wall_velocity_field(or_lattice *L, const double *u)
+{
+    free(L->wall_field);
+    L->wall_field = NULL;
+    if (!u)
+        return;
+    L->wall_field = (double *)malloc(sizeof(double) * 3 * (size_t)L->N);
+    memcpy(L->wall_field, u, sizeof(double) * 3 * (size_t)L->N);
 }
 
 int or_set_extrapolation(or_lattice *L, int order)

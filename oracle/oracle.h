@@ -81,6 +81,11 @@ int or_set_giesekus(or_lattice *L, double alpha);
  * T = (eta_p/lambda)(A - I); or_set_stress sets T, or_read_stress returns
  * the polymer stress tau = f T + (eta_p/lambda)(f - 1) I. */
 int or_set_fene_p(or_lattice *L, double L2);
+/* Wall velocity per cell (Section 3.1 velocity boundary condition with a
+ * wall velocity that varies along the wall): u holds 3*N values, the x, y
+ * and z planes; when set, every wall cell (mask 1..63) moves with its own
+ * entry instead of the per-id table.  NULL returns to the table. */
+void or_set_wall_velocity_field(or_lattice *L, const double *u);
 /* Stress extrapolation into solid face neighbours (Section 3.3): 0 constant
  * (default), 1 linear; the traction on obstacles uses the same face values.
  * -1 for other orders. */

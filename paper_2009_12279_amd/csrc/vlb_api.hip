@@ -94,6 +94,8 @@ struct vlb_lattice {
     float *d_tau[2] = {nullptr, nullptr};
     float *d_u = nullptr;
     double *d_wall = nullptr;
+    double *d_wfield = nullptr;   // per-cell wall velocity [3][N] (null: wall table)
+    std::vector<double> wfield_h; // host copy, for checkpoints
     Particle *d_parts = nullptr;
     double *d_partials = nullptr;
     double *d_pforce = nullptr;   // block sums of the obstacle forces
@@ -143,6 +145,7 @@ struct vlb_lattice {
         vlb::Bound b;
         b.wall_vel = d_wall;
         b.n_walls = n_walls;
+        b.wall_field = d_wfield;
         b.parts = d_parts;
         b.n_parts = static_cast<int32_t>(parts_h.size());
         b.moving = (any_movable || moving_walls) ? 1 : 0;
@@ -267,8 +270,8 @@ void free_all(vlb_lattice *lat)
         for (void *p : state)
             if (p)
                 (void)hipFree(p);
-    void *ptrs[] = {lat->d_wall,     lat->d_parts,  lat->d_partials, lat->d_out,
-                    lat->d_counters, lat->d_pforce, lat->d_count,    lat->d_g3};
+    void *ptrs[] = {lat->d_wall,   lat->d_parts,  lat->d_partials, lat->d_out, lat->d_counters,
+                    lat->d_pforce, lat->d_count,  lat->d_g3,       lat->d_wfield};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -396,6 +399,9 @@ vlb_status create_impl(const vlb_dims *dims, const uint8_t *mask, const double *
         return fail(nullptr, VLB_EINVAL, "vlb_create: unknown storage");
     if (n_walls < 0 || n_walls > VLB_MAX_WALL_ID || (n_walls > 0 && !wall_velocity))
         return fail(nullptr, VLB_EINVAL, "vlb_create: invalid wall table");
+    for (int i = 0; i < 3 * n_walls; ++i)
+        if (!std::isfinite(wall_velocity[i]))
+            return fail(nullptr, VLB_EINVAL, "vlb_create: non-finite wall velocity");
     const uint64_t N = static_cast<uint64_t>(dims->nx) * dims->ny * dims->nz;
     for (uint64_t n = 0; n < N; ++n)
         if (mask[n] >= vlb::PART0)
@@ -1096,7 +1102,7 @@ vlb_status vlb_set_check_interval(vlb_lattice *lat, int64_t steps)
 // checkpoint
 
 namespace {
-constexpr uint64_t kMagic = 0x36304B434C424C56ull;  // "VLBLCK06"
+constexpr uint64_t kMagic = 0x37304B434C424C56ull;  // "VLBLCK07"
 
 struct FileHeader {
     uint64_t magic;
@@ -1112,6 +1118,8 @@ struct FileHeader {
     int32_t extrap;
     double alpha;
     double L2;
+    int32_t wall_field;  // 1: 3*N doubles of per-cell wall velocity follow the walls
+    int32_t pad;
 };
 }  // namespace
 
@@ -1170,8 +1178,11 @@ vlb_status vlb_save(vlb_lattice *lat, const char *path)
     h.alpha = lat->alpha;
     h.L2 = lat->L2;
     h.extrap = lat->extrap;
+    h.wall_field = lat->d_wfield ? 1 : 0;
     bool ok = std::fwrite(&h, sizeof h, 1, fp) == 1;
     ok = ok && std::fwrite(lat->wall_h.data(), sizeof(double), 64 * 3, fp) == 64 * 3;
+    ok = ok && (!h.wall_field || std::fwrite(lat->wfield_h.data(), sizeof(double), 3 * N, fp) ==
+                                     3 * N);
     ok = ok && (parts.empty() || std::fwrite(parts.data(), sizeof(Particle), parts.size(), fp) ==
                                      parts.size());
     ok = ok && std::fwrite(lat->mask_h.data(), 1, N, fp) == N;
@@ -1210,12 +1221,14 @@ vlb_status vlb_load(const char *path, void *stream, vlb_lattice **out)
     }
     const uint64_t N = static_cast<uint64_t>(h.nx) * h.ny * h.nz;
     const size_t es = storage_bytes(h.storage);
-    std::vector<double> walls(64 * 3);
+    std::vector<double> walls(64 * 3), wfield(h.wall_field == 1 ? 3 * N : 0);
     std::vector<Particle> parts(h.n_parts);
     std::vector<uint8_t> mask(N);
     std::vector<char> f(vlb::Q * N * es);
     std::vector<float> tau(6 * N), tau_prev(6 * N);
     bool ok = std::fread(walls.data(), sizeof(double), walls.size(), fp) == walls.size();
+    ok = ok && (wfield.empty() ||
+                std::fread(wfield.data(), sizeof(double), wfield.size(), fp) == wfield.size());
     ok = ok && (parts.empty() || std::fread(parts.data(), sizeof(Particle), parts.size(), fp) ==
                                      parts.size());
     ok = ok && std::fread(mask.data(), 1, N, fp) == N;
@@ -1241,6 +1254,8 @@ vlb_status vlb_load(const char *path, void *stream, vlb_lattice **out)
         return s2;
     };
     if ((st = vlb_set_params(lat, &h.params)) != VLB_OK)
+        return bail(st);
+    if (!wfield.empty() && (st = vlb_set_wall_velocity_field(lat, wfield.data())) != VLB_OK)
         return bail(st);
     lat->mask_h = mask;
     lat->parts_h = parts;
@@ -1322,6 +1337,46 @@ vlb_status vlb_set_fene_p(vlb_lattice *lat, double L2)
     lat->L2 = L2;
     if (L2 > 0.0)
         lat->alpha = 0.0;
+    return VLB_OK;
+}
+
+vlb_status vlb_set_wall_velocity_field(vlb_lattice *lat, const double *u)
+{
+    if (!lat)
+        return VLB_EINVAL;
+    const uint64_t N = lat->g.N;
+    if (u)
+        for (uint64_t i = 0; i < 3 * N; ++i)
+            if (!std::isfinite(u[i]))
+                return fail(lat, VLB_EINVAL, "vlb_set_wall_velocity_field: non-finite value");
+    // work already queued may still read the old field
+    HIPCHK(lat, hipStreamSynchronize(lat->stream), "vlb_set_wall_velocity_field");
+    bool moving = false;
+    if (!u) {
+        if (lat->d_wfield)
+            HIPCHK(lat, hipFree(lat->d_wfield), "vlb_set_wall_velocity_field");
+        lat->d_wfield = nullptr;
+        lat->wfield_h.clear();
+        for (int i = 0; i < 3 * lat->n_walls; ++i)
+            moving = moving || lat->wall_h[i] != 0.0;
+        lat->moving_walls = moving;
+        return VLB_OK;
+    }
+    if (!lat->d_wfield)
+        HIPCHK(lat, hipMalloc(&lat->d_wfield, 3 * N * sizeof(double)),
+               "vlb_set_wall_velocity_field");
+    lat->wfield_h.assign(u, u + 3 * N);
+    HIPCHK(lat,
+           hipMemcpyAsync(lat->d_wfield, lat->wfield_h.data(), 3 * N * sizeof(double),
+                          hipMemcpyHostToDevice, lat->stream),
+           "vlb_set_wall_velocity_field");
+    // wall cells never change owner, so the host mask is current for them
+    for (uint64_t n = 0; n < N && !moving; ++n) {
+        const uint8_t m = lat->mask_h[n];
+        if (m >= 1 && m <= VLB_MAX_WALL_ID)
+            moving = u[n] != 0.0 || u[N + n] != 0.0 || u[2 * N + n] != 0.0;
+    }
+    lat->moving_walls = moving;
     return VLB_OK;
 }
 

@@ -58,6 +58,9 @@ struct Geom {
 struct Bound {
     const double *wall_vel;  // [n_walls][3]
     int32_t n_walls;
+    // per-cell wall velocity, planes [3][N]; when set it replaces wall_vel
+    // for every wall cell
+    const double *wall_field = nullptr;
     const Particle *parts;
     int32_t n_parts;
     int32_t moving;          // any moving wall or movable particle

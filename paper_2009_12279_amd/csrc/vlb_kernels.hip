@@ -281,13 +281,21 @@ __device__ __forceinline__ void lever(const Geom &g, const Particle &P, int x, i
 }
 
 // Section 3.4: velocity of a solid node, v + omega x (r_b - R) for a movable
-// particle, the wall velocity for a wall id, zero otherwise.
+// particle; for a wall cell its entry of the per-cell field when one is set,
+// else the velocity of its wall id; zero otherwise.
 __device__ void boundary_velocity_d(const Geom &g, const Bound &b, uint8_t m, int x, int y, int z,
                                     double ub[3])
 {
     ub[0] = ub[1] = ub[2] = 0.0;
     if (m < PART0) {
-        if (m >= 1 && m <= b.n_walls) {
+        if (m >= 1 && b.wall_field) {
+            const uint32_t n = static_cast<uint32_t>(x) +
+                               static_cast<uint32_t>(g.nx) *
+                                   (static_cast<uint32_t>(y) + static_cast<uint32_t>(g.ny) * z);
+            ub[0] = b.wall_field[n];
+            ub[1] = b.wall_field[g.N + n];
+            ub[2] = b.wall_field[2ull * g.N + n];
+        } else if (m >= 1 && m <= b.n_walls) {
             ub[0] = b.wall_vel[3 * (m - 1) + 0];
             ub[1] = b.wall_vel[3 * (m - 1) + 1];
             ub[2] = b.wall_vel[3 * (m - 1) + 2];
@@ -302,16 +310,6 @@ __device__ void boundary_velocity_d(const Geom &g, const Bound &b, uint8_t m, in
     ub[0] = P.v[0] + P.w[1] * r[2] - P.w[2] * r[1];
     ub[1] = P.v[1] + P.w[2] * r[0] - P.w[0] * r[2];
     ub[2] = P.v[2] + P.w[0] * r[1] - P.w[1] * r[0];
-}
-
-__device__ __forceinline__ void boundary_velocity(const Geom &g, const Bound &b, uint8_t m, int x,
-                                                  int y, int z, float ub[3])
-{
-    double d[3];
-    boundary_velocity_d(g, b, m, x, y, z, d);
-    ub[0] = static_cast<float>(d[0]);
-    ub[1] = static_cast<float>(d[1]);
-    ub[2] = static_cast<float>(d[2]);
 }
 
 // deterministic block sum (fixed shuffle tree, then fixed order over waves);
@@ -432,6 +430,7 @@ __device__ __forceinline__ Bound bound_copy(const B &b)
     Bound r;
     r.wall_vel = b.wall_vel;
     r.n_walls = b.n_walls;
+    r.wall_field = b.wall_field;
     r.parts = b.parts;
     r.n_parts = b.n_parts;
     r.moving = b.moving;

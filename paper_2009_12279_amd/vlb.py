@@ -107,6 +107,7 @@ SIGNATURES = [
     ("vlb_set_giesekus", ctypes.c_int, [_P, ctypes.c_double]),
     ("vlb_set_fene_p", ctypes.c_int, [_P, ctypes.c_double]),
     ("vlb_set_stress_extrapolation", ctypes.c_int, [_P, ctypes.c_int32]),
+    ("vlb_set_wall_velocity_field", ctypes.c_int, [_P, _D]),
     ("vlb_server_create", ctypes.c_int, [ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32, _P,
                                          ctypes.POINTER(_P)]),
     ("vlb_server_set_rounding", ctypes.c_int, [_P, ctypes.c_int]),
@@ -388,6 +389,10 @@ def vlb_set_stress_extrapolation(h, order):
     return _check(lib().vlb_set_stress_extrapolation(h, int(order)), h)
 
 
+def vlb_set_wall_velocity_field(h, u):
+    return _check(lib().vlb_set_wall_velocity_field(h, u), h)
+
+
 def vlb_set_counter_force(h, on=True):
     return _check(lib().vlb_set_counter_force(h, 1 if on else 0), h)
 
@@ -529,6 +534,18 @@ class Lattice:
 
     def set_extrapolation(self, order):
         vlb_set_stress_extrapolation(self._h, order)
+
+    def set_wall_velocity_field(self, u):
+        """Per-cell wall velocity, shape (3, nz, ny, nx); None returns to the
+        per-id wall table."""
+        if u is None:
+            vlb_set_wall_velocity_field(self._h, None)
+            return
+        nx, ny, nz = self.shape
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        if u.shape != (3, nz, ny, nx):
+            raise ValueError(f"wall velocity field must have shape {(3, nz, ny, nx)}")
+        vlb_set_wall_velocity_field(self._h, _dp(u))
 
 
 # ---- serving ------------------------------------------------------------------
