@@ -13,6 +13,8 @@
 #include <hip/hip_runtime.h>
 #include <hip/hip_fp16.h>
 
+#include <type_traits>
+
 #include "vlb_internal.h"
 
 namespace vlb {
@@ -689,22 +691,14 @@ __global__ __launch_bounds__(BLOCK) LB_OCCUPANCY void lb_step_kernel(StepArgs a)
 // The increment (fluxes + source, products of small quantities) is formed in
 // FP32; it is added to the stored stress in FP64 and rounded once.
 
-__device__ __forceinline__ float face_overlap(const float u[3], int k, int s)
-{
-#pragma clang fp contract(on)
-    const float ue = s * u[k];
-    if (ue <= 0.f)
-        return 0.f;
-    const int a1 = k == 0 ? 1 : 0, a2 = k == 2 ? 1 : 2;
-    return ue * (1.f - fabsf(u[a1])) * (1.f - fabsf(u[a2]));
-}
-
 // Stress update of fluid cell n at (x, y, z) from its own velocity and stress
 // (u0, t0) and those of its six face neighbours (un, tn: [axis k][side], side 0
 // along +e_k, side 1 along -e_k), `solid` holding bit 2k+side for each solid
 // face neighbour.  Shared by the per-cell and the tiled kernels, so both give
-// the same bits.
-template <bool SR, class A>
+// the same bits.  LAW selects the constitutive law at compile time: 0
+// Oldroyd-B, 1 Giesekus, 2 FENE-P.
+constexpr int LAW_OB = 0, LAW_GIESEKUS = 1, LAW_FENE = 2;
+template <bool SR, int LAW, class A>
 __device__ __forceinline__ void fv_compute(const A &a, const Geom &g, uint32_t n, int x, int y, int z,
                                            uint32_t step, const float u0[3], const float t0[6],
                                            float un[3][2][3], const float tn[3][2][6],
@@ -714,6 +708,40 @@ __device__ __forceinline__ void fv_compute(const A &a, const Geom &g, uint32_t n
     // it matters), so that every kernel this is inlined into computes the
     // same bits.
 #pragma clang fp contract(on)
+    // Face fluxes: the fraction of a cell moving with velocity v that crosses
+    // its face along +/- e_k in one step is max(+/- v_k, 0) times the
+    // product of (1 - |v_a|) over the two transverse axes a.  fo: out of this
+    // cell through face (k, side); fi: into it from the neighbour there.
+    float fo[3][2], fi[3][2];
+    const float om[3] = {1.f - fabsf(u0[0]), 1.f - fabsf(u0[1]), 1.f - fabsf(u0[2])};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int a1 = k == 0 ? 1 : 0, a2 = k == 2 ? 1 : 2;
+        const float p0 = om[a1] * om[a2];
+        fo[k][0] = fmaxf(u0[k], 0.f) * p0;
+        fo[k][1] = fmaxf(-u0[k], 0.f) * p0;
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const float *v = un[k][side];
+            const float pn = (1.f - fabsf(v[a1])) * (1.f - fabsf(v[a2]));
+            fi[k][side] = fmaxf(side == 0 ? -v[k] : v[k], 0.f) * pn;
+        }
+    }
+    if (solid) {
+        // no flux through a solid face; its velocity (zero for walls at
+        // rest) enters the gradient below
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int side = 0; side < 2; ++side)
+                if ((solid >> (2 * k + side)) & 1u) {
+                    fo[k][side] = 0.f;
+                    fi[k][side] = 0.f;
+#pragma unroll
+                    for (int j = 0; j < 3; ++j)
+                        un[k][side][j] = 0.f;
+                }
+    }
     float G[3][3];
     float in_sum[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     float out_tot = 0.f;
@@ -721,19 +749,10 @@ __device__ __forceinline__ void fv_compute(const A &a, const Geom &g, uint32_t n
     for (int k = 0; k < 3; ++k) {
 #pragma unroll
         for (int side = 0; side < 2; ++side) {
-            const int s = side == 0 ? 1 : -1;
-            const bool sol = (solid >> (2 * k + side)) & 1u;
-            // no flux through a solid face; its velocity (zero for walls at
-            // rest) enters the gradient below
-            const float out = sol ? 0.f : face_overlap(u0, k, s);
-            const float in = sol ? 0.f : face_overlap(un[k][side], k, -s);
-            out_tot += out;
+            out_tot += fo[k][side];
 #pragma unroll
             for (int c = 0; c < 6; ++c)
-                in_sum[c] = fmaf(in, tn[k][side][c], in_sum[c]);
-#pragma unroll
-            for (int j = 0; j < 3; ++j)
-                un[k][side][j] = sol ? 0.f : un[k][side][j];
+                in_sum[c] = fmaf(fi[k][side], tn[k][side][c], in_sum[c]);
         }
 #pragma unroll
         for (int j = 0; j < 3; ++j)
@@ -772,10 +791,9 @@ __device__ __forceinline__ void fv_compute(const A &a, const Geom &g, uint32_t n
     const float gk = a.gk;
     // FENE-P: relaxation -(1 + g0) T / lambda - epl g0 / lambda I of the stored
     // variable, g0 = f - 1 from this cell's trace
-    const float fl2m3 = a.sm.l2m3;
     float g0 = 0.f;
-    if (fl2m3 > 0.f) {
-        const float fc = a.sm.c, tr = t0[0] + t0[1] + t0[2];
+    if constexpr (LAW == LAW_FENE) {
+        const float fl2m3 = a.sm.l2m3, fc = a.sm.c, tr = t0[0] + t0[1] + t0[2];
         g0 = fc * tr / (fl2m3 - fc * tr);
     }
     Rng rng(n, step, a.seed ^ 0x5bd1e995u);
@@ -790,12 +808,12 @@ __device__ __forceinline__ void fv_compute(const A &a, const Geom &g, uint32_t n
         float inc = fmaf(-out_tot, t0[c], in_sum[c]) + sdot;
         inc = fmaf(epl, G[i][j] + G[j][i], inc);
         inc = fmaf(-t0[c], il, inc);
-        if (fl2m3 > 0.f) {
+        if constexpr (LAW == LAW_FENE) {
             inc = fmaf(-t0[c] * g0, il, inc);
             if (c < 3)
                 inc = fmaf(-epl * g0, il, inc);
         }
-        if (gk != 0.f) {
+        if constexpr (LAW == LAW_GIESEKUS) {
             // Giesekus: -(alpha / eta_p) (tau . tau)_ij
             float tt = 0.f;
 #pragma unroll
@@ -811,7 +829,7 @@ __device__ __forceinline__ void fv_compute(const A &a, const Geom &g, uint32_t n
 }
 
 // Per-cell stress update: every neighbour value is loaded from memory.
-template <bool SR, class A>
+template <bool SR, int LAW, class A>
 __device__ __forceinline__ void fv_cell(const A &a, uint32_t n, uint32_t step)
 {
     const Geom g = geom_copy(a.g);
@@ -843,16 +861,16 @@ __device__ __forceinline__ void fv_cell(const A &a, uint32_t n, uint32_t step)
         }
     if (mask[n] != 0)
         return;
-    fv_compute<SR>(a, g, n, x, y, z, step, u0, t0, un, tn, solid);
+    fv_compute<SR, LAW>(a, g, n, x, y, z, step, u0, t0, un, tn, solid);
 }
 
-template <bool SR>
+template <bool SR, int LAW>
 __global__ __launch_bounds__(BLOCK) FV_OCCUPANCY void fv_step_kernel(StepArgs a)
 {
     const uint32_t n = block_id(a.remap, a.slab_blocks) * BLOCK + threadIdx.x;
     if (n >= a.g.N)
         return;
-    fv_cell<SR>(a, n, a.step);
+    fv_cell<SR, LAW>(a, n, a.step);
 }
 
 // ---------------------------------------------------------------------------
@@ -936,7 +954,7 @@ __device__ __forceinline__ void fv_load(const StepArgs &a, uint32_t idx, float v
     v[9] = a.mask[idx] != 0 ? 1.f : 0.f;
 }
 
-template <bool SR, int TY>
+template <bool SR, int LAW, int TY>
 __global__ __launch_bounds__(FV_TX * TY) void fv_tile_kernel(StepArgs a, uint32_t zc)
 {
     static_assert(FV_TX * TY >= 2 * FV_TX + 2 * TY, "ring larger than the block");
@@ -1040,7 +1058,7 @@ __global__ __launch_bounds__(FV_TX * TY) void fv_tile_kernel(StepArgs a, uint32_
             solid |= (N[9] != 0.f ? 1u : 0u) << 4;
             solid |= (P[9] != 0.f ? 1u : 0u) << 5;
             const uint32_t n = own_xy + static_cast<uint32_t>(z) * nxy;
-            fv_compute<SR>(a, g, n, x, y, z, a.step, u0, t0, un, tn, solid);
+            fv_compute<SR, LAW>(a, g, n, x, y, z, a.step, u0, t0, un, tn, solid);
         }
         if (more) {
 #pragma unroll
@@ -1111,7 +1129,8 @@ __global__ __launch_bounds__(BLOCK) void fv_batch_kernel(const BatchTable *__res
     const uint32_t n = (b - bs.first_block) * BLOCK + threadIdx.x;
     if (n >= a.g.N)
         return;
-    fv_cell<SR>(a, n, step);
+    // served solves are Oldroyd-B
+    fv_cell<SR, LAW_OB>(a, n, step);
 }
 
 __global__ void batch_advance_kernel(BatchTable *t)
@@ -1978,26 +1997,32 @@ hipError_t launch_fv_step(int storage, const StepArgs &a, hipStream_t s, int til
     // at most an eighth of the tile lanes beyond the end of the rows
     const uint32_t lanes_x = ((a.g.nx + FV_TX - 1) / FV_TX) * FV_TX;
     const bool rows_fill = 8u * (lanes_x - a.g.nx) <= lanes_x;
-    if ((tile_rows == 4 || tile_rows == 8) &&
-        (force || (rows_fill && tiles_xy * ((a.g.nz + zc - 1) / zc) >= 1024))) {
-        const uint32_t tiles = tiles_xy * ((a.g.nz + zc - 1) / zc);
-        if (tile_rows == 4) {
-            if (a.stochastic)
-                hipLaunchKernelGGL((fv_tile_kernel<true, 4>), dim3(tiles), dim3(FV_TX * 4), 0, s, a, zc);
-            else
-                hipLaunchKernelGGL((fv_tile_kernel<false, 4>), dim3(tiles), dim3(FV_TX * 4), 0, s, a, zc);
-        } else {
-            if (a.stochastic)
-                hipLaunchKernelGGL((fv_tile_kernel<true, 8>), dim3(tiles), dim3(FV_TX * 8), 0, s, a, zc);
-            else
-                hipLaunchKernelGGL((fv_tile_kernel<false, 8>), dim3(tiles), dim3(FV_TX * 8), 0, s, a, zc);
-        }
-        return hipGetLastError();
-    }
+    const bool tiled = (tile_rows == 4 || tile_rows == 8) &&
+                       (force || (rows_fill && tiles_xy * ((a.g.nz + zc - 1) / zc) >= 1024));
+    const uint32_t tiles = tiles_xy * ((a.g.nz + zc - 1) / zc);
+    const int law = a.sm.l2m3 > 0.f ? LAW_FENE : (a.gk != 0.f ? LAW_GIESEKUS : LAW_OB);
+    auto go = [&](auto sr, auto lw) {
+        constexpr bool SR = decltype(sr)::value;
+        constexpr int LAW = decltype(lw)::value;
+        if (tiled && tile_rows == 4)
+            hipLaunchKernelGGL((fv_tile_kernel<SR, LAW, 4>), dim3(tiles), dim3(FV_TX * 4), 0, s, a, zc);
+        else if (tiled)
+            hipLaunchKernelGGL((fv_tile_kernel<SR, LAW, 8>), dim3(tiles), dim3(FV_TX * 8), 0, s, a, zc);
+        else
+            hipLaunchKernelGGL((fv_step_kernel<SR, LAW>), dim3(blocks_for(a.g.N)), dim3(BLOCK), 0, s, a);
+    };
+    auto with_law = [&](auto sr) {
+        if (law == LAW_FENE)
+            go(sr, std::integral_constant<int, LAW_FENE>{});
+        else if (law == LAW_GIESEKUS)
+            go(sr, std::integral_constant<int, LAW_GIESEKUS>{});
+        else
+            go(sr, std::integral_constant<int, LAW_OB>{});
+    };
     if (a.stochastic)
-        hipLaunchKernelGGL(fv_step_kernel<true>, dim3(blocks_for(a.g.N)), dim3(BLOCK), 0, s, a);
+        with_law(std::true_type{});
     else
-        hipLaunchKernelGGL(fv_step_kernel<false>, dim3(blocks_for(a.g.N)), dim3(BLOCK), 0, s, a);
+        with_law(std::false_type{});
     return hipGetLastError();
 }
 
