@@ -234,6 +234,14 @@ vlb_status vlb_set_fene_p(vlb_lattice *lat, double L2);
  * VLB_EINVAL for other orders.  Kept in checkpoints. */
 vlb_status vlb_set_stress_extrapolation(vlb_lattice *lat, int32_t order);
 
+/* Force density that varies from cell to cell (Section 3.1 Guo forcing; the
+ * driving force of the four-roll mill, Section 4.4).  F: 3*N doubles, the
+ * x, y and z planes in cell order, copied and stored in FP32; added to the
+ * uniform body force at every fluid cell.  NULL frees the field.
+ * Synchronises the lattice's stream.  Errors: VLB_EINVAL (non-finite value),
+ * VLB_ENOMEM.  Kept in checkpoints. */
+vlb_status vlb_set_force_field(vlb_lattice *lat, const double *F);
+
 /* Wall velocity that varies along a wall (Section 3.1 velocity boundary
  * condition; the regularized lid of the lid-driven cavity, Section 4.3).
  * u: 3*N doubles, the x, y and z planes in cell order, copied.  When set,

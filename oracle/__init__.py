@@ -82,6 +82,7 @@ def lib():
         L.or_polymer_force_ext.argtypes = [I, I, I, ctypes.c_char_p, D, I, D]
         L.or_set_extrapolation.restype = I
         L.or_set_wall_velocity_field.argtypes = [P, D]
+        L.or_set_force_field.argtypes = [P, D]
         L.or_set_extrapolation.argtypes = [P, I]
         L.or_set_threads.argtypes = [I]
         L.or_get_threads.restype = I
@@ -214,6 +215,17 @@ class Lattice:
     def set_giesekus(self, alpha):
         if lib().or_set_giesekus(self._h, float(alpha)) != 0:
             raise ValueError("oracle: Giesekus mobility must lie in [0, 1/2]")
+
+    def set_force_field(self, F):
+        """Per-cell force density added to the body force, shape
+        (3, nz, ny, nx); None removes it."""
+        if F is None:
+            lib().or_set_force_field(self._h, None)
+        else:
+            F = np.ascontiguousarray(F, dtype=np.float64)
+            nx, ny, nz = self.shape
+            assert F.shape == (3, nz, ny, nx)
+            lib().or_set_force_field(self._h, _dp(F))
 
     def set_wall_velocity_field(self, u):
         """Per-cell wall velocity, shape (3, nz, ny, nx); None returns to

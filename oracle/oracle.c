@@ -425,6 +425,7 @@ struct or_lattice {
     double *wall_vel;
     int n_walls;
     double *wall_field;              /* per-cell wall velocity (3*N) or NULL */
+    double *force_field;             /* per-cell force density added to g (3*N) or NULL */
     double eta, beta, lambda, magic, g[3];
     int counter_force;               /* -sum of the free particles' F_ext spread over the fluid */
     double alpha;                    /* Giesekus mobility (0: Oldroyd-B) */
@@ -489,6 +490,7 @@ void or_destroy(or_lattice *L)
     free(L->mask);
     free(L->wall_vel);
     free(L->wall_field);
+    free(L->force_field);
     free(L->f);
     free(L->fnew);
     free(L->fpost);
@@ -721,6 +723,16 @@ int or_set_giesekus(or_lattice *L, double alpha)
     return 0;
 }
 
+void or_set_force_field(or_lattice *L, const double *F)
+{
+    free(L->force_field);
+    L->force_field = NULL;
+    if (!F)
+        return;
+    L->force_field = (double *)malloc(sizeof(double) * 3 * (size_t)L->N);
+    memcpy(L->force_field, F, sizeof(double) * 3 * (size_t)L->N);
+}
+
 void or_set_wall_velocity_field(or_lattice *L, const double *u)
 {
     free(L->wall_field);
@@ -769,6 +781,12 @@ static void state_stress(const or_lattice *L, const double *state, double *out)
     }
 }
 
+/* Body force density at cell n: the uniform g plus the per-cell field, if set. */
+static double cell_g(const or_lattice *L, const double g[3], long n, int a)
+{
+    return L->force_field ? g[a] + L->force_field[a * L->N + n] : g[a];
+}
+
 static void fluid_moments(const or_lattice *L, const double *f, const double *fp, const double g[3],
                           long n, double *rho, double u[3])
 {
@@ -782,7 +800,7 @@ static void fluid_moments(const or_lattice *L, const double *f, const double *fp
     }
     *rho = r;
     for (int a = 0; a < 3; ++a)
-        u[a] = (j[a] + 0.5 * (g[a] + fp[a * N + n])) / r;
+        u[a] = (j[a] + 0.5 * (cell_g(L, g, n, a) + fp[a * N + n])) / r;
 }
 
 static void conversion(or_lattice *L);
@@ -825,7 +843,7 @@ void or_step(or_lattice *L, long n_steps)
             for (int i = 0; i < Q; ++i)
                 fin[i] = L->f[i * N + n];
             for (int a = 0; a < 3; ++a)
-                F[a] = geff[a] + L->fp[a * N + n];
+                F[a] = cell_g(L, geff, n, a) + L->fp[a * N + n];
             or_collide_cell(fin, F, L->wp, L->wm, fout, &rho, u);
             for (int i = 0; i < Q; ++i)
                 L->fpost[i * N + n] = fout[i];

@@ -81,6 +81,11 @@ int or_set_giesekus(or_lattice *L, double alpha);
  * T = (eta_p/lambda)(A - I); or_set_stress sets T, or_read_stress returns
  * the polymer stress tau = f T + (eta_p/lambda)(f - 1) I. */
 int or_set_fene_p(or_lattice *L, double L2);
+/* Force density per cell (Section 3.1 Guo forcing with a force that varies
+ * in space, as the four-roll mill of Section 4.4 needs): F holds 3*N values,
+ * the x, y and z planes, added to the uniform body force at every fluid
+ * cell.  NULL removes it. */
+void or_set_force_field(or_lattice *L, const double *F);
 /* Wall velocity per cell (Section 3.1 velocity boundary condition with a
  * wall velocity that varies along the wall): u holds 3*N values, the x, y
  * and z planes; when set, every wall cell (mask 1..63) moves with its own

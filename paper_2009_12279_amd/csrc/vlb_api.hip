@@ -96,6 +96,8 @@ struct vlb_lattice {
     double *d_wall = nullptr;
     double *d_wfield = nullptr;   // per-cell wall velocity [3][N] (null: wall table)
     std::vector<double> wfield_h; // host copy, for checkpoints
+    float *d_gfield = nullptr;    // per-cell force density, 3 planes of g.plane (null: none)
+    std::vector<float> gfield_h;  // host copy [3][N], for checkpoints
     Particle *d_parts = nullptr;
     double *d_partials = nullptr;
     double *d_pforce = nullptr;   // block sums of the obstacle forces
@@ -270,8 +272,9 @@ void free_all(vlb_lattice *lat)
         for (void *p : state)
             if (p)
                 (void)hipFree(p);
-    void *ptrs[] = {lat->d_wall,   lat->d_parts,  lat->d_partials, lat->d_out, lat->d_counters,
-                    lat->d_pforce, lat->d_count,  lat->d_g3,       lat->d_wfield};
+    void *ptrs[] = {lat->d_wall,   lat->d_parts, lat->d_partials, lat->d_out,
+                    lat->d_counters, lat->d_pforce, lat->d_count, lat->d_g3,
+                    lat->d_wfield, lat->d_gfield};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -761,6 +764,9 @@ vlb_status vlb_step(vlb_lattice *lat, int64_t n_steps)
         a.g3[k] = lat->params.body_force[k];
     const bool counter = lat->counter_force && lat->any_movable;
     a.g3_dev = counter ? lat->d_g3 : nullptr;
+    if (lat->d_gfield)
+        for (int k = 0; k < 3; ++k)
+            a.gf_p[k] = lat->d_gfield + k * lat->g.plane;
     const int n_parts = static_cast<int>(lat->parts_h.size());
     if (counter && n_steps > 0)
         HIPCHK(lat, vlb::launch_body_force(lat->g, lat->d_mask, lat->d_parts, n_parts,
@@ -920,7 +926,8 @@ vlb_status vlb_read_density(vlb_lattice *lat, double *rho)
         [&](double *d) {
             return vlb::launch_read_moments(lat->storage, lat->g, lat->bound(), lat->d_mask,
                                             lat->d_f[lat->cur], lat->d_tau[lat->cur], lat->polymer,
-                                            gv, lat->inv_scale, d, nullptr, lat->stream,
+                                            gv, lat->d_gfield, lat->inv_scale, d, nullptr,
+                                            lat->stream,
                                             lat->stress_map());
         },
         "vlb_read_density");
@@ -941,7 +948,8 @@ vlb_status vlb_read_velocity(vlb_lattice *lat, double *u)
         [&](double *d) {
             return vlb::launch_read_moments(lat->storage, lat->g, lat->bound(), lat->d_mask,
                                             lat->d_f[lat->cur], lat->d_tau[lat->cur], lat->polymer,
-                                            gv, lat->inv_scale, nullptr, d, lat->stream,
+                                            gv, lat->d_gfield, lat->inv_scale, nullptr, d,
+                                            lat->stream,
                                             lat->stress_map());
         },
         "vlb_read_velocity");
@@ -1118,8 +1126,9 @@ struct FileHeader {
     int32_t extrap;
     double alpha;
     double L2;
-    int32_t wall_field;  // 1: 3*N doubles of per-cell wall velocity follow the walls
-    int32_t pad;
+    int32_t wall_field;   // 1: 3*N doubles of per-cell wall velocity follow the walls
+    int32_t force_field;  // 1: 3*N floats of per-cell force density follow
+
 };
 }  // namespace
 
@@ -1179,10 +1188,13 @@ vlb_status vlb_save(vlb_lattice *lat, const char *path)
     h.L2 = lat->L2;
     h.extrap = lat->extrap;
     h.wall_field = lat->d_wfield ? 1 : 0;
+    h.force_field = lat->d_gfield ? 1 : 0;
     bool ok = std::fwrite(&h, sizeof h, 1, fp) == 1;
     ok = ok && std::fwrite(lat->wall_h.data(), sizeof(double), 64 * 3, fp) == 64 * 3;
     ok = ok && (!h.wall_field || std::fwrite(lat->wfield_h.data(), sizeof(double), 3 * N, fp) ==
                                      3 * N);
+    ok = ok && (!h.force_field || std::fwrite(lat->gfield_h.data(), sizeof(float), 3 * N, fp) ==
+                                      3 * N);
     ok = ok && (parts.empty() || std::fwrite(parts.data(), sizeof(Particle), parts.size(), fp) ==
                                      parts.size());
     ok = ok && std::fwrite(lat->mask_h.data(), 1, N, fp) == N;
@@ -1222,6 +1234,7 @@ vlb_status vlb_load(const char *path, void *stream, vlb_lattice **out)
     const uint64_t N = static_cast<uint64_t>(h.nx) * h.ny * h.nz;
     const size_t es = storage_bytes(h.storage);
     std::vector<double> walls(64 * 3), wfield(h.wall_field == 1 ? 3 * N : 0);
+    std::vector<float> gfield(h.force_field == 1 ? 3 * N : 0);
     std::vector<Particle> parts(h.n_parts);
     std::vector<uint8_t> mask(N);
     std::vector<char> f(vlb::Q * N * es);
@@ -1229,6 +1242,8 @@ vlb_status vlb_load(const char *path, void *stream, vlb_lattice **out)
     bool ok = std::fread(walls.data(), sizeof(double), walls.size(), fp) == walls.size();
     ok = ok && (wfield.empty() ||
                 std::fread(wfield.data(), sizeof(double), wfield.size(), fp) == wfield.size());
+    ok = ok && (gfield.empty() ||
+                std::fread(gfield.data(), sizeof(float), gfield.size(), fp) == gfield.size());
     ok = ok && (parts.empty() || std::fread(parts.data(), sizeof(Particle), parts.size(), fp) ==
                                      parts.size());
     ok = ok && std::fread(mask.data(), 1, N, fp) == N;
@@ -1257,6 +1272,12 @@ vlb_status vlb_load(const char *path, void *stream, vlb_lattice **out)
         return bail(st);
     if (!wfield.empty() && (st = vlb_set_wall_velocity_field(lat, wfield.data())) != VLB_OK)
         return bail(st);
+    if (!gfield.empty()) {
+        // FP32 values widened exactly, so the device field is restored bit for bit
+        std::vector<double> gd(gfield.begin(), gfield.end());
+        if ((st = vlb_set_force_field(lat, gd.data())) != VLB_OK)
+            return bail(st);
+    }
     lat->mask_h = mask;
     lat->parts_h = parts;
     lat->any_movable = h.any_movable != 0;
@@ -1337,6 +1358,41 @@ vlb_status vlb_set_fene_p(vlb_lattice *lat, double L2)
     lat->L2 = L2;
     if (L2 > 0.0)
         lat->alpha = 0.0;
+    return VLB_OK;
+}
+
+vlb_status vlb_set_force_field(vlb_lattice *lat, const double *F)
+{
+    if (!lat)
+        return VLB_EINVAL;
+    const uint64_t N = lat->g.N;
+    if (F)
+        for (uint64_t i = 0; i < 3 * N; ++i)
+            if (!std::isfinite(F[i]))
+                return fail(lat, VLB_EINVAL, "vlb_set_force_field: non-finite value");
+    // work already queued may still read the old field
+    HIPCHK(lat, hipStreamSynchronize(lat->stream), "vlb_set_force_field");
+    if (!F) {
+        if (lat->d_gfield)
+            HIPCHK(lat, hipFree(lat->d_gfield), "vlb_set_force_field");
+        lat->d_gfield = nullptr;
+        lat->gfield_h.clear();
+        return VLB_OK;
+    }
+    if (!lat->d_gfield) {
+        HIPCHK(lat, hipMalloc(&lat->d_gfield, 3 * lat->g.plane * sizeof(float)),
+               "vlb_set_force_field");
+        HIPCHK(lat, hipMemsetAsync(lat->d_gfield, 0, 3 * lat->g.plane * sizeof(float), lat->stream),
+               "vlb_set_force_field");
+    }
+    lat->gfield_h.resize(3 * N);
+    for (uint64_t i = 0; i < 3 * N; ++i)
+        lat->gfield_h[i] = static_cast<float>(F[i]);
+    for (int k = 0; k < 3; ++k)
+        HIPCHK(lat,
+               hipMemcpyAsync(lat->d_gfield + k * lat->g.plane, lat->gfield_h.data() + k * N,
+                              N * sizeof(float), hipMemcpyHostToDevice, lat->stream),
+               "vlb_set_force_field");
     return VLB_OK;
 }
 

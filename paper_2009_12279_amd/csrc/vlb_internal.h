@@ -98,6 +98,9 @@ struct StepArgs {
     double wp, wm;           // omega+, omega-
     double g3[3];            // body force density
     const double *g3_dev;    // body force read on the device instead (counter-force), or null
+    // per-cell force density added to the body force: 3 planes laid out like
+    // u, or null
+    const float *gf_p[3] = {nullptr, nullptr, nullptr};
     double eta_p_lam, inv_lam;
     float scale, inv_scale;  // storage scale s and 1/s
     float gk;                // Giesekus alpha / eta_p (0: Oldroyd-B)
@@ -152,10 +155,11 @@ hipError_t launch_set_populations(int storage, const Geom &g, const uint8_t *mas
                                   const double *f_in, void *f, float scale, hipStream_t s);
 hipError_t launch_set_stress(const Geom &g, const uint8_t *mask, const double *tau_in,
                              float *tau, hipStream_t s);
+// gfield: per-cell force density planes (stride g.plane) added to gvec, or null
 hipError_t launch_read_moments(int storage, const Geom &g, const Bound &b, const uint8_t *mask,
                                const void *f, const float *tau, int polymer, const float gvec[3],
-                               float inv_scale, double *rho_out, double *u_out, hipStream_t s,
-                               const StressMap &sm = StressMap{});
+                               const float *gfield, float inv_scale, double *rho_out,
+                               double *u_out, hipStream_t s, const StressMap &sm = StressMap{});
 hipError_t launch_read_populations(int storage, const Geom &g, const uint8_t *mask, const void *f,
                                    float inv_scale, double *out, hipStream_t s);
 hipError_t launch_read_stress(const Geom &g, const uint8_t *mask, const float *tau, double *out,

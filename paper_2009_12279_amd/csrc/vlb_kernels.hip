@@ -601,6 +601,12 @@ __device__ __forceinline__ void lb_cell(const A &a, uint32_t n, uint32_t step)
         g3[1] = a.g3[1];
         g3[2] = a.g3[2];
     }
+    if (a.gf_p[0]) {
+        // per-cell force density (uniform branch)
+        g3[0] += static_cast<double>(*elem(a.gf_p[0], n));
+        g3[1] += static_cast<double>(*elem(a.gf_p[1], n));
+        g3[2] += static_cast<double>(*elem(a.gf_p[2], n));
+    }
     const R Fx = static_cast<R>(g3[0]) + static_cast<R>(Fp[0]);
     const R Fy = static_cast<R>(g3[1]) + static_cast<R>(Fp[1]);
     const R Fz = static_cast<R>(g3[2]) + static_cast<R>(Fp[2]);
@@ -955,7 +961,7 @@ __device__ __forceinline__ void fv_load(const StepArgs &a, uint32_t idx, float v
 }
 
 template <bool SR, int LAW, int TY>
-__global__ __launch_bounds__(FV_TX * TY) void fv_tile_kernel(StepArgs a, uint32_t zc)
+__global__ __launch_bounds__(FV_TX * TY) FV_OCCUPANCY void fv_tile_kernel(StepArgs a, uint32_t zc)
 {
     static_assert(FV_TX * TY >= 2 * FV_TX + 2 * TY, "ring larger than the block");
     constexpr int W = FV_TX + 2, S = W * (TY + 2);
@@ -1207,9 +1213,9 @@ template <int S>
 __global__ __launch_bounds__(BLOCK) void read_moments_kernel(Geom g, Bound b, const uint8_t *mask,
                                                              const void *fv, const float *tau,
                                                              int polymer, float gx, float gy,
-                                                             float gz, float inv_scale,
-                                                             double *rho_out, double *u_out,
-                                                             StressMap sm)
+                                                             float gz, const float *gfield,
+                                                             float inv_scale, double *rho_out,
+                                                             double *u_out, StressMap sm)
 {
     using St = Store<S>;
     using T = typename St::T;
@@ -1238,6 +1244,9 @@ __global__ __launch_bounds__(BLOCK) void read_moments_kernel(Geom g, Bound b, co
         j[2] += CZ[i] * h;
     }
     double F[3] = {gx, gy, gz};
+    if (gfield)
+        for (int a = 0; a < 3; ++a)
+            F[a] += static_cast<double>(gfield[a * g.plane + n]);
     if (polymer) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
@@ -2074,13 +2083,13 @@ hipError_t launch_set_stress(const Geom &g, const uint8_t *mask, const double *t
 
 hipError_t launch_read_moments(int storage, const Geom &g, const Bound &b, const uint8_t *mask,
                                const void *f, const float *tau, int polymer, const float gvec[3],
-                               float inv_scale, double *rho_out, double *u_out, hipStream_t s,
-                               const StressMap &sm)
+                               const float *gfield, float inv_scale, double *rho_out,
+                               double *u_out, hipStream_t s, const StressMap &sm)
 {
     return dispatch(storage, [&](auto st) {
         hipLaunchKernelGGL(read_moments_kernel<decltype(st)::value>, dim3(blocks_for(g.N)),
                            dim3(BLOCK), 0, s, g, b, mask, f, tau, polymer, gvec[0], gvec[1],
-                           gvec[2], inv_scale, rho_out, u_out, sm);
+                           gvec[2], gfield, inv_scale, rho_out, u_out, sm);
         return hipGetLastError();
     });
 }

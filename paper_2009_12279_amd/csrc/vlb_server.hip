@@ -497,7 +497,8 @@ vlb_status collect(vlb_server *srv, const std::vector<Slot> &done)
         double *d = srv->d_result + off;
         if (e == hipSuccess)
             e = vlb::launch_read_moments(vlb::ST_F32, sl.g, b, sl.mask, sl.f[par], sl.tau[par],
-                                         rq.params.beta > 0.0, gv, 1.f, nullptr, d, srv->io);
+                                         rq.params.beta > 0.0, gv, nullptr, 1.f, nullptr, d,
+                                         srv->io);
         if (e == hipSuccess)
             e = vlb::launch_read_stress(sl.g, sl.mask, sl.tau[par], d + 3 * N, srv->io);
         if (e == hipSuccess)

@@ -108,6 +108,7 @@ SIGNATURES = [
     ("vlb_set_fene_p", ctypes.c_int, [_P, ctypes.c_double]),
     ("vlb_set_stress_extrapolation", ctypes.c_int, [_P, ctypes.c_int32]),
     ("vlb_set_wall_velocity_field", ctypes.c_int, [_P, _D]),
+    ("vlb_set_force_field", ctypes.c_int, [_P, _D]),
     ("vlb_server_create", ctypes.c_int, [ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32, _P,
                                          ctypes.POINTER(_P)]),
     ("vlb_server_set_rounding", ctypes.c_int, [_P, ctypes.c_int]),
@@ -393,6 +394,10 @@ def vlb_set_wall_velocity_field(h, u):
     return _check(lib().vlb_set_wall_velocity_field(h, u), h)
 
 
+def vlb_set_force_field(h, F):
+    return _check(lib().vlb_set_force_field(h, F), h)
+
+
 def vlb_set_counter_force(h, on=True):
     return _check(lib().vlb_set_counter_force(h, 1 if on else 0), h)
 
@@ -534,6 +539,18 @@ class Lattice:
 
     def set_extrapolation(self, order):
         vlb_set_stress_extrapolation(self._h, order)
+
+    def set_force_field(self, F):
+        """Per-cell force density added to the body force, shape
+        (3, nz, ny, nx), stored in FP32; None removes it."""
+        if F is None:
+            vlb_set_force_field(self._h, None)
+            return
+        nx, ny, nz = self.shape
+        F = np.ascontiguousarray(F, dtype=np.float64)
+        if F.shape != (3, nz, ny, nx):
+            raise ValueError(f"force field must have shape {(3, nz, ny, nx)}")
+        vlb_set_force_field(self._h, _dp(F))
 
     def set_wall_velocity_field(self, u):
         """Per-cell wall velocity, shape (3, nz, ny, nx); None returns to the

@@ -1,0 +1,102 @@
+"""Force densities that vary from cell to cell on the GPU: parity with the
+oracle (a 3D box with a random force field and polymer stress, and the
+four-roll mill at the paper's size), and the four-roll mill of Section 4.4
+on its 45-degree rotated 214 x 214 lattice (L = 214 sqrt2, eta_n = 1.5,
+eta_p / eta = 1/3, u0 = 1e-3, 20 lambda_p steps): at low Wi the flow is the
+Newtonian one slowed by eta_n / eta, and at the central stagnation point the
+stress obeys the steady planar-extension relation of the Oldroyd-B model,
+tau_XX = 2 eta_p alpha / (1 - 2 lambda_p alpha), alpha the extension rate."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2009_12279_amd import inputs
+from parity import Case, build, compare, log
+from test_oracle_4rm import SQ2, four_roll_mill
+
+pytestmark = pytest.mark.gpu
+
+THREADS = max(1, min(16, os.cpu_count() or 1))
+M, ETA_N, BETA, U0 = 214, 1.5, 1 / 3, 1e-3
+ETA = ETA_N / (1 - BETA)
+
+
+def test_random_force_field_box_parity():
+    """20x18x16 box, walls along y, random force density up to 1e-4, Oldroyd-B,
+    300 steps."""
+    shape = (20, 18, 16)
+    mask = inputs.channel_mask(shape, wall_axes=(1,))
+    F = inputs.noise_field(43, 0, shape, 1e-4)
+    case = Case("force-field-box", shape, mask, (1, 0, 1), None,
+                dict(eta=1 / 3, beta=0.5, lambda_p=40.0, magic=3 / 16, body_force=(1e-6, 0, 0)))
+    log("[4rm] random per-cell force density, 20x18x16 channel, 300 steps")
+    g, o = build(case, threads=THREADS)
+    g.set_force_field(F)
+    o.set_force_field(F)
+    g.step(300)
+    o.step(300)
+    e = compare(g, o, case, what=("u", "tau", "rho"))
+    log(f"[4rm]   errors {e}")
+    for k in ("u", "tau", "rho"):
+        assert e[k][0] < 1e-5 and e[k][1] < 1e-5, (k, e[k])
+    g.close()
+    o.close()
+
+
+def run_mill(lam, oracle_steps=0):
+    F, U, L = four_roll_mill(M, True, ETA_N, U0)
+    case = Case("four-roll-mill", (M, M, 1), np.zeros((1, M, M), np.uint8), (1, 1, 1), None,
+                dict(eta=ETA, beta=BETA, lambda_p=lam, magic=3 / 16))
+    g, o = build(case, threads=THREADS)
+    g.set_force_field(F)
+    if oracle_steps:
+        o.set_force_field(F)
+        g.step(oracle_steps)
+        o.step(oracle_steps)
+        e = compare(g, o, case, what=("u", "tau", "rho"))
+        log(f"[4rm]   {oracle_steps} steps against the oracle: {e}")
+        for k in ("u", "tau", "rho"):
+            assert e[k][0] < 1e-5, (k, e[k])
+    o.close()
+    g.step(int(20 * lam) - oracle_steps)
+    u, tau = g.velocity(), g.stress()
+    g.close()
+    return u, tau, U, L
+
+
+def centre(u, tau, lam):
+    """Extension rate alpha along X and tau_XX at the centre cell (M/2, M/2);
+    X runs along the lattice diagonal (1, -1)."""
+    c = M // 2
+    uX = lambda i, j: (u[0, 0, j, i] - u[1, 0, j, i]) / SQ2
+    alpha = (uX(c + 1, c - 1) - uX(c - 1, c + 1)) / (2 * SQ2)
+    tXX = 0.5 * (tau[0, 0, c, c] - 2 * tau[3, 0, c, c] + tau[1, 0, c, c])
+    return alpha, tXX
+
+
+def test_four_roll_mill_low_wi_newtonian_limit():
+    lam = 1000.0
+    log(f"[4rm] four-roll mill 214x214 rotated, lambda_p = {lam:.0f}, 20 lambda_p steps")
+    u, tau, U, L = run_mill(lam, oracle_steps=200)
+    amp = np.sum(u[:2] * U[:2]) / np.sum(U[:2] ** 2)
+    dev = np.abs(u[:2] - amp * U[:2]).max() / U0
+    alpha, tXX = centre(u, tau, lam)
+    log(f"[4rm]   Wi = {4 * np.pi * lam * U0 / L:.3f}: amplitude {amp:.5f} (eta_n/eta = "
+        f"{ETA_N / ETA:.5f}), deviation from that field {dev:.2e} u0, Wi_eff = {lam * alpha:.4f}")
+    assert abs(amp / (ETA_N / ETA) - 1) < 1e-3
+    assert dev < 1e-4
+    k = 2 * np.pi / L
+    assert abs(alpha / (k * U0 * ETA_N / ETA) - 1) < 1e-3
+
+
+def test_four_roll_mill_stagnation_point_stress():
+    lam = 6000.0
+    log(f"[4rm] four-roll mill 214x214 rotated, lambda_p = {lam:.0f}, 20 lambda_p steps")
+    u, tau, U, L = run_mill(lam)
+    alpha, tXX = centre(u, tau, lam)
+    eta_p = BETA * ETA
+    pred = 2 * eta_p * alpha / (1 - 2 * lam * alpha)
+    log(f"[4rm]   Wi = {4 * np.pi * lam * U0 / L:.3f}: Wi_eff = {lam * alpha:.4f}, tau_XX(centre) "
+        f"{tXX:.5e}, planar extension {pred:.5e}")
+    assert abs(tXX / pred - 1) < 1e-3
