@@ -89,6 +89,51 @@ def test_checkpoint_restart_is_bitwise(tmp_path, storage):
     assert not np.array_equal(got[2], m_saved)
 
 
+def test_checkpoint_keeps_wall_velocity_and_force_fields(tmp_path):
+    """Per-cell wall velocity and force density survive save/load bit for bit
+    (the FP32 force planes included), and clearing them returns to the plain
+    lattice."""
+    path = str(tmp_path / "ck_fields.vlb")
+    shape = (16, 14, 12)
+    log("[lattice] checkpoint with wall velocity and force fields")
+    mask = inputs.channel_mask(shape, wall_axes=(1, 2))
+    wf = inputs.noise_field(51, 0, shape, 1e-3)
+    wf[:, mask == 0] = 0.0
+    F = inputs.noise_field(52, 0, shape, 1e-4)
+    L = vlb.Lattice(shape, mask, (1, 0, 0))
+    L.set_params(eta=1 / 3, beta=0.5, lambda_p=30.0, magic=3 / 16)
+    L.set_check_interval(0)
+    L.set_wall_velocity_field(wf)
+    L.set_force_field(F)
+    L.step(50)
+    L.save(path)
+    L.step(100)
+    ref = (L.populations(), L.stress(), L.velocity())
+    R = vlb.Lattice.load(path, shape)
+    R.step(100)
+    got = (R.populations(), R.stress(), R.velocity())
+    R.close()
+    for a, b in zip(got, ref):
+        np.testing.assert_array_equal(a, b)
+    L.close()
+    # cleared fields: the same as a lattice that never had them
+    runs = []
+    for clear in (True, False):
+        P = vlb.Lattice(shape, mask, (1, 0, 0))
+        P.set_params(eta=1 / 3, beta=0.5, lambda_p=30.0, magic=3 / 16, body_force=(1e-5, 0, 0))
+        P.set_check_interval(0)
+        if clear:
+            P.set_wall_velocity_field(wf)
+            P.set_force_field(F)
+            P.set_wall_velocity_field(None)
+            P.set_force_field(None)
+        P.step(50)
+        runs.append((P.populations(), P.stress()))
+        P.close()
+    for a, b in zip(*runs):
+        np.testing.assert_array_equal(a, b)
+
+
 def test_load_rejects_a_file_that_is_not_a_checkpoint(tmp_path):
     p = tmp_path / "junk.vlb"
     p.write_bytes(b"not a checkpoint" * 8)
