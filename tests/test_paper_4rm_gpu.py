@@ -54,10 +54,15 @@ def run_mill(lam, oracle_steps=0):
         o.set_force_field(F)
         g.step(oracle_steps)
         o.step(oracle_steps)
-        e = compare(g, o, case, what=("u", "tau", "rho"))
-        log(f"[4rm]   {oracle_steps} steps against the oracle: {e}")
-        for k in ("u", "tau", "rho"):
+        e = compare(g, o, case, what=("u", "tau"))
+        # rho - 1 is O(u0^2) here, below what FP32 populations (deviations
+        # O(u0)) resolve relative to itself; its error is held to the
+        # population scale instead
+        drho = np.abs(g.density() - o.density()).max()
+        log(f"[4rm]   {oracle_steps} steps against the oracle: {e}, max |d rho| {drho:.2e}")
+        for k in ("u", "tau"):
             assert e[k][0] < 1e-5, (k, e[k])
+        assert drho < 1e-5 * U0
     o.close()
     g.step(int(20 * lam) - oracle_steps)
     u, tau = g.velocity(), g.stress()
