@@ -156,7 +156,7 @@ def fv_apply(mask, tau, u, eta_p, lambda_p, alpha=0.0, L2=0.0):
 
 def polymer_force(mask, tau, order=0):
     """Discrete polymer force; `order` of the extrapolation into solid face
-    neighbours (0 constant, 1 linear)."""
+    neighbours (0 constant, 1 linear, 2 quadratic)."""
     nz, ny, nx = mask.shape
     m = np.ascontiguousarray(mask, dtype=np.uint8)
     t = np.ascontiguousarray(tau, dtype=np.float64)
@@ -240,7 +240,7 @@ class Lattice:
 
     def set_extrapolation(self, order):
         if lib().or_set_extrapolation(self._h, int(order)) != 0:
-            raise ValueError("oracle: extrapolation order must be 0 or 1")
+            raise ValueError("oracle: extrapolation order must be 0, 1 or 2")
 
     def set_fene_p(self, L2):
         if lib().or_set_fene_p(self._h, float(L2)) != 0:

@@ -228,9 +228,13 @@ static void tau_put(double *tau, long N, long n, double t[3][3])
 /* Section 3.3: polymer force and finite-volume stress update */
 
 /* Stress taken for a solid face neighbour of fluid cell n in direction k
- * (Section 3.3, extrapolation into boundary nodes): this cell's stress
- * (constant, order 0), or with order 1 the linear extrapolation
- * 2 tau(n) - tau(n - e_k) when the cell behind n is fluid (else constant). */
+ * (Section 3.3, extrapolation into boundary nodes), as the polynomial
+ * through n and the fluid cells behind it evaluated one cell ahead:
+ * this cell's stress (constant, order 0); with order 1 the line through n
+ * and n - e_k, 2 tau(n) - tau(n - e_k); with order 2 the parabola through
+ * n, n - e_k and n - 2 e_k, 3 tau(n) - 3 tau(n - e_k) + tau(n - 2 e_k).
+ * Where a cell behind is solid the order drops to what the fluid cells
+ * support. */
 static void boundary_stress(int nx, int ny, int nz, const unsigned char *mask, const double *tau,
                             long N, int x, int y, int z, int k, int order, double tb[3][3])
 {
@@ -244,6 +248,19 @@ static void boundary_stress(int nx, int ny, int nz, const unsigned char *mask, c
         return;
     double tm[3][3];
     tau_get(tau, N, b, tm);
+    if (order >= 2) {
+        /* the cell two behind, reached from the first one */
+        int x1 = wrap(x + back[0], nx), y1 = wrap(y + back[1], ny), z1 = wrap(z + back[2], nz);
+        long b2 = nbr(nx, ny, nz, x1, y1, z1, back);
+        if (mask[b2] == 0) {
+            double t2[3][3];
+            tau_get(tau, N, b2, t2);
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j)
+                    tb[i][j] = 3.0 * tb[i][j] - 3.0 * tm[i][j] + t2[i][j];
+            return;
+        }
+    }
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j)
             tb[i][j] = 2.0 * tb[i][j] - tm[i][j];
@@ -430,7 +447,7 @@ struct or_lattice {
     int counter_force;               /* -sum of the free particles' F_ext spread over the fluid */
     double alpha;                    /* Giesekus mobility (0: Oldroyd-B) */
     double L2;                       /* FENE-P extensibility L^2 (0: not FENE-P) */
-    int extrap;                      /* stress extrapolation into solid nodes: 0 constant, 1 linear */
+    int extrap;                      /* stress extrapolation into solid nodes: 0 constant, 1 linear, 2 quadratic */
     double *stress;                  /* polymer stress of the stored state (6*N) */
     double wp, wm, eta_p;
     int polymer;
@@ -745,7 +762,7 @@ void or_set_wall_velocity_field(or_lattice *L, const double *u)
 
 int or_set_extrapolation(or_lattice *L, int order)
 {
-    if (order < 0 || order > 1)
+    if (order < 0 || order > 2)
         return -1;
     L->extrap = order;
     return 0;

@@ -57,8 +57,9 @@ void or_fv_apply(int nx, int ny, int nz, const unsigned char *mask, const double
 void or_polymer_force(int nx, int ny, int nz, const unsigned char *mask, const double *tau,
                       double *fp_out);
 /* Same with the extrapolation into solid face neighbours of order 0
- * (constant, as above) or 1 (linear through the cell behind, constant when
- * that cell is solid). */
+ * (constant, as above), 1 (linear through the cell behind, constant when
+ * that cell is solid) or 2 (quadratic through the two cells behind, linear
+ * when only the first of them is fluid). */
 void or_polymer_force_ext(int nx, int ny, int nz, const unsigned char *mask, const double *tau,
                           int order, double *fp);
 
@@ -92,8 +93,9 @@ void or_set_force_field(or_lattice *L, const double *F);
  * entry instead of the per-id table.  NULL returns to the table. */
 void or_set_wall_velocity_field(or_lattice *L, const double *u);
 /* Stress extrapolation into solid face neighbours (Section 3.3): 0 constant
- * (default), 1 linear; the traction on obstacles uses the same face values.
- * -1 for other orders. */
+ * (default), 1 linear, 2 quadratic through the fluid cells behind (lower
+ * where fewer of them are fluid); the traction on obstacles uses the same
+ * face values.  -1 for other orders. */
 int or_set_extrapolation(or_lattice *L, int order);
 void or_init_equilibrium(or_lattice *L, const double *u);
 void or_set_populations(or_lattice *L, const double *f);

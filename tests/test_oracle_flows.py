@@ -284,11 +284,13 @@ def test_momentum_balance_holds_for_other_constitutive_laws(orc, model):
         p0 = p1
 
 
-def test_momentum_balance_holds_with_linear_extrapolation(orc):
+@pytest.mark.parametrize("order", [1, 2])
+def test_momentum_balance_holds_with_extrapolation(orc, order):
     """The traction on obstacles uses the face values the polymer force used,
-    so the exact momentum balance also holds with linear extrapolation."""
+    so the exact momentum balance also holds with linear and quadratic
+    extrapolation."""
     L, m, g = _fixed_geometry(orc, 4)
-    L.set_extrapolation(1)
+    L.set_extrapolation(order)
     Nf = int((m == 0).sum())
     _, p0 = L.sums()
     for _ in range(10):

@@ -266,6 +266,39 @@ def test_fene_p_steady_shear_matches_the_conformation_solution(orc):
     np.testing.assert_allclose(T_fe, T_ob, rtol=1e-8, atol=1e-9 * np.abs(T_ob).max())
 
 
+def test_quadratic_extrapolation_reproduces_the_divergence_next_to_walls(orc):
+    """With quadratic extrapolation the discrete force of a stress field
+    quadratic in the wall-normal coordinate is its divergence in every fluid
+    cell with two fluid layers behind it (central differences are exact for
+    quadratics); linear extrapolation misses the curvature in the cells next
+    to the walls, and with a single fluid layer behind a wall the quadratic
+    order falls back to the linear one."""
+    rng = np.random.default_rng(16)
+    nx, ny, nz = 6, 12, 5
+    mask = np.zeros((nz, ny, nx), np.uint8)
+    mask[:, 0, :] = 1
+    mask[:, -1, :] = 1
+    A, B, Cq = rng.standard_normal(6), rng.standard_normal(6), rng.standard_normal(6)
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    yy = y.astype(float)
+    tau = np.stack([A[k] + B[k] * yy + Cq[k] * yy ** 2 for k in range(6)])
+    # divergence: F_j = d tau_yj / dy at cell centres
+    dtau = np.stack([B[k] + 2 * Cq[k] * yy for k in range(6)])
+    div = np.stack([dtau[3], dtau[1], dtau[5]])   # (tau_xy, tau_yy, tau_yz) along y
+    quad = orc.polymer_force(mask, tau, order=2)
+    lin = orc.polymer_force(mask, tau, order=1)
+    fluid = mask == 0
+    np.testing.assert_allclose(quad[:, fluid], div[:, fluid], rtol=0, atol=1e-11)
+    wall_rows = (slice(None), slice(None), [1, -2], slice(None))
+    assert np.max(np.abs(lin[wall_rows] - div[wall_rows])) > 0.1 * np.abs(Cq[[3, 1, 5]]).min()
+    # one fluid layer behind the wall: quadratic = linear there
+    mask2 = mask.copy()
+    mask2[:, 3, :] = 1            # fluid rows 1, 2 between two walls
+    q2 = orc.polymer_force(mask2, tau, order=2)
+    l2 = orc.polymer_force(mask2, tau, order=1)
+    np.testing.assert_array_equal(q2[:, :, 1:3, :], l2[:, :, 1:3, :])
+
+
 def test_linear_extrapolation_reproduces_the_divergence_next_to_walls(orc):
     """With linear extrapolation into solid neighbours (Section 3.3 offers it
     beside the constant one) the discrete force of a linear stress field is
