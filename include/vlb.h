@@ -226,12 +226,13 @@ vlb_status vlb_set_giesekus(vlb_lattice *lat, double alpha);
 vlb_status vlb_set_fene_p(vlb_lattice *lat, double L2);
 
 /* Extrapolation of the stress into solid face neighbours for the polymer
- * force (Section 3.3): 0 takes the fluid cell's own stress (the default), 1
- * extrapolates linearly through the cell behind it, as
- * 2 tau(x) - tau(x - e), falling back to the own stress where that cell is
- * solid.  The traction on
- * obstacles uses the same face values, so momentum stays balanced.
- * VLB_EINVAL for other orders.  Kept in checkpoints. */
+ * force (Section 3.3): the polynomial through the fluid cell and the fluid
+ * cells behind it, evaluated at the solid neighbour.  0 takes the cell's own
+ * stress (the default); 1 is linear, 2 tau(x) - tau(x - e); 2 is quadratic,
+ * 3 tau(x) - 3 tau(x - e) + tau(x - 2e).  Where a cell behind is solid the
+ * order drops to what the fluid cells support.  The traction on obstacles
+ * uses the same face values, so momentum stays balanced.  VLB_EINVAL for
+ * other orders.  Kept in checkpoints. */
 vlb_status vlb_set_stress_extrapolation(vlb_lattice *lat, int32_t order);
 
 /* Force density that varies from cell to cell (Section 3.1 Guo forcing; the

@@ -1287,7 +1287,7 @@ vlb_status vlb_load(const char *path, void *stream, vlb_lattice **out)
     lat->counter_force = h.counter_force != 0;
     lat->alpha = (h.alpha >= 0.0 && h.alpha <= 0.5) ? h.alpha : 0.0;
     lat->L2 = (h.L2 > 3.0 && std::isfinite(h.L2)) ? h.L2 : 0.0;
-    lat->extrap = h.extrap == 1 ? 1 : 0;
+    lat->extrap = (h.extrap >= 0 && h.extrap <= 2) ? h.extrap : 0;
     lat->scale = h.scale;
     lat->inv_scale = 1.f / h.scale;
     hipError_t e = hipMemcpyAsync(lat->d_mask, mask.data(), N, hipMemcpyHostToDevice, lat->stream);
@@ -1343,8 +1343,8 @@ vlb_status vlb_set_stress_extrapolation(vlb_lattice *lat, int32_t order)
 {
     if (!lat)
         return VLB_EINVAL;
-    if (order < 0 || order > 1)
-        return fail(lat, VLB_EINVAL, "vlb_set_stress_extrapolation: order must be 0 or 1");
+    if (order < 0 || order > 2)
+        return fail(lat, VLB_EINVAL, "vlb_set_stress_extrapolation: order must be 0, 1 or 2");
     lat->extrap = order;
     return VLB_OK;
 }

@@ -74,7 +74,8 @@ struct Bound {
 struct StressMap {
     float c = 0.f, l2m3 = 0.f, epl = 0.f;
     // extrapolation into a solid face neighbour: 0 this cell's stress, 1 linear
-    // through the cell behind (constant where that cell is solid)
+    // through the cell behind, 2 quadratic through the two cells behind (the
+    // order drops where a cell behind is solid)
     int32_t extrap = 0;
 };
 

@@ -409,6 +409,31 @@ __device__ __forceinline__ double mapped_stress(const StressMap &sm, const float
     return t * (1.0 + g1) + (comp < 3 ? static_cast<double>(sm.epl) * g1 : 0.0);
 }
 
+// Stress that fluid cell nb.at(0, 0, 0) extrapolates into its solid face
+// neighbour along c = (cx, cy, cz) (Section 3.3): the polynomial through the
+// cell and the fluid cells behind it, evaluated one cell ahead, of degree
+// sm.extrap at most (0 the cell's own stress, 1 linear, 2 quadratic) and
+// lower where a cell behind is solid.
+__device__ double extrap_stress(const Geom &g, const uint8_t *mask, const float *tau,
+                                const StressMap &sm, const Nbr &nb, int cx, int cy, int cz,
+                                int comp)
+{
+    const double own = mapped_stress(sm, tau, g.plane, nb.at(0, 0, 0), comp);
+    if (!sm.extrap)
+        return own;
+    const uint32_t b1 = nb.at(-cx, -cy, -cz);
+    if (mask[b1] != 0)
+        return own;
+    const double t1 = mapped_stress(sm, tau, g.plane, b1, comp);
+    if (sm.extrap >= 2) {
+        const Nbr nb1(g, nb.xc[1 - cx], nb.yc[1 - cy], nb.zc[1 - cz]);
+        const uint32_t b2 = nb1.at(-cx, -cy, -cz);
+        if (mask[b2] == 0)
+            return 3.0 * own - 3.0 * t1 + mapped_stress(sm, tau, g.plane, b2, comp);
+    }
+    return 2.0 * own - t1;
+}
+
 // Field-wise copies of the geometry and boundary descriptors, for argument
 // blocks that live in the constant address space (the implicit copy
 // constructor cannot bind to those).
@@ -566,15 +591,43 @@ __device__ __forceinline__ void lb_cell(const A &a, uint32_t n, uint32_t step)
         }
         // face bits of `links`: +x 1, -x 2, +y 3, -y 4, +z 5, -z 6
         if (a.sm.extrap && ((links >> 1) & 63u)) {
-            // linear extrapolation into solid face neighbours (rare path)
+            // linear or quadratic extrapolation into solid face neighbours
+            // through the fluid cells behind (rare path)
+            StressMap smc;
+            smc.c = a.sm.c;
+            smc.l2m3 = a.sm.l2m3;
+            smc.epl = a.sm.epl;
+            smc.extrap = a.sm.extrap;
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 const bool sp = (links >> (2 * k + 1)) & 1u, sm = (links >> (2 * k + 2)) & 1u;
+                // quadratic: the cell two behind the solid face, if fluid
+                float t2[3] = {0.f, 0.f, 0.f};
+                bool quad = false;
+                if (smc.extrap >= 2 && sp != sm) {
+                    const int sg = sp ? -1 : 1;  // from the cell toward the fluid behind it
+                    const int cx = sg * (k == 0), cy = sg * (k == 1), cz = sg * (k == 2);
+                    const uint32_t m1 = d.at_rt(n, cx, cy, cz);
+                    int x1, y1, z1;
+                    coords(g, m1, x1, y1, z1);
+                    const Delta d1(g, x1, y1, z1);
+                    const uint32_t m2 = d1.at_rt(m1, cx, cy, cz);
+                    if (mask[m2] == 0) {
+                        quad = true;
+                        for (int j = 0; j < 3; ++j)
+                            t2[j] = static_cast<float>(
+                                mapped_stress(smc, a.tin, g.plane, m2, TROW[k][j]));
+                    }
+                }
 #pragma unroll
                 for (int j = 0; j < 3; ++j) {
                     const float own = town[TROW[k][j]];
-                    const float vp = sp ? (sm ? own : 2.f * own - tn[k][1][j]) : tn[k][0][j];
-                    const float vm = sm ? (sp ? own : 2.f * own - tn[k][0][j]) : tn[k][1][j];
+                    const float ep = quad ? fmaf(3.f, own - tn[k][1][j], t2[j])
+                                          : 2.f * own - tn[k][1][j];
+                    const float em = quad ? fmaf(3.f, own - tn[k][0][j], t2[j])
+                                          : 2.f * own - tn[k][0][j];
+                    const float vp = sp ? (sm ? own : ep) : tn[k][0][j];
+                    const float vm = sm ? (sp ? own : em) : tn[k][1][j];
                     Fp[j] += 0.5f * (vp - vm);
                 }
             }
@@ -1255,14 +1308,12 @@ __global__ __launch_bounds__(BLOCK) void read_moments_kernel(Geom g, Bound b, co
             const bool solp = mask[ip] != 0, solm = mask[im] != 0;
 #pragma unroll
             for (int jj = 0; jj < 3; ++jj) {
-                const double own = mapped_stress(sm, tau, g.plane, n, TROW[k][jj]);
-                const double tp = solp ? own : mapped_stress(sm, tau, g.plane, ip, TROW[k][jj]);
-                const double tm = solm ? own : mapped_stress(sm, tau, g.plane, im, TROW[k][jj]);
-                double vp = tp, vm = tm;
-                if (sm.extrap && solp && !solm)
-                    vp = 2.0 * own - tm;
-                if (sm.extrap && solm && !solp)
-                    vm = 2.0 * own - tp;
+                const int c = TROW[k][jj];
+                const double vp = solp ? extrap_stress(g, mask, tau, sm, nb, k == 0, k == 1, k == 2, c)
+                                       : mapped_stress(sm, tau, g.plane, ip, c);
+                const double vm = solm ? extrap_stress(g, mask, tau, sm, nb, -(k == 0), -(k == 1),
+                                                       -(k == 2), c)
+                                       : mapped_stress(sm, tau, g.plane, im, c);
                 F[jj] += 0.5 * (vp - vm);
             }
         }
@@ -1477,16 +1528,16 @@ __device__ void link_forces(const Geom &g, const uint8_t *mask, const void *fv, 
             const uint32_t m = nb.at(cx, cy, cz);
             if (!owner_match(mask[m]))
                 continue;
-            // the face value the polymer force used: this cell's stress, or
-            // with linear extrapolation the mean of it and 2 tau(n) - tau(behind)
-            const uint32_t bk = nb.at(-cx, -cy, -cz);
-            const bool lin = sm.extrap && mask[bk] == 0;
+            // the face value the polymer force used: the mean of this cell's
+            // stress and the one extrapolated into the solid neighbour
             double dF[3];
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
                 const double own = mapped_stress(sm, tau, g.plane, n, TROW[k][j]);
                 const double face =
-                    lin ? 1.5 * own - 0.5 * mapped_stress(sm, tau, g.plane, bk, TROW[k][j]) : own;
+                    sm.extrap ? 0.5 * (own + extrap_stress(g, mask, tau, sm, nb, cx, cy, cz,
+                                                           TROW[k][j]))
+                              : own;
                 dF[j] = -s * face;
             }
             acc[6] += dF[0];

@@ -256,17 +256,20 @@ def test_giesekus_channel():
     assert o.stress()[1][:, 10:-10, :].max() < 0
 
 
-@pytest.mark.parametrize("steps", [1, 30])
-def test_fene_p_random_lattice(steps):
-    """FENE-P (L^2 = 10) on a random lattice with moving walls and a sphere:
-    stored variable, polymer stress, populations, and the forces on the
-    sphere and walls, GPU against the oracle."""
+@pytest.mark.parametrize("order,steps", [(0, 1), (0, 30), (2, 30)])
+def test_fene_p_random_lattice(steps, order):
+    """FENE-P (L^2 = 10) on a random lattice with moving walls and a sphere,
+    with constant and quadratic stress extrapolation: stored variable,
+    polymer stress, populations, and the forces on the sphere and walls, GPU
+    against the oracle."""
     case = random_case(22, (10, 9, 8), (1, 0, 1), True, ((4.6, 4.3, 3.9), 2.0))
     case.tau0 = case.tau0 * 5.0
-    log(f"[parity] fene-p random lattice, {steps} steps")
+    log(f"[parity] fene-p random lattice, extrapolation order {order}, {steps} steps")
     g, o = build(case)
     g.set_fene_p(10.0)
     o.set_fene_p(10.0)
+    g.set_extrapolation(order)
+    o.set_extrapolation(order)
     g.step(steps)
     o.step(steps)
     e = compare(g, o, case)
@@ -299,16 +302,16 @@ def test_fene_p_channel():
     assert e["u"][0] < 1e-5 and e["tau"][0] < 1e-5
 
 
-@pytest.mark.parametrize("steps", [1, 30])
-def test_linear_extrapolation_random_lattice(steps):
-    """Linear stress extrapolation into solid neighbours on a random lattice
-    with moving walls and a sphere, GPU against the oracle (fields and the
-    forces on sphere and walls)."""
+@pytest.mark.parametrize("order,steps", [(1, 1), (1, 30), (2, 1), (2, 30)])
+def test_extrapolation_random_lattice(order, steps):
+    """Linear and quadratic stress extrapolation into solid neighbours on a
+    random lattice with moving walls and a sphere, GPU against the oracle
+    (fields and the forces on sphere and walls)."""
     case = random_case(23, (10, 9, 8), (1, 0, 1), True, ((4.6, 4.3, 3.9), 2.0))
-    log(f"[parity] linear extrapolation random lattice, {steps} steps")
+    log(f"[parity] extrapolation order {order} random lattice, {steps} steps")
     g, o = build(case)
-    g.set_extrapolation(1)
-    o.set_extrapolation(1)
+    g.set_extrapolation(order)
+    o.set_extrapolation(order)
     g.step(steps)
     o.step(steps)
     e = compare(g, o, case)
