@@ -98,6 +98,13 @@ struct vlb_lattice {
     std::vector<double> wfield_h; // host copy, for checkpoints
     float *d_gfield = nullptr;    // per-cell force density, 3 planes of g.plane (null: none)
     std::vector<float> gfield_h;  // host copy [3][N], for checkpoints
+    // graph replays of kGraphSteps steps, one per starting buffer parity,
+    // with the step arguments and launch shape they were captured with
+    uint32_t *d_step = nullptr;   // base step the replayed kernels add their offset to
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    vlb::StepArgs gkey[2];
+    int gshape[2][2] = {{0, 0}, {0, 0}};
+    bool graph_broken = false;    // capture failed once: keep launching step by step
     Particle *d_parts = nullptr;
     double *d_partials = nullptr;
     double *d_pforce = nullptr;   // block sums of the obstacle forces
@@ -272,9 +279,14 @@ void free_all(vlb_lattice *lat)
         for (void *p : state)
             if (p)
                 (void)hipFree(p);
+    for (hipGraphExec_t &x : lat->gexec)
+        if (x) {
+            (void)hipGraphExecDestroy(x);
+            x = nullptr;
+        }
     void *ptrs[] = {lat->d_wall,   lat->d_parts, lat->d_partials, lat->d_out,
                     lat->d_counters, lat->d_pforce, lat->d_count, lat->d_g3,
-                    lat->d_wfield, lat->d_gfield};
+                    lat->d_wfield, lat->d_gfield, lat->d_step};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -745,6 +757,104 @@ vlb_status vlb_add_sphere(vlb_lattice *lat, const double center[3], double radiu
     return VLB_OK;
 }
 
+namespace {
+
+// Steps per graph replay (even, so that a replay leaves the buffer parity
+// as it found it).
+constexpr int kGraphSteps = 32;
+
+bool graphs_enabled()
+{
+    const char *e = std::getenv("VLB_GRAPH");
+    return !(e && e[0] == '0');
+}
+
+// Point the plane pointers of `a` at the buffers of parity `cur`.
+void set_planes(const vlb_lattice *lat, vlb::StepArgs &a, int cur)
+{
+    a.fin = lat->d_f[cur];
+    a.fout = lat->d_f[cur ^ 1];
+    a.tin = lat->d_tau[cur];
+    a.tout = lat->d_tau[cur ^ 1];
+    const size_t pb = lat->g.plane * storage_bytes(lat->storage);
+    for (int i = 0; i < vlb::Q; ++i) {
+        a.fin_p[i] = static_cast<const char *>(a.fin) + i * pb;
+        a.fout_p[i] = static_cast<char *>(a.fout) + i * pb;
+    }
+    for (int c = 0; c < 6; ++c) {
+        a.tin_p[c] = a.tin + c * lat->g.plane;
+        a.tout_p[c] = a.tout + c * lat->g.plane;
+    }
+    for (int c = 0; c < 3; ++c)
+        a.u_p[c] = a.u + c * lat->g.plane;
+}
+
+// Record the kGraphSteps steps that start at parity `par` into a graph
+// executable; kernels take their step index as *d_step + offset.
+hipError_t capture_steps(vlb_lattice *lat, const vlb::StepArgs &base, int par, int tile_rows,
+                         uint32_t z_chunk, hipGraphExec_t *out)
+{
+    hipStream_t st = lat->stream;
+    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess)
+        return e;
+    hipError_t le = hipSuccess;
+    for (int k = 0; k < kGraphSteps && le == hipSuccess; ++k) {
+        vlb::StepArgs a = base;
+        set_planes(lat, a, (par + k) & 1);
+        a.step = static_cast<uint32_t>(k);
+        a.step_dev = lat->d_step;
+        le = vlb::launch_lb_step(lat->storage, a, st);
+        if (le == hipSuccess && lat->polymer)
+            le = vlb::launch_fv_step(lat->storage, a, st, tile_rows, z_chunk);
+    }
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(st, &graph);
+    if (le == hipSuccess)
+        le = e;
+    if (le == hipSuccess)
+        le = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+    if (graph)
+        (void)hipGraphDestroy(graph);
+    return le;
+}
+
+// One replay of kGraphSteps steps from the lattice's current step and
+// parity; the graph is captured again when the step arguments or the launch
+// shape differ from those it was captured with.
+hipError_t replay_steps(vlb_lattice *lat, const vlb::StepArgs &base)
+{
+    const int par = lat->cur;
+    const int tile_rows = fv_tile_rows();
+    const uint32_t z_chunk = fv_z_chunk();
+    hipError_t e = hipSuccess;
+    if (!lat->d_step && (e = hipMalloc(&lat->d_step, sizeof(uint32_t))) != hipSuccess)
+        return e;
+    vlb::StepArgs key = base;
+    set_planes(lat, key, par);
+    key.step_dev = lat->d_step;
+    if (!lat->gexec[par] || std::memcmp(&key, &lat->gkey[par], sizeof key) != 0 ||
+        lat->gshape[par][0] != tile_rows || lat->gshape[par][1] != static_cast<int>(z_chunk)) {
+        if (lat->gexec[par]) {
+            (void)hipGraphExecDestroy(lat->gexec[par]);
+            lat->gexec[par] = nullptr;
+        }
+        if ((e = capture_steps(lat, base, par, tile_rows, z_chunk, &lat->gexec[par])) != hipSuccess) {
+            lat->gexec[par] = nullptr;
+            return e;
+        }
+        std::memcpy(&lat->gkey[par], &key, sizeof key);
+        lat->gshape[par][0] = tile_rows;
+        lat->gshape[par][1] = static_cast<int>(z_chunk);
+    }
+    if ((e = vlb::launch_set_step(lat->d_step, static_cast<uint32_t>(lat->step), 0,
+                                  lat->stream)) != hipSuccess)
+        return e;
+    return hipGraphLaunch(lat->gexec[par], lat->stream);
+}
+
+}  // namespace
+
 vlb_status vlb_step(vlb_lattice *lat, int64_t n_steps)
 {
     if (!lat)
@@ -753,7 +863,9 @@ vlb_status vlb_step(vlb_lattice *lat, int64_t n_steps)
         return fail(lat, VLB_EINVAL, "vlb_step: negative step count");
     if (lat->unstable)
         return fail(lat, VLB_EUNSTABLE, "vlb_step: lattice is unstable (sticky)");
-    vlb::StepArgs a{};
+    // zeroed padding included, so that step arguments compare bytewise
+    vlb::StepArgs a;
+    std::memset(&a, 0, sizeof a);
     a.g = lat->g;
     a.b = lat->bound();
     a.mask = lat->d_mask;
@@ -793,23 +905,36 @@ vlb_status vlb_step(vlb_lattice *lat, int64_t n_steps)
             lat->events.push_back(e);
         }
     }
-    for (int64_t s = 0; s < n_steps; ++s) {
-        a.fin = lat->d_f[lat->cur];
-        a.fout = lat->d_f[lat->cur ^ 1];
-        a.tin = lat->d_tau[lat->cur];
-        a.tout = lat->d_tau[lat->cur ^ 1];
-        const size_t pb = lat->g.plane * storage_bytes(lat->storage);
-        for (int i = 0; i < vlb::Q; ++i) {
-            a.fin_p[i] = static_cast<const char *>(a.fin) + i * pb;
-            a.fout_p[i] = static_cast<char *>(a.fout) + i * pb;
+    // Lattices without moving particles replay their steps from a graph, in
+    // chunks of kGraphSteps that no health check falls inside; the same
+    // kernels with the same arguments run, so the results are the same bits.
+    const bool graph_ok = !lat->timing && !lat->any_movable && !counter && !lat->graph_broken &&
+                          graphs_enabled();
+    int64_t s = 0;
+    while (s < n_steps) {
+        const int64_t ci = lat->check_interval;
+        const bool check_inside = ci > 0 && (lat->step / ci + 1) * ci < lat->step + kGraphSteps;
+        if (graph_ok && n_steps - s >= kGraphSteps && !check_inside) {
+            const hipError_t e = replay_steps(lat, a);
+            if (e == hipSuccess) {
+                lat->step += kGraphSteps;
+                s += kGraphSteps;
+                if (ci > 0 && lat->step % ci == 0) {
+                    double max_speed;
+                    int64_t bad;
+                    vlb_status st = vlb_check_health(lat, &max_speed, &bad);
+                    if (st != VLB_OK)
+                        return st;
+                }
+                continue;
+            }
+            // capture is not available on this stream: step by step from here on
+            (void)hipGetLastError();
+            lat->graph_broken = true;
         }
-        for (int c = 0; c < 6; ++c) {
-            a.tin_p[c] = a.tin + c * lat->g.plane;
-            a.tout_p[c] = a.tout + c * lat->g.plane;
-        }
-        for (int c = 0; c < 3; ++c)
-            a.u_p[c] = a.u + c * lat->g.plane;
+        set_planes(lat, a, lat->cur);
         a.step = static_cast<uint32_t>(lat->step);
+        a.step_dev = nullptr;
         hipEvent_t *ev = lat->timing ? &lat->events[nev * s] : nullptr;
         if (ev)
             HIPCHK(lat, hipEventRecord(ev[0], lat->stream), "event");
@@ -844,6 +969,7 @@ vlb_status vlb_step(vlb_lattice *lat, int64_t n_steps)
             HIPCHK(lat, hipEventRecord(ev[3], lat->stream), "event");
         lat->cur ^= 1;
         lat->step += 1;
+        ++s;
         if (lat->check_interval > 0 && lat->step % lat->check_interval == 0) {
             double max_speed;
             int64_t bad;

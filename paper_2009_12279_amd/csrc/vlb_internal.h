@@ -110,7 +110,9 @@ struct StepArgs {
     int32_t remap;           // XCD-aware block order (0 off, 1 ranges, 2 y-slabs)
     uint32_t slab_blocks;    // remap 2: blocks per XCD per z-plane
     int32_t stochastic;      // stochastic rounding of stored values
-    uint32_t step;           // step index (random stream of the rounding)
+    uint32_t step;           // step index (random stream of the rounding); with
+                             // step_dev, the offset added to *step_dev
+    const uint32_t *step_dev = nullptr;  // base step read on the device (graph replays)
     uint32_t seed;
 };
 
@@ -142,6 +144,8 @@ hipError_t launch_body_force(const Geom &g, const uint8_t *mask, const Particle 
 hipError_t launch_lb_step(int storage, const StepArgs &a, hipStream_t s);
 // n_steps batched steps (stream-collide, stress update, counter advance per
 // step) over every solve of the table; grid of max_blocks blocks.
+// Base step of graph replays: *step = value, or *step += value (add != 0).
+hipError_t launch_set_step(uint32_t *step, uint32_t value, int add, hipStream_t s);
 hipError_t launch_batch_step(const BatchTable *t, uint32_t max_blocks, int stochastic, int n_steps,
                              hipStream_t s);
 // tile_rows 4 or 8 selects the tiled kernel (64 x tile_rows tiles marching

@@ -742,7 +742,7 @@ __global__ __launch_bounds__(BLOCK) LB_OCCUPANCY void lb_step_kernel(StepArgs a)
     const uint32_t n = block_id(a.remap, a.slab_blocks) * BLOCK + threadIdx.x;
     if (n >= a.g.N)
         return;
-    lb_cell<S, SR, FENE>(a, n, a.step);
+    lb_cell<S, SR, FENE>(a, n, a.step_dev ? *a.step_dev + a.step : a.step);
 }
 
 // ---------------------------------------------------------------------------
@@ -929,7 +929,7 @@ __global__ __launch_bounds__(BLOCK) FV_OCCUPANCY void fv_step_kernel(StepArgs a)
     const uint32_t n = block_id(a.remap, a.slab_blocks) * BLOCK + threadIdx.x;
     if (n >= a.g.N)
         return;
-    fv_cell<SR, LAW>(a, n, a.step);
+    fv_cell<SR, LAW>(a, n, a.step_dev ? *a.step_dev + a.step : a.step);
 }
 
 // ---------------------------------------------------------------------------
@@ -1062,6 +1062,7 @@ __global__ __launch_bounds__(FV_TX * TY) FV_OCCUPANCY void fv_tile_kernel(StepAr
     }
     const int z0 = static_cast<int>(cz * zc);
     const int z1 = min(z0 + static_cast<int>(zc), nz);
+    const uint32_t step = a.step_dev ? *a.step_dev + a.step : a.step;
     // own column at z-1, z, z+1 and the ring cell at z
     float P[FV_NV], C[FV_NV], N[FV_NV], HV[FV_NV];
     fv_load(a, own_xy + wrap_coord(z0 - 1, nz) * nxy, P);
@@ -1117,7 +1118,7 @@ __global__ __launch_bounds__(FV_TX * TY) FV_OCCUPANCY void fv_tile_kernel(StepAr
             solid |= (N[9] != 0.f ? 1u : 0u) << 4;
             solid |= (P[9] != 0.f ? 1u : 0u) << 5;
             const uint32_t n = own_xy + static_cast<uint32_t>(z) * nxy;
-            fv_compute<SR, LAW>(a, g, n, x, y, z, a.step, u0, t0, un, tn, solid);
+            fv_compute<SR, LAW>(a, g, n, x, y, z, step, u0, t0, un, tn, solid);
         }
         if (more) {
 #pragma unroll
@@ -1190,6 +1191,11 @@ __global__ __launch_bounds__(BLOCK) void fv_batch_kernel(const BatchTable *__res
         return;
     // served solves are Oldroyd-B
     fv_cell<SR, LAW_OB>(a, n, step);
+}
+
+__global__ void set_step_kernel(uint32_t *step, uint32_t value, int add)
+{
+    *step = add ? *step + value : value;
 }
 
 __global__ void batch_advance_kernel(BatchTable *t)
@@ -2083,6 +2089,12 @@ hipError_t launch_fv_step(int storage, const StepArgs &a, hipStream_t s, int til
         with_law(std::true_type{});
     else
         with_law(std::false_type{});
+    return hipGetLastError();
+}
+
+hipError_t launch_set_step(uint32_t *step, uint32_t value, int add, hipStream_t s)
+{
+    hipLaunchKernelGGL(set_step_kernel, dim3(1), dim3(1), 0, s, step, value, add);
     return hipGetLastError();
 }
 
