@@ -375,6 +375,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-moving", action="store_true",
                     help="skip the moving-boundary (settling sphere) measurements")
+    ap.add_argument("--no-storage-variants", action="store_true",
+                    help="skip timing the same workload with FP16 and BF16 population storage")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (torch) so that hardware byte "
                          "counters can be scaled against a kernel of known traffic")
@@ -393,6 +395,21 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    variants = None
+    if not args.no_storage_variants:
+        # the precision pattern: the same workload with 16-bit population storage
+        variants = {}
+        for st in ("f16", "bf16"):
+            if st == args.storage:
+                continue
+            v = run_gpu(argparse.Namespace(**{**vars(args), "storage": st}))
+            variants[st] = dict(
+                ms_per_step=round(v["ms_per_step"], 4), mlups=round(v["mlups"], 1),
+                kernel_ms={k: round(x, 5) for k, x in v["kernels"].items()},
+                algorithmic_bytes_per_cell=v["alg"],
+                stream_collide_hbm_frac=round(
+                    v["alg"]["stream_collide"] * v["N"] / (v["kernels"]["stream_collide"] * 1e-3)
+                    / 8e12, 4))
     moving = None if args.no_moving else run_moving(args)
     serving = None if args.no_serving else run_serving(args)
     cpu = None
@@ -441,6 +458,7 @@ def main():
             "traffic": traffic,
         },
         "cpu_baseline": cpu,
+        "storage_variants": variants,
         "moving_particle": moving,
         "serving": serving,
     }
