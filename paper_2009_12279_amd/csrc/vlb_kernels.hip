@@ -495,12 +495,14 @@ __device__ void reflect_links(const A &a, typename Store<S>::T *fout, uint32_t n
     }
 }
 
-// Optional occupancy targets for the step kernels (waves per SIMD); the
-// default leaves register allocation to the compiler.
+// Occupancy targets of the step kernels (waves per SIMD), overridable at
+// build time for measurements.
 #ifdef VLB_LB_WAVES
-#define LB_OCCUPANCY __attribute__((amdgpu_waves_per_eu(VLB_LB_WAVES)))
+#define LB_OCCUPANCY(S) __attribute__((amdgpu_waves_per_eu(VLB_LB_WAVES)))
 #else
-#define LB_OCCUPANCY
+// 16-bit storage: at least 5 waves per SIMD (at most 96 VGPRs), measured
+// faster there; FP32 storage with FP64 arithmetic keeps the compiler's choice
+#define LB_OCCUPANCY(S) __attribute__((amdgpu_waves_per_eu((S) == ST_F32 ? 1 : 5)))
 #endif
 #ifdef VLB_FV_WAVES
 #define FV_OCCUPANCY __attribute__((amdgpu_waves_per_eu(VLB_FV_WAVES)))
@@ -737,7 +739,7 @@ __device__ __forceinline__ void lb_cell(const A &a, uint32_t n, uint32_t step)
 }
 
 template <int S, bool SR, bool FENE>
-__global__ __launch_bounds__(BLOCK) LB_OCCUPANCY void lb_step_kernel(StepArgs a)
+__global__ __launch_bounds__(BLOCK) LB_OCCUPANCY(S) void lb_step_kernel(StepArgs a)
 {
     const uint32_t n = block_id(a.remap, a.slab_blocks) * BLOCK + threadIdx.x;
     if (n >= a.g.N)
