@@ -81,6 +81,28 @@ def test_create_rejects_invalid_input_on_the_host():
     assert "non-periodic" in vlb.vlb_last_error(None) or vlb.vlb_last_error(None)
 
 
+def test_create_rejects_oversized_lattices_and_bad_walls():
+    """Planes are addressed with 32-bit byte offsets, so lattices of 2^30
+    cells or more are refused before the mask is read; non-finite wall
+    velocities are refused too.  All on the host."""
+    import ctypes
+
+    h = vlb._P()
+    d = vlb.make_dims((1024, 1024, 1024), (1, 1, 1))
+    tiny = np.zeros(1, np.uint8)  # never read: the size check comes first
+    st = vlb.lib().vlb_create(ctypes.byref(d), tiny.tobytes(), None, 0, vlb.STORAGE["f32"], None,
+                              ctypes.byref(h))
+    assert st == vlb.VLB_EINVAL
+    assert "dimensions" in vlb.vlb_last_error(None)
+    m = np.zeros((4, 4, 4), np.uint8)
+    m[:, 0, :] = 1
+    m[:, -1, :] = 2
+    _expect_status(lambda: vlb.vlb_create((4, 4, 4), m, periodic=(1, 0, 1),
+                                          wall_velocity=[[0, 0, 0], [np.nan, 0, 0]]),
+                   vlb.VLB_EINVAL)
+    assert "non-finite" in vlb.vlb_last_error(None)
+
+
 def test_create_without_device_reports_device_error():
     import torch
     if torch.cuda.device_count() > 0:

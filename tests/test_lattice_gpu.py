@@ -105,6 +105,12 @@ def test_checkpoint_keeps_wall_velocity_and_force_fields(tmp_path):
     L.set_check_interval(0)
     L.set_wall_velocity_field(wf)
     L.set_force_field(F)
+    # non-finite entries are refused and leave the fields as they were
+    for setter, bad in ((L.set_wall_velocity_field, wf.copy()), (L.set_force_field, F.copy())):
+        bad[0, 3, 4, 5] = np.inf
+        with pytest.raises(vlb.VlbError) as ei:
+            setter(bad)
+        assert ei.value.status == vlb.VLB_EINVAL
     L.step(50)
     L.save(path)
     L.step(100)
