@@ -83,7 +83,7 @@ def build_workload(storage, steps_hint=0):
     return shape, spheres, params
 
 
-def run_gpu(args):
+def run_gpu(args, law=None):
     import torch
 
     from paper_2009_12279_amd import vlb
@@ -102,6 +102,10 @@ def run_gpu(args):
     lat.set_check_interval(0)
     if args.rounding:
         lat.set_rounding(args.rounding)
+    if law == "giesekus":
+        lat.set_giesekus(0.2)
+    elif law == "fene_p":
+        lat.set_fene_p(100.0)
     fluid = int((lat.mask() == 0).sum())
 
     lat.step(args.warmup)
@@ -377,6 +381,8 @@ def main():
                     help="skip the moving-boundary (settling sphere) measurements")
     ap.add_argument("--no-storage-variants", action="store_true",
                     help="skip timing the same workload with FP16 and BF16 population storage")
+    ap.add_argument("--no-law-variants", action="store_true",
+                    help="skip timing the same workload with the Giesekus and FENE-P laws")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (torch) so that hardware byte "
                          "counters can be scaled against a kernel of known traffic")
@@ -410,6 +416,15 @@ def main():
                 stream_collide_hbm_frac=round(
                     v["alg"]["stream_collide"] * v["N"] / (v["kernels"]["stream_collide"] * 1e-3)
                     / 8e12, 4))
+    laws = None
+    if not args.no_law_variants:
+        # the other constitutive laws through the same stress update
+        laws = {}
+        for law, what in (("giesekus", "alpha = 0.2"), ("fene_p", "L^2 = 100")):
+            v = run_gpu(args, law)
+            laws[law] = dict(parameter=what, ms_per_step=round(v["ms_per_step"], 4),
+                             mlups=round(v["mlups"], 1),
+                             kernel_ms={k: round(x, 5) for k, x in v["kernels"].items()})
     moving = None if args.no_moving else run_moving(args)
     serving = None if args.no_serving else run_serving(args)
     cpu = None
@@ -459,6 +474,7 @@ def main():
         },
         "cpu_baseline": cpu,
         "storage_variants": variants,
+        "law_variants": laws,
         "moving_particle": moving,
         "serving": serving,
     }
