@@ -173,6 +173,47 @@ def test_graph_replays_give_the_same_bits(monkeypatch, storage, tile):
         np.testing.assert_array_equal(ta, tb)
 
 
+def test_largest_lattice_accelerates_uniformly():
+    """The largest lattice the 32-bit plane offsets allow (the FP32 planes
+    just under 4 GiB): 1024 x 1024 x 1000 cells, about 224 GB of state held
+    in torch tensors.  From rest under a uniform body force g every cell
+    carries u = (n + 1/2) g in step n (Guo's half force) and the stress stays
+    zero up to rounding noise; checked on every cell through the device
+    buffers."""
+    import torch
+
+    shape = (1024, 1024, 1000)
+    N = shape[0] * shape[1] * shape[2]
+    sizes = vlb.vlb_buffer_sizes(shape)
+    free, _ = torch.cuda.mem_get_info()
+    if sum(sizes) + (8 << 30) > free:
+        pytest.skip(f"needs {sum(sizes) / 2**30:.0f} GiB of free device memory")
+    log(f"[lattice] largest lattice {shape}, {sum(sizes) / 2**30:.0f} GiB, 3 steps")
+    g = 1e-5
+    L = vlb.Lattice(shape, np.zeros(shape[::-1], np.uint8), (1, 1, 1), torch_buffers=True)
+    L.set_params(eta=1 / 3, beta=0.5, lambda_p=100.0, magic=3 / 16, body_force=(g, 0, 0))
+    L.set_check_interval(0)
+    L.init_equilibrium()
+    L.step(3)
+    L.sync()
+    P = sizes[5] // 12
+    u = L._buffers[5].view(torch.float32)
+    ux = u[:N]
+    assert float((ux - 2.5 * g).abs().max()) < 1e-5 * 2.5 * g
+    # the other components and the stress only carry the rounding noise of
+    # the stochastically rounded populations: half a unit in the last place
+    # of deviations of a few 1e-6, summed over the directions, is ~1e-12
+    assert float(u[P:P + N].abs().max()) < 1e-6 * g
+    assert float(u[2 * P:2 * P + N].abs().max()) < 1e-6 * g
+    for b in (3, 4):
+        t = L._buffers[b].view(torch.float32)
+        for c in range(6):
+            assert float(t[c * P:c * P + N].abs().max()) < 1e-10
+    L.close()
+    del u, ux
+    torch.cuda.empty_cache()
+
+
 def test_load_rejects_a_file_that_is_not_a_checkpoint(tmp_path):
     p = tmp_path / "junk.vlb"
     p.write_bytes(b"not a checkpoint" * 8)
