@@ -832,6 +832,7 @@ hipError_t replay_steps(vlb_lattice *lat, const vlb::StepArgs &base)
         return e;
     vlb::StepArgs key = base;
     set_planes(lat, key, par);
+    key.step = 0;
     key.step_dev = lat->d_step;
     if (!lat->gexec[par] || std::memcmp(&key, &lat->gkey[par], sizeof key) != 0 ||
         lat->gshape[par][0] != tile_rows || lat->gshape[par][1] != static_cast<int>(z_chunk)) {
