@@ -103,7 +103,7 @@ struct vlb_lattice {
     uint32_t *d_step = nullptr;   // base step the replayed kernels add their offset to
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     vlb::StepArgs gkey[2];
-    int gshape[2][2] = {{0, 0}, {0, 0}};
+    int gshape[2][3] = {{0, 0, 0}, {0, 0, 0}};  // tile rows, z chunk, path flags
     bool graph_broken = false;    // capture failed once: keep launching step by step
     Particle *d_parts = nullptr;
     double *d_partials = nullptr;
@@ -789,10 +789,49 @@ void set_planes(const vlb_lattice *lat, vlb::StepArgs &a, int cur)
         a.u_p[c] = a.u + c * lat->g.plane;
 }
 
+// The kernels of one step, in order: stream-collide, stress update, and for
+// moving particles their forces, rigid-body update, conversion and (under
+// the counter-force) the next step's body force.  `ev`, if given, receives
+// events before stream-collide, before the stress update, before the
+// particle path and after it.
+hipError_t launch_step(vlb_lattice *lat, const vlb::StepArgs &a, bool counter, int tile_rows,
+                       uint32_t z_chunk, hipEvent_t *ev)
+{
+    hipStream_t st = lat->stream;
+    hipError_t e = hipSuccess;
+    auto rec = [&](int k) {
+        if (ev && e == hipSuccess)
+            e = hipEventRecord(ev[k], st);
+    };
+    rec(0);
+    if (e == hipSuccess)
+        e = vlb::launch_lb_step(lat->storage, a, st);
+    rec(1);
+    if (e == hipSuccess && lat->polymer)
+        e = vlb::launch_fv_step(lat->storage, a, st, tile_rows, z_chunk);
+    rec(2);
+    if (e == hipSuccess && lat->any_movable) {
+        const int np = static_cast<int>(lat->parts_h.size());
+        e = vlb::launch_particle_forces(lat->storage, lat->g, lat->d_mask, a.fout, a.tin,
+                                        lat->polymer, lat->inv_scale, lat->d_parts, np,
+                                        lat->d_pforce, st, lat->stress_map());
+        if (e == hipSuccess)
+            e = vlb::launch_particle_update(lat->g, lat->d_parts, np, st);
+        if (e == hipSuccess)
+            e = vlb::launch_conversion(lat->storage, lat->g, a.b, lat->d_mask, a.fout, a.tout,
+                                       lat->scale, lat->inv_scale, lat->d_counters, st);
+        if (e == hipSuccess && counter)
+            e = vlb::launch_body_force(lat->g, lat->d_mask, lat->d_parts, np,
+                                       lat->params.body_force, lat->d_count, lat->d_g3, st);
+    }
+    rec(3);
+    return e;
+}
+
 // Record the kGraphSteps steps that start at parity `par` into a graph
 // executable; kernels take their step index as *d_step + offset.
-hipError_t capture_steps(vlb_lattice *lat, const vlb::StepArgs &base, int par, int tile_rows,
-                         uint32_t z_chunk, hipGraphExec_t *out)
+hipError_t capture_steps(vlb_lattice *lat, const vlb::StepArgs &base, int par, bool counter,
+                         int tile_rows, uint32_t z_chunk, hipGraphExec_t *out)
 {
     hipStream_t st = lat->stream;
     hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
@@ -804,9 +843,7 @@ hipError_t capture_steps(vlb_lattice *lat, const vlb::StepArgs &base, int par, i
         set_planes(lat, a, (par + k) & 1);
         a.step = static_cast<uint32_t>(k);
         a.step_dev = lat->d_step;
-        le = vlb::launch_lb_step(lat->storage, a, st);
-        if (le == hipSuccess && lat->polymer)
-            le = vlb::launch_fv_step(lat->storage, a, st, tile_rows, z_chunk);
+        le = launch_step(lat, a, counter, tile_rows, z_chunk, nullptr);
     }
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(st, &graph);
@@ -822,7 +859,7 @@ hipError_t capture_steps(vlb_lattice *lat, const vlb::StepArgs &base, int par, i
 // One replay of kGraphSteps steps from the lattice's current step and
 // parity; the graph is captured again when the step arguments or the launch
 // shape differ from those it was captured with.
-hipError_t replay_steps(vlb_lattice *lat, const vlb::StepArgs &base)
+hipError_t replay_steps(vlb_lattice *lat, const vlb::StepArgs &base, bool counter)
 {
     const int par = lat->cur;
     const int tile_rows = fv_tile_rows();
@@ -834,19 +871,23 @@ hipError_t replay_steps(vlb_lattice *lat, const vlb::StepArgs &base)
     set_planes(lat, key, par);
     key.step = 0;
     key.step_dev = lat->d_step;
+    const int flags = (lat->any_movable ? 1 : 0) | (counter ? 2 : 0);
     if (!lat->gexec[par] || std::memcmp(&key, &lat->gkey[par], sizeof key) != 0 ||
-        lat->gshape[par][0] != tile_rows || lat->gshape[par][1] != static_cast<int>(z_chunk)) {
+        lat->gshape[par][0] != tile_rows || lat->gshape[par][1] != static_cast<int>(z_chunk) ||
+        lat->gshape[par][2] != flags) {
         if (lat->gexec[par]) {
             (void)hipGraphExecDestroy(lat->gexec[par]);
             lat->gexec[par] = nullptr;
         }
-        if ((e = capture_steps(lat, base, par, tile_rows, z_chunk, &lat->gexec[par])) != hipSuccess) {
+        if ((e = capture_steps(lat, base, par, counter, tile_rows, z_chunk, &lat->gexec[par])) !=
+            hipSuccess) {
             lat->gexec[par] = nullptr;
             return e;
         }
         std::memcpy(&lat->gkey[par], &key, sizeof key);
         lat->gshape[par][0] = tile_rows;
         lat->gshape[par][1] = static_cast<int>(z_chunk);
+        lat->gshape[par][2] = flags;
     }
     if ((e = vlb::launch_set_step(lat->d_step, static_cast<uint32_t>(lat->step), 0,
                                   lat->stream)) != hipSuccess)
@@ -906,20 +947,22 @@ vlb_status vlb_step(vlb_lattice *lat, int64_t n_steps)
             lat->events.push_back(e);
         }
     }
-    // Lattices without moving particles replay their steps from a graph, in
-    // chunks of kGraphSteps that no health check falls inside; the same
-    // kernels with the same arguments run, so the results are the same bits.
-    const bool graph_ok = !lat->timing && !lat->any_movable && !counter && !lat->graph_broken &&
-                          graphs_enabled();
+    // Steps replay from a graph in chunks of kGraphSteps that no health check
+    // falls inside; the same kernels with the same arguments run (the particle
+    // path is driven from device memory alone), so the results are the same
+    // bits.
+    const bool graph_ok = !lat->timing && !lat->graph_broken && graphs_enabled();
     int64_t s = 0;
     while (s < n_steps) {
         const int64_t ci = lat->check_interval;
         const bool check_inside = ci > 0 && (lat->step / ci + 1) * ci < lat->step + kGraphSteps;
         if (graph_ok && n_steps - s >= kGraphSteps && !check_inside) {
-            const hipError_t e = replay_steps(lat, a);
+            const hipError_t e = replay_steps(lat, a, counter);
             if (e == hipSuccess) {
                 lat->step += kGraphSteps;
                 s += kGraphSteps;
+                if (lat->any_movable)
+                    lat->mask_h_valid = false;
                 if (ci > 0 && lat->step % ci == 0) {
                     double max_speed;
                     int64_t bad;
@@ -937,37 +980,9 @@ vlb_status vlb_step(vlb_lattice *lat, int64_t n_steps)
         a.step = static_cast<uint32_t>(lat->step);
         a.step_dev = nullptr;
         hipEvent_t *ev = lat->timing ? &lat->events[nev * s] : nullptr;
-        if (ev)
-            HIPCHK(lat, hipEventRecord(ev[0], lat->stream), "event");
-        HIPCHK(lat, vlb::launch_lb_step(lat->storage, a, lat->stream), "stream-collide launch");
-        if (ev)
-            HIPCHK(lat, hipEventRecord(ev[1], lat->stream), "event");
-        if (lat->polymer)
-            HIPCHK(lat, vlb::launch_fv_step(lat->storage, a, lat->stream, fv_tile_rows(), fv_z_chunk()),
-                   "stress update launch");
-        if (ev)
-            HIPCHK(lat, hipEventRecord(ev[2], lat->stream), "event");
-        if (lat->any_movable) {
-            const int np = static_cast<int>(lat->parts_h.size());
-            HIPCHK(lat, vlb::launch_particle_forces(lat->storage, lat->g, lat->d_mask, a.fout, a.tin,
-                                                    lat->polymer, lat->inv_scale, lat->d_parts, np,
-                                                    lat->d_pforce, lat->stream, lat->stress_map()),
-                   "particle forces");
-            HIPCHK(lat, vlb::launch_particle_update(lat->g, lat->d_parts, np, lat->stream),
-                   "particle update");
-            HIPCHK(lat, vlb::launch_conversion(lat->storage, lat->g, a.b, lat->d_mask, a.fout,
-                                               a.tout, lat->scale, lat->inv_scale,
-                                               lat->d_counters, lat->stream),
-                   "conversion");
-            if (counter)
-                HIPCHK(lat, vlb::launch_body_force(lat->g, lat->d_mask, lat->d_parts, n_parts,
-                                                   lat->params.body_force, lat->d_count,
-                                                   lat->d_g3, lat->stream),
-                       "counter-force");
+        HIPCHK(lat, launch_step(lat, a, counter, fv_tile_rows(), fv_z_chunk(), ev), "step launch");
+        if (lat->any_movable)
             lat->mask_h_valid = false;
-        }
-        if (ev)
-            HIPCHK(lat, hipEventRecord(ev[3], lat->stream), "event");
         lat->cur ^= 1;
         lat->step += 1;
         ++s;

@@ -140,31 +140,43 @@ def test_checkpoint_keeps_wall_velocity_and_force_fields(tmp_path):
         np.testing.assert_array_equal(a, b)
 
 
-@pytest.mark.parametrize("storage,tile", [("f32", "4"), ("f32", "-4"), ("f16", "4")])
-def test_graph_replays_give_the_same_bits(monkeypatch, storage, tile):
+@pytest.mark.parametrize("storage,tile,moving", [("f32", "4", False), ("f32", "-4", False),
+                                                 ("f16", "4", False), ("f32", "4", True)])
+def test_graph_replays_give_the_same_bits(monkeypatch, storage, tile, moving):
     """Steps replayed from captured graphs (chunks of 32) against the same
     steps launched one by one: bitwise equal after every call, across health
     checks inside and at the end of chunks, a parameter change (a new
-    capture) and both starting buffer parities."""
+    capture) and both starting buffer parities; with a fixed sphere, or with
+    a moving sphere under the counter-force (the particle path in the
+    graph)."""
     shape = (24, 20, 16)
     mask = inputs.channel_mask(shape, wall_axes=(1,), top_id=2)
     monkeypatch.setenv("VLB_FV_TILE", tile)
     runs = []
     for graph in ("0", "1"):
         monkeypatch.setenv("VLB_GRAPH", graph)
-        log(f"[lattice] graph replays {graph} storage={storage} tile={tile}")
+        log(f"[lattice] graph replays {graph} storage={storage} tile={tile} moving={moving}")
         L = vlb.Lattice(shape, mask, (1, 0, 1), [[0, 0, 0], [1e-3, 0, 0]], storage=storage)
         L.set_params(eta=1 / 3, beta=0.5, lambda_p=50.0, magic=3 / 16, body_force=(1e-6, 0, 0))
-        L.add_sphere(center=(11.5, 9.7, 8.2), radius=3.0)
+        if moving:
+            L.add_sphere(center=(11.5, 9.7, 8.2), radius=3.0, density_ratio=3.0, movable=True,
+                         f_ext=(4e-3, 0.0, -2e-3), t_ext=(0.0, 0.0, 1e-3))
+            L.set_counter_force(True)
+        else:
+            L.add_sphere(center=(11.5, 9.7, 8.2), radius=3.0)
         L.set_check_interval(50)
         L.init_equilibrium()
         out = []
         for n in (100, 37, 64):
             L.step(n)
             out.append((L.populations(), L.stress()))
+            if moving:
+                p = L.particle(0)
+                out.append((p["pos"], p["vel"]))
         L.set_params(eta=1 / 3, beta=0.5, lambda_p=80.0, magic=3 / 16, body_force=(2e-6, 0, 0))
         L.step(65)
         out.append((L.populations(), L.stress()))
+        out.append((L.mask(), L.mask()))
         assert L.step_count == 266
         runs.append(out)
         L.close()
