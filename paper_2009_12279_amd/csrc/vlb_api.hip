@@ -816,8 +816,6 @@ hipError_t launch_step(vlb_lattice *lat, const vlb::StepArgs &a, bool counter, i
                                         lat->polymer, lat->inv_scale, lat->d_parts, np,
                                         lat->d_pforce, st, lat->stress_map());
         if (e == hipSuccess)
-            e = vlb::launch_particle_update(lat->g, lat->d_parts, np, st);
-        if (e == hipSuccess)
             e = vlb::launch_conversion(lat->storage, lat->g, a.b, lat->d_mask, a.fout, a.tout,
                                        lat->scale, lat->inv_scale, lat->d_counters, st);
         if (e == hipSuccess && counter)
@@ -1156,8 +1154,6 @@ vlb_status vlb_read_particle(vlb_lattice *lat, int32_t id, double pos[3], double
                                                 lat->polymer, lat->inv_scale, lat->d_parts, np,
                                                 lat->d_pforce, lat->stream, lat->stress_map()),
                "particle forces");
-        HIPCHK(lat, vlb::launch_particle_update(lat->g, lat->d_parts, np, lat->stream),
-               "particle totals");
     }
     std::vector<Particle> cur;
     vlb_status st = download_particles(lat, cur);

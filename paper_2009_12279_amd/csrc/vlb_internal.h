@@ -177,7 +177,8 @@ hipError_t launch_sums(int storage, const Geom &g, const uint8_t *mask, const vo
                        float inv_scale, double *partials, double *out, hipStream_t s);
 // Per-particle momentum exchange + polymer traction over each particle's
 // bounding box (PF_BLOCKS blocks per particle, block sums into `partials`,
-// MAX_PARTICLES x PF_BLOCKS x 12 doubles, then a fixed-order FP64 sum).
+// MAX_PARTICLES x PF_BLOCKS x 12 doubles), then per particle the fixed-order
+// FP64 sum, the totals and the symplectic Euler update of movable particles.
 constexpr int PF_BLOCKS = 32;
 hipError_t launch_particle_forces(int storage, const Geom &g, const uint8_t *mask, const void *f,
                                   const float *tau_n, int polymer, float inv_scale,
@@ -187,8 +188,6 @@ hipError_t launch_particle_forces(int storage, const Geom &g, const uint8_t *mas
 hipError_t launch_wall_force(int storage, const Geom &g, const uint8_t *mask, const void *f,
                              const float *tau_n, int polymer, float inv_scale, double *partials,
                              double *out, hipStream_t s, const StressMap &sm = StressMap{});
-// Totals, symplectic Euler for movable particles.
-hipError_t launch_particle_update(const Geom &g, Particle *parts, int n_parts, hipStream_t s);
 // Fluid/solid conversion around every movable particle.
 hipError_t launch_conversion(int storage, const Geom &g, const Bound &b, uint8_t *mask, void *f,
                              float *tau, float scale, float inv_scale, int32_t *counters,

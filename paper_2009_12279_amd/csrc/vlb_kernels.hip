@@ -1563,7 +1563,7 @@ __device__ void link_forces(const Geom &g, const uint8_t *mask, const void *fv, 
 
 // Obstacle forces: PF_BLOCKS blocks per particle (blockIdx.y) share the
 // particle's bounding box; each writes its block sum of the 12 components,
-// and particle_forces_reduce_kernel adds the blocks in a fixed order.
+// and particle_reduce_update_kernel adds the blocks in a fixed order.
 template <int S>
 __global__ __launch_bounds__(BLOCK) void particle_forces_kernel(Geom g, const uint8_t *mask,
                                                                 const void *fv, const float *tau,
@@ -1594,7 +1594,11 @@ __global__ __launch_bounds__(BLOCK) void particle_forces_kernel(Geom g, const ui
     }
 }
 
-__global__ void particle_forces_reduce_kernel(Particle *parts, const double *partials, int n_parts)
+// Per particle: the fixed-order sum of its PF_BLOCKS block sums, then the
+// totals and, for a movable particle, the symplectic Euler update
+// (Section 3.4).  One thread per particle.
+__global__ void particle_reduce_update_kernel(Geom g, Particle *parts, const double *partials,
+                                              int n_parts)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n_parts)
@@ -1603,12 +1607,32 @@ __global__ void particle_forces_reduce_kernel(Particle *parts, const double *par
     for (int b = 0; b < PF_BLOCKS; ++b)
         for (int k = 0; k < 12; ++k)
             r[k] += partials[(static_cast<size_t>(p) * PF_BLOCKS + b) * 12 + k];
-    Particle &Q_ = parts[p];
+    Particle &P = parts[p];
     for (int a = 0; a < 3; ++a) {
-        Q_.fmex[a] = r[a];
-        Q_.tmex[a] = r[3 + a];
-        Q_.ftau[a] = r[6 + a];
-        Q_.ttau[a] = r[9 + a];
+        P.fmex[a] = r[a];
+        P.tmex[a] = r[3 + a];
+        P.ftau[a] = r[6 + a];
+        P.ttau[a] = r[9 + a];
+    }
+    for (int a = 0; a < 3; ++a) {
+        P.ftot[a] = P.fmex[a] + P.ftau[a] + P.fconv[a] + P.fext[a];
+        P.ttot[a] = P.tmex[a] + P.ttau[a] + P.tconv[a] + P.text[a];
+        P.fconv[a] = 0.0;
+        P.tconv[a] = 0.0;
+    }
+    if (!P.movable)
+        return;
+    const int len[3] = {g.nx, g.ny, g.nz};
+    for (int a = 0; a < 3; ++a) {
+        P.v[a] += P.ftot[a] / P.mass;
+        P.w[a] += P.ttot[a] / P.inertia;
+    }
+    for (int a = 0; a < 3; ++a) {
+        P.R[a] += P.v[a];
+        if (g.per[a]) {
+            const double L = static_cast<double>(len[a]);
+            P.R[a] -= L * floor(P.R[a] / L);
+        }
     }
 }
 
@@ -1637,34 +1661,6 @@ __global__ __launch_bounds__(BLOCK) void wall_force_kernel(Geom g, const uint8_t
 
 // Section 3.4: totals and symplectic Euler (velocity first, then position
 // with the new velocity).
-__global__ void particle_update_kernel(Geom g, Particle *parts, int n_parts)
-{
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n_parts)
-        return;
-    Particle &P = parts[p];
-    for (int a = 0; a < 3; ++a) {
-        P.ftot[a] = P.fmex[a] + P.ftau[a] + P.fconv[a] + P.fext[a];
-        P.ttot[a] = P.tmex[a] + P.ttau[a] + P.tconv[a] + P.text[a];
-        P.fconv[a] = 0.0;
-        P.tconv[a] = 0.0;
-    }
-    if (!P.movable)
-        return;
-    const int len[3] = {g.nx, g.ny, g.nz};
-    for (int a = 0; a < 3; ++a) {
-        P.v[a] += P.ftot[a] / P.mass;
-        P.w[a] += P.ttot[a] / P.inertia;
-    }
-    for (int a = 0; a < 3; ++a) {
-        P.R[a] += P.v[a];
-        if (g.per[a]) {
-            const double L = static_cast<double>(len[a]);
-            P.R[a] -= L * floor(P.R[a] / L);
-        }
-    }
-}
-
 // ---------------------------------------------------------------------------
 // Fluid/solid conversion around movable particles (Section 3.4), one block.
 // The new owner of a cell is a pure function of its old mask byte and the
@@ -2213,8 +2209,8 @@ hipError_t launch_particle_forces(int storage, const Geom &g, const uint8_t *mas
     });
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(particle_forces_reduce_kernel, dim3((n_parts + 63) / 64), dim3(64), 0, s,
-                       parts, partials, n_parts);
+    hipLaunchKernelGGL(particle_reduce_update_kernel, dim3((n_parts + 63) / 64), dim3(64), 0, s,
+                       g, parts, partials, n_parts);
     return hipGetLastError();
 }
 
@@ -2246,15 +2242,6 @@ hipError_t launch_body_force(const Geom &g, const uint8_t *mask, const Particle 
         return e;
     hipLaunchKernelGGL(body_force_kernel, dim3(1), dim3(1), 0, s, parts, n_parts, body_force[0],
                        body_force[1], body_force[2], count, g_out);
-    return hipGetLastError();
-}
-
-hipError_t launch_particle_update(const Geom &g, Particle *parts, int n_parts, hipStream_t s)
-{
-    if (n_parts <= 0)
-        return hipSuccess;
-    hipLaunchKernelGGL(particle_update_kernel, dim3((n_parts + 63) / 64), dim3(64), 0, s, g, parts,
-                       n_parts);
     return hipGetLastError();
 }
 
