@@ -155,14 +155,18 @@ vlb_status vlb_add_sphere(vlb_lattice *lat, const double center[3], double radiu
                           double density_ratio, int32_t movable, const double f_ext[3],
                           const double t_ext[3], int32_t *id_out);
 
-/* Advance n_steps time steps (asynchronous). */
+/* Advance n_steps time steps (asynchronous).  Runs of 32 steps and more are
+ * replayed from captured HIP graphs in chunks of 32, with the same kernels
+ * and arguments, so the results are the same bits as step-by-step launches;
+ * VLB_GRAPH=0 in the environment turns the replays off. */
 vlb_status vlb_step(vlb_lattice *lat, int64_t n_steps);
 vlb_status vlb_sync(vlb_lattice *lat);
 int64_t vlb_step_count(const vlb_lattice *lat);
 
 /* Reads of the current state (FP64 host arrays of N, 3*N, 6*N, 19*N values;
  * solid cells read 0).  Density rho = sum f; velocity u = (sum f c + F/2)/rho
- * with F = g + polymer force of the current stress (Section 3.1). */
+ * with F = g + the per-cell force field, if set, + the polymer force of the
+ * current stress (Section 3.1). */
 vlb_status vlb_read_density(vlb_lattice *lat, double *rho);
 vlb_status vlb_read_velocity(vlb_lattice *lat, double *u);
 vlb_status vlb_read_stress(vlb_lattice *lat, double *tau);
@@ -190,8 +194,9 @@ vlb_status vlb_check_health(vlb_lattice *lat, double *max_speed, int64_t *non_fi
 vlb_status vlb_set_check_interval(vlb_lattice *lat, int64_t steps);
 
 /* Checkpoint: parameters, mask, walls, particles, step count, rounding mode
- * and seed, and the state in its storage precision, so that a restarted run
- * continues bit for bit.  vlb_load creates a new lattice (VLB_EINVAL for a
+ * and seed, the constitutive law, extrapolation order, counter-force, the
+ * wall-velocity and force fields, and the state in its storage precision,
+ * so that a restarted run continues bit for bit.  vlb_load creates a new lattice (VLB_EINVAL for a
  * file that is not a checkpoint of this format). */
 vlb_status vlb_save(vlb_lattice *lat, const char *path);
 vlb_status vlb_load(const char *path, void *stream, vlb_lattice **out);
