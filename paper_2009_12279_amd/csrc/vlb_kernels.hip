@@ -334,6 +334,33 @@ __device__ double block_sum(double v, double *sh)
     return r;
 }
 
+// The same for K values at once with a single barrier: each value takes the
+// shuffle tree and the fixed wave order of block_sum, so the sums are the
+// same bits.  sh holds K * NT / 64 doubles; the results are valid in
+// thread 0.
+template <int NT, int K>
+__device__ void block_sums(double (&v)[K], double *sh)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1)
+            v[k] += __shfl_down(v[k], off, 64);
+        if (lane == 0)
+            sh[k * (NT / 64) + wid] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            double r = 0.0;
+            for (int w = 0; w < NT / 64; ++w)
+                r += sh[k * (NT / 64) + w];
+            v[k] = r;
+        }
+}
+
 template <int NT>
 __device__ double block_max(double v, double *sh)
 {
@@ -1571,7 +1598,7 @@ __global__ __launch_bounds__(BLOCK) void particle_forces_kernel(Geom g, const ui
                                                                 const Particle *parts,
                                                                 double *partials, StressMap sm)
 {
-    __shared__ double sh[BLOCK / 64];
+    __shared__ double sh[12 * (BLOCK / 64)];
     const int p = blockIdx.y;
     const Particle &P = parts[p];
     const uint8_t me = static_cast<uint8_t>(PART0 + p);
@@ -1587,26 +1614,38 @@ __global__ __launch_bounds__(BLOCK) void particle_forces_kernel(Geom g, const ui
         link_forces<S>(g, mask, fv, tau, polymer, inv_scale, x, y, z, &P,
                        [me](uint8_t m) { return m == me; }, acc, sm);
     }
-    for (int k = 0; k < 12; ++k) {
-        const double r = block_sum<BLOCK>(acc[k], sh);
-        if (threadIdx.x == 0)
-            partials[(static_cast<size_t>(p) * PF_BLOCKS + blockIdx.x) * 12 + k] = r;
-    }
+    block_sums<BLOCK, 12>(acc, sh);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 12; ++k)
+            partials[(static_cast<size_t>(p) * PF_BLOCKS + blockIdx.x) * 12 + k] = acc[k];
 }
 
-// Per particle: the fixed-order sum of its PF_BLOCKS block sums, then the
-// totals and, for a movable particle, the symplectic Euler update
-// (Section 3.4).  One thread per particle.
-__global__ void particle_reduce_update_kernel(Geom g, Particle *parts, const double *partials,
-                                              int n_parts)
+// Per particle (one 64-thread block each): the fixed-order sum of its
+// PF_BLOCKS block sums, one component per thread with every load in flight
+// at once, then the totals and, for a movable particle, the symplectic Euler
+// update (Section 3.4) by thread 0.
+__global__ __launch_bounds__(64) void particle_reduce_update_kernel(Geom g, Particle *parts,
+                                                                    const double *partials)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n_parts)
+    __shared__ double rs[12];
+    const int p = blockIdx.x, t = threadIdx.x;
+    if (t < 12) {
+        double v[PF_BLOCKS];
+#pragma unroll
+        for (int b = 0; b < PF_BLOCKS; ++b)
+            v[b] = partials[(static_cast<size_t>(p) * PF_BLOCKS + b) * 12 + t];
+        double acc = 0.0;
+#pragma unroll
+        for (int b = 0; b < PF_BLOCKS; ++b)
+            acc += v[b];
+        rs[t] = acc;
+    }
+    __syncthreads();
+    if (t != 0)
         return;
-    double r[12] = {0};
-    for (int b = 0; b < PF_BLOCKS; ++b)
-        for (int k = 0; k < 12; ++k)
-            r[k] += partials[(static_cast<size_t>(p) * PF_BLOCKS + b) * 12 + k];
+    double r[12];
+    for (int k = 0; k < 12; ++k)
+        r[k] = rs[k];
     Particle &P = parts[p];
     for (int a = 0; a < 3; ++a) {
         P.fmex[a] = r[a];
@@ -2209,8 +2248,8 @@ hipError_t launch_particle_forces(int storage, const Geom &g, const uint8_t *mas
     });
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(particle_reduce_update_kernel, dim3((n_parts + 63) / 64), dim3(64), 0, s,
-                       g, parts, partials, n_parts);
+    hipLaunchKernelGGL(particle_reduce_update_kernel, dim3(n_parts), dim3(64), 0, s, g, parts,
+                       partials);
     return hipGetLastError();
 }
 
