@@ -986,11 +986,21 @@ __global__ __launch_bounds__(BLOCK) void fluid_count_kernel(Geom g, const uint8_
     if (blockIdx.x == 0 && threadIdx.x == 0)
         for (uint32_t n = nvec * 16u; n < g.N; ++n)
             c += mask[n] == 0 ? 1u : 0u;
-    // integer sums: the result does not depend on the order
+    // integer sums: the result does not depend on the order.  One atomic
+    // per block: per-wave atomics on the one counter serialise in L2.
+    __shared__ uint32_t ws[BLOCK / 64];
     for (int off = 32; off > 0; off >>= 1)
         c += __shfl_down(c, off, 64);
-    if ((threadIdx.x & 63) == 0 && c)
-        atomicAdd(count, c);
+    if ((threadIdx.x & 63) == 0)
+        ws[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int w = 0; w < BLOCK / 64; ++w)
+            t += ws[w];
+        if (t)
+            atomicAdd(count, t);
+    }
 }
 
 __global__ void body_force_kernel(const Particle *parts, int n_parts, double g0, double g1,
@@ -2274,7 +2284,7 @@ hipError_t launch_body_force(const Geom &g, const uint8_t *mask, const Particle 
                              double *g_out, hipStream_t s)
 {
     const uint32_t vec_blocks = blocks_for(g.N / 16u + 1u);
-    const uint32_t blocks = vec_blocks < 1024u ? vec_blocks : 1024u;
+    const uint32_t blocks = vec_blocks < 512u ? vec_blocks : 512u;
     hipLaunchKernelGGL(fluid_count_kernel, dim3(blocks), dim3(BLOCK), 0, s, g, mask, count);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
