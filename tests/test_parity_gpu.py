@@ -6,8 +6,8 @@ its name before touching the GPU."""
 import numpy as np
 import pytest
 
-from paper_2009_12279_amd import inputs
-from parity import Case, build, compare, log
+from paper_2009_12279_amd import inputs, vlb
+from parity import Case, build, compare, log, public_from_oracle_perm
 
 pytestmark = pytest.mark.gpu
 
@@ -324,3 +324,59 @@ def test_extrapolation_random_lattice(order, steps):
                                atol=1e-5 * np.abs(po["force"]).max())
     wo = o.wall_force()
     np.testing.assert_allclose(g.wall_force(), wo, rtol=0, atol=1e-5 * np.abs(wo).max() + 1e-12)
+
+
+def test_degenerate_lattices():
+    """Degenerate cases against the oracle: a single periodic fluid cell
+    (every neighbour is the cell itself; under a body force it accelerates
+    as u = (n + 1/2) g), a single fluid cell enclosed by walls (every link
+    bounces back), an all-solid box, and zero steps."""
+    g_x = 1e-5
+    one = Case("one-cell", (1, 1, 1), np.zeros((1, 1, 1), np.uint8), (1, 1, 1), None,
+               dict(eta=1 / 3, beta=0.5, lambda_p=20.0, magic=3 / 16, body_force=(g_x, 0, 0)))
+    log("[parity] single periodic cell, 20 steps")
+    g, o = build(one)
+    g.step(20)
+    o.step(20)
+    # the readout uses the current populations: 20 steps of forcing plus half a step
+    np.testing.assert_allclose(g.velocity()[0].ravel(), [20.5 * g_x], rtol=1e-6)
+    e = compare(g, o, one, what=("u", "tau", "rho"))
+    assert e["u"][0] < 1e-5 and e["tau"][1] < 1e-5, e
+    g.close()
+    o.close()
+
+    mask = np.ones((3, 3, 3), np.uint8)
+    mask[1, 1, 1] = 0
+    enclosed = Case("enclosed", (3, 3, 3), mask, (0, 0, 0), [[0, 0, 0]],
+                    dict(eta=1 / 3, beta=0.5, lambda_p=20.0, magic=3 / 16, body_force=(g_x, 0, 0)),
+                    u0=None)
+    log("[parity] single enclosed cell, 21 and 22 steps")
+    g, o = build(enclosed)
+    # bounce-back on every link flips the momentum each step: j alternates
+    # between -g and 0, so the deviations from the weights alternate between
+    # O(g) and O(g^2); both are held to 1e-5 of g in absolute terms, the
+    # scale the FP32-stored populations resolve
+    for n in (21, 1):
+        g.step(n)
+        o.step(n)
+        e = compare(g, o, enclosed, what=("u",))
+        log(f"[parity]   step {g.step_count}: errors {e}")
+        assert e["u"][0] < 1e-5, e
+        df = np.abs(g.populations()[:, 1, 1, 1] - o.populations()[public_from_oracle_perm(), 1, 1, 1])
+        assert df.max() < 1e-5 * g_x, df.max()
+        assert abs(g.density()[1, 1, 1] - o.density()[1, 1, 1]) < 1e-5 * g_x
+    g.close()
+    o.close()
+
+    log("[parity] all-solid box and zero steps")
+    solid = vlb.Lattice((4, 4, 4), np.ones((4, 4, 4), np.uint8), (0, 0, 0))
+    solid.set_params(eta=1 / 3, beta=0.5, lambda_p=20.0, magic=3 / 16, body_force=(g_x, 0, 0))
+    solid.set_check_interval(1)
+    solid.step(0)
+    assert solid.step_count == 0
+    solid.step(5)
+    assert solid.step_count == 5
+    assert not np.any(solid.velocity()) and not np.any(solid.stress())
+    mass, mom = solid.sums()
+    assert mass == 0.0 and not np.any(mom)
+    solid.close()
