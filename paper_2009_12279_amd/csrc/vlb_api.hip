@@ -1355,7 +1355,8 @@ vlb_status vlb_load(const char *path, void *stream, vlb_lattice **out)
         return fail(nullptr, VLB_EINVAL, std::string("vlb_load: cannot open ") + path);
     FileHeader h{};
     if (std::fread(&h, sizeof h, 1, fp) != 1 || h.magic != kMagic || h.n_parts < 0 ||
-        h.n_parts > vlb::MAX_PARTICLES) {
+        h.n_parts > vlb::MAX_PARTICLES || h.storage < VLB_STORE_F32 || h.storage > VLB_STORE_BF16 ||
+        h.scale != default_scale(h.storage)) {
         std::fclose(fp);
         return fail(nullptr, VLB_EINVAL, "vlb_load: not a lattice checkpoint");
     }

@@ -88,7 +88,8 @@ __device__ __forceinline__ void st_stream(T *p, T v)
 // storage codecs: deviation h = s * (f - w) in FP32, FP16 or BF16.
 // st() rounds to nearest; st_sr() rounds stochastically with the 16-bit
 // uniform r16, which removes the systematic bias round-to-nearest leaves in
-// a slowly relaxing steady state.
+// a slowly relaxing steady state.  The scale s is 1 for FP32 and BF16 (the
+// library never sets another), so their codecs skip the multiplications.
 
 template <int S>
 struct Store;
@@ -97,22 +98,22 @@ template <>
 struct Store<ST_F32> {
     using T = float;
     using R = double;  // register type of the per-cell arithmetic
-    static __device__ __forceinline__ float ld(const T *p, uint64_t i, float inv)
+    static __device__ __forceinline__ float ld(const T *p, uint64_t i, float)
     {
-        return p[i] * inv;
+        return p[i];
     }
     template <class V>
-    static __device__ __forceinline__ void st(T *p, uint64_t i, V v, float s)
+    static __device__ __forceinline__ void st(T *p, uint64_t i, V v, float)
     {
-        st_stream(p + i, static_cast<float>(v * s));
+        st_stream(p + i, static_cast<float>(v));
     }
     template <class V>
-    static __device__ __forceinline__ void st_sr(T *p, uint64_t i, V v, float s, int32_t r16)
+    static __device__ __forceinline__ void st_sr(T *p, uint64_t i, V v, float, int32_t r16)
     {
         if constexpr (sizeof(V) == 8)
-            st_stream(p + i, sr_f32(v * static_cast<double>(s), r16));
+            st_stream(p + i, sr_f32(v, r16));
         else
-            st_stream(p + i, static_cast<float>(v * s));
+            st_stream(p + i, static_cast<float>(v));
     }
 };
 
@@ -140,23 +141,23 @@ template <>
 struct Store<ST_BF16> {
     using T = uint16_t;
     using R = float;
-    static __device__ __forceinline__ float ld(const T *p, uint64_t i, float inv)
+    static __device__ __forceinline__ float ld(const T *p, uint64_t i, float)
     {
-        return __uint_as_float(static_cast<uint32_t>(p[i]) << 16) * inv;
+        return __uint_as_float(static_cast<uint32_t>(p[i]) << 16);
     }
     template <class V>
-    static __device__ __forceinline__ void st(T *p, uint64_t i, V v, float s)
+    static __device__ __forceinline__ void st(T *p, uint64_t i, V v, float)
     {
         // round to nearest even on the upper 16 bits
-        uint32_t b = __float_as_uint(static_cast<float>(v) * s);
+        uint32_t b = __float_as_uint(static_cast<float>(v));
         b += 0x7fffu + ((b >> 16) & 1u);
         p[i] = static_cast<uint16_t>(b >> 16);
     }
     template <class V>
-    static __device__ __forceinline__ void st_sr(T *p, uint64_t i, V v, float s, int32_t r16)
+    static __device__ __forceinline__ void st_sr(T *p, uint64_t i, V v, float, int32_t r16)
     {
         // uniform bits added below the kept 16 bits, then truncation
-        const uint32_t b = __float_as_uint(static_cast<float>(v) * s) +
+        const uint32_t b = __float_as_uint(static_cast<float>(v)) +
                            static_cast<uint32_t>(r16 + 32768);
         p[i] = static_cast<uint16_t>(b >> 16);
     }
