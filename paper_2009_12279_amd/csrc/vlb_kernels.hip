@@ -1543,14 +1543,28 @@ __device__ void link_forces(const Geom &g, const uint8_t *mask, const void *fv, 
     const T *f = static_cast<const T *>(fv);
     const Nbr nb(g, x, y, z);
     const uint32_t n = nb.at(0, 0, 0);
+    // Every load first (all in bounds), the arithmetic on the matching links
+    // afterwards: a wave then waits for memory once, not once per link.
+    uint8_t mk[Q];
+    float hd[Q], ho[Q];
 #pragma unroll
     for (int d = 1; d < Q; ++d) {
         const uint32_t m = nb.at(CX[d], CY[d], CZ[d]);
-        if (!owner_match(mask[m]))
-            continue;
+        mk[d] = mask[m];
         // f*_d(x) in its own slot, the reflected population in the solid slot
-        const double s = 2.0 * WD[d] + static_cast<double>(St::ld(f, d * g.plane + n, inv_scale)) +
-                         static_cast<double>(St::ld(f, OPP[d] * g.plane + m, inv_scale));
+        hd[d] = St::ld(f, d * g.plane + n, inv_scale);
+        ho[d] = St::ld(f, OPP[d] * g.plane + m, inv_scale);
+    }
+    double town[6];  // this cell's polymer stress, for the traction
+    if (polymer)
+#pragma unroll
+        for (int c = 0; c < 6; ++c)
+            town[c] = mapped_stress(sm, tau, g.plane, n, c);
+#pragma unroll
+    for (int d = 1; d < Q; ++d) {
+        if (!owner_match(mk[d]))
+            continue;
+        const double s = 2.0 * WD[d] + static_cast<double>(hd[d]) + static_cast<double>(ho[d]);
         const double dF[3] = {CX[d] * s, CY[d] * s, CZ[d] * s};
         acc[0] += dF[0];
         acc[1] += dF[1];
@@ -1571,15 +1585,15 @@ __device__ void link_forces(const Geom &g, const uint8_t *mask, const void *fv, 
         for (int side = 0; side < 2; ++side) {
             const int s = side == 0 ? 1 : -1;
             const int cx = s * (k == 0), cy = s * (k == 1), cz = s * (k == 2);
-            const uint32_t m = nb.at(cx, cy, cz);
-            if (!owner_match(mask[m]))
+            // face directions are 1..6 in the order +x, -x, +y, -y, +z, -z
+            if (!owner_match(mk[2 * k + 1 + side]))
                 continue;
             // the face value the polymer force used: the mean of this cell's
             // stress and the one extrapolated into the solid neighbour
             double dF[3];
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
-                const double own = mapped_stress(sm, tau, g.plane, n, TROW[k][j]);
+                const double own = town[TROW[k][j]];
                 const double face =
                     sm.extrap ? 0.5 * (own + extrap_stress(g, mask, tau, sm, nb, cx, cy, cz,
                                                            TROW[k][j]))
