@@ -158,6 +158,7 @@ struct vlb_lattice {
         b.parts = d_parts;
         b.n_parts = static_cast<int32_t>(parts_h.size());
         b.moving = (any_movable || moving_walls) ? 1 : 0;
+        b.walls_move = moving_walls ? 1 : 0;
         return b;
     }
 };

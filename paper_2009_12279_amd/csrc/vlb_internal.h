@@ -64,6 +64,7 @@ struct Bound {
     const Particle *parts;
     int32_t n_parts;
     int32_t moving;          // any moving wall or movable particle
+    int32_t walls_move = 0;  // some wall moves (a nonzero table entry or a per-cell field)
 };
 
 // Map from the stored stress variable to the polymer stress.  Identity for

@@ -489,6 +489,7 @@ __device__ __forceinline__ Bound bound_copy(const B &b)
     r.parts = b.parts;
     r.n_parts = b.n_parts;
     r.moving = b.moving;
+    r.walls_move = b.walls_move;
     return r;
 }
 
@@ -561,11 +562,14 @@ __device__ __forceinline__ void lb_cell(const A &a, uint32_t n, uint32_t step)
     for (int i = 0; i < Q; ++i)
         f[i] = ldp<S>(static_cast<const T *>(a.fin_p[i]), d.at(n, -CX[i], -CY[i], -CZ[i]),
                       a.inv_scale);
-    // solid neighbours along every direction
-    uint32_t links = 0;
+    // solid neighbours along every direction, and which of them are particles
+    uint32_t links = 0, plinks = 0;
 #pragma unroll
-    for (int j = 1; j < Q; ++j)
-        links |= (mask[d.at(n, CX[j], CY[j], CZ[j])] != 0 ? 1u : 0u) << j;
+    for (int j = 1; j < Q; ++j) {
+        const uint8_t mj = mask[d.at(n, CX[j], CY[j], CZ[j])];
+        links |= (mj != 0 ? 1u : 0u) << j;
+        plinks |= (mj >= PART0 ? 1u : 0u) << j;
+    }
     // stress of the face neighbours and of the cell itself (for the
     // constant extrapolation into solid neighbours)
     float tn[3][2][3], town[6];
@@ -730,10 +734,20 @@ __device__ __forceinline__ void lb_cell(const A &a, uint32_t n, uint32_t step)
     const R P1 = wp * (drho - R(1.5) * rho * uu) - R(3) * cp * uF;
     const R Q1 = R(4.5) * wp * rho, C9 = R(9) * cp;
     const R M3 = R(3) * wm * rho, C3 = R(3) * cm;
+    // Bounce-back (Section 3.1 velocity boundary condition): a link into a
+    // solid cell sends the post-collision population of its direction into
+    // the slot of the opposite direction at the solid cell, which the next
+    // pull of this cell reads.  Links into walls at rest are written from
+    // registers right after the population; links that need the moving-wall
+    // term (into moving walls, or into particles when some particle moves)
+    // go through reflect_links afterwards.
+    const uint32_t slow = a.b.moving ? (a.b.walls_move ? links : plinks) : 0u;
+    const uint32_t fast = links & ~slow;
     Rng rng(n, step, a.seed);
-    uint32_t r = rng.next32();
     stp<S, SR>(static_cast<T *>(a.fout_p[0]), n,
-               R(2) * a1 * static_cast<R>(pop(0)) + static_cast<R>(WD[0]) * P1, a.scale, rhi(r));
+               R(2) * a1 * static_cast<R>(pop(0)) + static_cast<R>(WD[0]) * P1, a.scale,
+               rhi(rng.next32()));
+    // one 32-bit random word per opposite pair, a 16-bit half each
 #pragma unroll
     for (int k = 0; k < Q / 2; ++k) {
         const int i = 2 * k + 1, o = i + 1;
@@ -745,19 +759,19 @@ __device__ __forceinline__ void lb_cell(const A &a, uint32_t n, uint32_t step)
         const R nm = b1 * (a_ - b_) + w * (M3 * cu + C3 * cF);
         T *pi = static_cast<T *>(a.fout_p[i]);
         T *po = static_cast<T *>(a.fout_p[o]);
-        if (k & 1) {
-            stp<S, SR>(pi, n, np + nm, a.scale, rlo(r));
-            r = rng.next32();
-            stp<S, SR>(po, n, np - nm, a.scale, rhi(r));
-        } else {
-            r = rng.next32();
-            stp<S, SR>(pi, n, np + nm, a.scale, rhi(r));
-            stp<S, SR>(po, n, np - nm, a.scale, rlo(r));
+        const uint32_t r = rng.next32();
+        stp<S, SR>(pi, n, np + nm, a.scale, rhi(r));
+        stp<S, SR>(po, n, np - nm, a.scale, rlo(r));
+        if (fast & ((1u << i) | (1u << o))) {
+            if ((fast >> i) & 1u)
+                stp<S, SR>(po, d.at(n, CX[i], CY[i], CZ[i]), np + nm, a.scale, rhi(rng.next32()));
+            if ((fast >> o) & 1u)
+                stp<S, SR>(pi, d.at(n, CX[o], CY[o], CZ[o]), np - nm, a.scale, rhi(rng.next32()));
         }
     }
 
-    if (links)
-        reflect_links<S, SR>(a, static_cast<T *>(a.fout), n, d, links, rho, rng);
+    if (slow)
+        reflect_links<S, SR>(a, static_cast<T *>(a.fout), n, d, slow, rho, rng);
 
     if (a.polymer) {
         *elem(a.u_p[0], n) = static_cast<float>(ux);
