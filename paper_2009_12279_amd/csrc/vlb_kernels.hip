@@ -740,8 +740,12 @@ __device__ __forceinline__ void lb_cell(const A &a, uint32_t n, uint32_t step)
     // pull of this cell reads.  Links into walls at rest are written from
     // registers right after the population; links that need the moving-wall
     // term (into moving walls, or into particles when some particle moves)
-    // go through reflect_links afterwards.
-    const uint32_t slow = a.b.moving ? (a.b.walls_move ? links : plinks) : 0u;
+    // go through reflect_links afterwards.  With 16-bit storage every link
+    // takes the reload path: the extra live registers of the register path
+    // push the kernel past the register budget of five waves per SIMD, and
+    // the spills cost more than the reloads save.
+    const uint32_t slow = S != ST_F32 ? links
+                                      : (a.b.moving ? (a.b.walls_move ? links : plinks) : 0u);
     const uint32_t fast = links & ~slow;
     Rng rng(n, step, a.seed);
     stp<S, SR>(static_cast<T *>(a.fout_p[0]), n,
