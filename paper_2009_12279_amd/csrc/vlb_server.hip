@@ -26,6 +26,8 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <memory>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -50,7 +52,8 @@ struct Request {
     int state = VLB_REQ_QUEUED;
     clock_type::time_point submitted;
     double latency_ms = -1.0;
-    std::vector<double> u, tau;  // results (host)
+    std::unique_ptr<double[]> result;  // host: u (3 N) then tau (6 N)
+    uint64_t result_n = 0;             // N of the result
     std::string error;
 };
 
@@ -119,11 +122,9 @@ struct vlb_server {
     bool tables_dirty = false;
     bool admitted_since_launch = false;
     hipEvent_t io_done = nullptr;
-    // result staging (doubles)
+    // device result buffer (doubles), grown in stream order on io
     double *d_result = nullptr;
     uint64_t d_result_cap = 0;
-    double *h_result = nullptr;
-    uint64_t h_result_cap = 0;
     // two graph executables, used by alternate replays, so that one can be
     // updated while the other is in flight
     struct GraphSet {
@@ -459,33 +460,34 @@ vlb_status ensure_graph(vlb_server *srv, vlb_server::GraphSet &gs)
 }
 
 // Results of finished solves (their last replay has completed): velocity from
-// the moments of the final state and the stress, read on the io stream into
-// pinned staging while later replays run.
-vlb_status collect(vlb_server *srv, const std::vector<Slot> &done)
+// the moments of the final state and the stress.  collect_issue enqueues the
+// readout kernels on the io stream and returns at once: that must happen
+// before any admission can take the solves' arena ranges (a later reuse is
+// stream-ordered after the readout).  collect_finish copies the results into
+// each request's own host array; it runs after the next replays are issued,
+// so the copies overlap GPU work.  The device result buffer grows with
+// stream-ordered allocation on io: a plain free would wait for the replays
+// in flight.
+hipError_t collect_issue(vlb_server *srv, const std::vector<Slot> &done)
 {
     uint64_t total = 0;
     for (const Slot &sl : done)
         total += 9ull * sl.g.N;
     if (total == 0)
-        return VLB_OK;
+        return hipSuccess;
+    hipError_t e = hipSuccess;
     if (total > srv->d_result_cap) {
+        const uint64_t cap = std::max<uint64_t>(total, 2 * srv->d_result_cap);
         if (srv->d_result)
-            (void)hipFree(srv->d_result);
+            (void)hipFreeAsync(srv->d_result, srv->io);
         srv->d_result = nullptr;
         srv->d_result_cap = 0;
-        SCHK(srv, hipMalloc(&srv->d_result, total * sizeof(double)), "result buffer");
-        srv->d_result_cap = total;
-    }
-    if (total > srv->h_result_cap) {
-        if (srv->h_result)
-            (void)hipHostFree(srv->h_result);
-        srv->h_result = nullptr;
-        srv->h_result_cap = 0;
-        SCHK(srv, hipHostMalloc(&srv->h_result, total * sizeof(double)), "result staging");
-        srv->h_result_cap = total;
+        if ((e = hipMallocAsync(reinterpret_cast<void **>(&srv->d_result), cap * sizeof(double),
+                                srv->io)) != hipSuccess)
+            return e;
+        srv->d_result_cap = cap;
     }
     uint64_t off = 0;
-    hipError_t e = hipSuccess;
     for (const Slot &sl : done) {
         const Request &rq = srv->requests[sl.ticket];
         const uint64_t N = sl.g.N;
@@ -501,31 +503,47 @@ vlb_status collect(vlb_server *srv, const std::vector<Slot> &done)
                                          srv->io);
         if (e == hipSuccess)
             e = vlb::launch_read_stress(sl.g, sl.mask, sl.tau[par], d + 3 * N, srv->io);
+        off += 9 * N;
+    }
+    return e;
+}
+
+// e: the status of the matching collect_issue.
+vlb_status collect_finish(vlb_server *srv, const std::vector<Slot> &done, hipError_t e)
+{
+    if (done.empty())
+        return VLB_OK;
+    uint64_t off = 0;
+    for (const Slot &sl : done) {
+        Request &rq = srv->requests[sl.ticket];
+        const uint64_t N = sl.g.N;
+        if (e == hipSuccess) {
+            rq.result.reset(new (std::nothrow) double[9 * N]);
+            if (!rq.result)
+                e = hipErrorOutOfMemory;
+        }
         if (e == hipSuccess)
-            e = hipMemcpyAsync(srv->h_result + off, d, 9 * N * sizeof(double),
+            e = hipMemcpyAsync(rq.result.get(), srv->d_result + off, 9 * N * sizeof(double),
                                hipMemcpyDeviceToHost, srv->io);
         off += 9 * N;
     }
     if (e == hipSuccess)
         e = hipStreamSynchronize(srv->io);
-    off = 0;
     const auto now = clock_type::now();
     for (const Slot &sl : done) {
         Request &rq = srv->requests[sl.ticket];
-        const uint64_t N = sl.g.N;
         if (e == hipSuccess) {
-            rq.u.assign(srv->h_result + off, srv->h_result + off + 3 * N);
-            rq.tau.assign(srv->h_result + off + 3 * N, srv->h_result + off + 9 * N);
+            rq.result_n = sl.g.N;
             rq.latency_ms = std::chrono::duration<double, std::milli>(now - rq.submitted).count();
             rq.state = VLB_REQ_DONE;
             srv->stats.completed += 1;
         } else {
+            rq.result.reset();
             rq.state = VLB_REQ_FAILED;
             rq.error = std::string("result readout: ") + hipGetErrorString(e);
         }
         rq.mask.clear();
         rq.mask.shrink_to_fit();
-        off += 9 * N;
     }
     SCHK(srv, e, "result readout");
     return VLB_OK;
@@ -556,6 +574,70 @@ vlb_status reap(vlb_server *srv, bool block)
             SCHK(srv, q, "replay query");
         }
         srv->n_completed += 1;
+    }
+    return VLB_OK;
+}
+
+// Admit queued requests while slots and memory allow (FIFO, no overtaking)
+// and keep up to two replays in flight.  Admitted requests of zero steps are
+// moved to zero_step.
+vlb_status admit_and_launch(vlb_server *srv, std::vector<Slot> &zero_step)
+{
+    vlb_status st = VLB_OK;
+    while (!srv->queue.empty() && static_cast<int>(srv->slots.size()) < srv->max_slots) {
+        Request &rq = srv->requests[srv->queue.front()];
+        if (rq.state == VLB_REQ_CANCELLED) {
+            srv->queue.pop_front();
+            continue;
+        }
+        if (srv->used + footprint(rq.dims) > srv->budget)
+            break;
+        bool no_room = false;
+        st = admit(srv, rq, no_room);
+        if (no_room)
+            break;  // no free range yet: wait for retirements
+        srv->queue.pop_front();
+        if (st != VLB_OK) {
+            rq.state = VLB_REQ_FAILED;
+            rq.error = srv->err;
+            continue;
+        }
+        if (rq.steps == 0) {
+            // nothing to advance: the result is the initial state
+            zero_step.push_back(srv->slots.back());
+            srv->slots.pop_back();
+            srv->new_ids.pop_back();
+        }
+    }
+    srv->stats.running = static_cast<int64_t>(srv->slots.size());
+    srv->stats.queued = static_cast<int64_t>(srv->queue.size());
+    srv->stats.bytes_in_use = srv->used;
+    // keep up to two replays in flight while some solve still has steps that
+    // no replay has been issued for
+    while (srv->n_launched - srv->n_completed < 2) {
+        uint64_t cells = 0;
+        for (const Slot &sl : srv->slots)
+            if (sl.last_launch >= srv->n_launched)
+                cells += sl.g.N;
+        if (cells == 0)
+            break;
+        if (srv->tables_dirty && (st = rebuild_tables(srv)) != VLB_OK)
+            return st;
+        if (srv->admitted_since_launch) {
+            SCHK(srv, hipEventRecord(srv->io_done, srv->io), "admission event");
+            SCHK(srv, hipStreamWaitEvent(srv->stream, srv->io_done, 0), "admission wait");
+            srv->admitted_since_launch = false;
+        }
+        // this set's previous replay (two back) has completed
+        const uint32_t which = static_cast<uint32_t>(srv->n_launched & 1u);
+        vlb_server::GraphSet &gs = srv->graphs[which];
+        if ((st = ensure_graph(srv, gs)) != VLB_OK)
+            return st;
+        SCHK(srv, hipGraphLaunch(gs.exec, srv->stream), "graph launch");
+        SCHK(srv, hipEventRecord(srv->launch_done[which], srv->stream), "event");
+        srv->n_launched += 1;
+        srv->stats.launches += 1;
+        srv->stats.cell_steps_launched += cells * static_cast<uint64_t>(srv->k_steps);
     }
     return VLB_OK;
 }
@@ -776,7 +858,10 @@ vlb_status vlb_server_pump(vlb_server *srv, int32_t wait)
             keep.push_back(sl);
     }
     srv->slots.swap(keep);
-    const vlb_status cst = collect(srv, done);
+    // the readout of finished solves is issued now, before any admission can
+    // take their ranges, and finished after the next replays are issued, so
+    // that the host's copies overlap GPU work
+    const hipError_t issued = collect_issue(srv, done);
     for (const Slot &sl : done)
         retire(srv, sl);
     for (const Slot &sl : dropped) {
@@ -785,74 +870,19 @@ vlb_status vlb_server_pump(vlb_server *srv, int32_t wait)
         rq.mask.shrink_to_fit();
         retire(srv, sl);
     }
-    if (cst != VLB_OK)
-        return cst;
+    if (issued != hipSuccess)
+        return collect_finish(srv, done, issued);
     release_quarantine(srv);
-    // admit from the queue while slots and memory allow (FIFO, no overtaking)
     std::vector<Slot> zero_step;
-    while (!srv->queue.empty() && static_cast<int>(srv->slots.size()) < srv->max_slots) {
-        Request &rq = srv->requests[srv->queue.front()];
-        if (rq.state == VLB_REQ_CANCELLED) {
-            srv->queue.pop_front();
-            continue;
-        }
-        if (srv->used + footprint(rq.dims) > srv->budget)
-            break;
-        bool no_room = false;
-        st = admit(srv, rq, no_room);
-        if (no_room)
-            break;  // no free range yet: wait for retirements
-        srv->queue.pop_front();
-        if (st != VLB_OK) {
-            rq.state = VLB_REQ_FAILED;
-            rq.error = srv->err;
-            continue;
-        }
-        if (rq.steps == 0) {
-            // nothing to advance: the result is the initial state
-            zero_step.push_back(srv->slots.back());
-            srv->slots.pop_back();
-            srv->new_ids.pop_back();
-        }
-    }
+    const vlb_status lst = admit_and_launch(srv, zero_step);
+    const vlb_status cst = collect_finish(srv, done, hipSuccess);
+    vlb_status zst = VLB_OK;
     if (!zero_step.empty()) {
-        const vlb_status zst = collect(srv, zero_step);
+        zst = collect_finish(srv, zero_step, collect_issue(srv, zero_step));
         for (const Slot &sl : zero_step)
             retire(srv, sl);
-        if (zst != VLB_OK)
-            return zst;
     }
-    srv->stats.running = static_cast<int64_t>(srv->slots.size());
-    srv->stats.queued = static_cast<int64_t>(srv->queue.size());
-    srv->stats.bytes_in_use = srv->used;
-    // keep up to two replays in flight while some solve still has steps that
-    // no replay has been issued for
-    while (srv->n_launched - srv->n_completed < 2) {
-        uint64_t cells = 0;
-        for (const Slot &sl : srv->slots)
-            if (sl.last_launch >= srv->n_launched)
-                cells += sl.g.N;
-        if (cells == 0)
-            break;
-        if (srv->tables_dirty && (st = rebuild_tables(srv)) != VLB_OK)
-            return st;
-        if (srv->admitted_since_launch) {
-            SCHK(srv, hipEventRecord(srv->io_done, srv->io), "admission event");
-            SCHK(srv, hipStreamWaitEvent(srv->stream, srv->io_done, 0), "admission wait");
-            srv->admitted_since_launch = false;
-        }
-        // this set's previous replay (two back) has completed
-        const uint32_t which = static_cast<uint32_t>(srv->n_launched & 1u);
-        vlb_server::GraphSet &gs = srv->graphs[which];
-        if ((st = ensure_graph(srv, gs)) != VLB_OK)
-            return st;
-        SCHK(srv, hipGraphLaunch(gs.exec, srv->stream), "graph launch");
-        SCHK(srv, hipEventRecord(srv->launch_done[which], srv->stream), "event");
-        srv->n_launched += 1;
-        srv->stats.launches += 1;
-        srv->stats.cell_steps_launched += cells * static_cast<uint64_t>(srv->k_steps);
-    }
-    return VLB_OK;
+    return lst != VLB_OK ? lst : cst != VLB_OK ? cst : zst;
 }
 
 vlb_status vlb_server_poll(vlb_server *srv, uint64_t ticket, int32_t *state)
@@ -879,10 +909,11 @@ vlb_status vlb_server_result(vlb_server *srv, uint64_t ticket, double *u, double
         return sfail(srv, VLB_EDEVICE, "vlb_server_result: request failed: " + rq.error);
     if (rq.state != VLB_REQ_DONE)
         return sfail(srv, VLB_ESTATE, "vlb_server_result: request not finished");
+    const uint64_t N = rq.result_n;
     if (u)
-        std::memcpy(u, rq.u.data(), rq.u.size() * sizeof(double));
+        std::memcpy(u, rq.result.get(), 3 * N * sizeof(double));
     if (tau)
-        std::memcpy(tau, rq.tau.data(), rq.tau.size() * sizeof(double));
+        std::memcpy(tau, rq.result.get() + 3 * N, 6 * N * sizeof(double));
     if (latency_ms)
         *latency_ms = rq.latency_ms;
     srv->requests.erase(it);
@@ -919,20 +950,24 @@ void vlb_server_destroy(vlb_server *srv)
         return;
     if (srv->stream)
         (void)hipStreamSynchronize(srv->stream);
-    if (srv->io)
+    if (srv->io) {
+        if (srv->d_result)
+            (void)hipFreeAsync(srv->d_result, srv->io);
+        srv->d_result = nullptr;
         (void)hipStreamSynchronize(srv->io);
+    }
     drop_graph(srv->graphs[0]);
     drop_graph(srv->graphs[1]);
-    void *p[] = {srv->arena, srv->d_table, srv->d_solves, srv->d_block_solve, srv->d_steps,
-                 srv->d_result};
+    void *p[] = {srv->arena, srv->d_table, srv->d_solves, srv->d_block_solve, srv->d_steps};
     for (void *q : p)
         if (q)
             (void)hipFree(q);
-    void *h[] = {srv->h_table, srv->h_solves, srv->h_block_solve, srv->h_zero, srv->h_result};
+    void *h[] = {srv->h_table, srv->h_solves, srv->h_block_solve, srv->h_zero};
     for (void *q : h)
         if (q)
             (void)hipHostFree(q);
-    for (hipEvent_t ev : {srv->launch_done[0], srv->launch_done[1], srv->tables_copied, srv->io_done})
+    for (hipEvent_t ev : {srv->launch_done[0], srv->launch_done[1], srv->tables_copied,
+                          srv->io_done})
         if (ev)
             (void)hipEventDestroy(ev);
     if (srv->io)
