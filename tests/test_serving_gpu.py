@@ -84,6 +84,22 @@ def test_results_identical_alone_and_in_the_mix():
         np.testing.assert_array_equal(ta, tm)
 
 
+def test_result_buffer_grows_between_readouts():
+    """A larger solve that finishes after a smaller one has been read out
+    makes the server grow its device result buffer (in stream order, while
+    replays may be in flight); both results must equal those of solves run
+    alone."""
+    small = make_request(11, (12, 10, 8), 20, 0)
+    large = make_request(12, (40, 30, 24), 90, 2)
+    log("[serving] small then large: result buffer growth")
+    mixed, stats = serve([small, large], k=10, stagger=False)
+    assert stats["completed"] == 2
+    for r in (small, large):
+        alone, _ = serve([r], slots=1, k=10)
+        for a, b in zip(alone[r["seed"]][:2], mixed[r["seed"]][:2]):
+            np.testing.assert_array_equal(a, b)
+
+
 def test_served_solve_equals_plain_lattice():
     r = make_request(7, (18, 16, 14), 150, 1)
     log("[serving] served vs plain lattice")
