@@ -279,7 +279,10 @@ double vlb_kernel_time_ms(const vlb_lattice *lat, int32_t which);
  * in the budget and in a free range of the arena, and issues replays of
  * steps_per_launch batched steps that advance every admitted solve together
  * (a replayed hipGraph), keeping up to two replays in flight so that the
- * host's retire/admit work overlaps the GPU's.  Requests submitted while
+ * host's retire/admit work overlaps the GPU's.  Results are read into a
+ * device buffer outside the budget (72 bytes per cell of the solves that
+ * finish in one round, grown in stream order, never shrunk) and copied to
+ * host memory after that round's replays are issued.  Requests submitted while
  * others run join at the next pump.  Each solve computes exactly what a lone
  * vlb_lattice with the same mask, parameters and rounding seed computes:
  * results do not depend on what else is in the batch.  Walls in a request
