@@ -441,8 +441,11 @@ vlb_status create_impl(const vlb_dims *dims, const uint8_t *mask, const double *
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
         return fail(nullptr, VLB_EDEVICE, "vlb_create: no HIP device");
 
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess)
+        return fail(nullptr, VLB_EDEVICE, "vlb_create: no current HIP device");
     vlb_lattice *lat = new vlb_lattice();
-    (void)hipGetDevice(&lat->device);
+    lat->device = device;
     lat->g.nx = dims->nx;
     lat->g.ny = dims->ny;
     lat->g.nz = dims->nz;
