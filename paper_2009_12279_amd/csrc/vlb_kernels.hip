@@ -529,9 +529,11 @@ __device__ void reflect_links(const A &a, typename Store<S>::T *fout, uint32_t n
 #ifdef VLB_LB_WAVES
 #define LB_OCCUPANCY(S) __attribute__((amdgpu_waves_per_eu(VLB_LB_WAVES)))
 #else
-// 16-bit storage: at least 5 waves per SIMD (at most 96 VGPRs), measured
-// faster there; FP32 storage with FP64 arithmetic keeps the compiler's choice
-#define LB_OCCUPANCY(S) __attribute__((amdgpu_waves_per_eu((S) == ST_F32 ? 1 : 5)))
+// At least 5 waves per SIMD (at most 96 VGPRs) for 16-bit storage and 4
+// (at most 128 VGPRs, a 20-byte spill) for FP32 storage with FP64
+// arithmetic: both measured faster than the compiler's own choice (4 and 3
+// waves)
+#define LB_OCCUPANCY(S) __attribute__((amdgpu_waves_per_eu((S) == ST_F32 ? 4 : 5)))
 #endif
 #ifdef VLB_FV_WAVES
 #define FV_OCCUPANCY __attribute__((amdgpu_waves_per_eu(VLB_FV_WAVES)))
@@ -1213,7 +1215,7 @@ __device__ __forceinline__ const VLB_CONST_AS X *uniform_ptr(const X *p)
 }
 
 template <bool SR>
-__global__ __launch_bounds__(BLOCK) void lb_batch_kernel(const BatchTable *__restrict__ t)
+__global__ __launch_bounds__(BLOCK) LB_OCCUPANCY(ST_F32) void lb_batch_kernel(const BatchTable *__restrict__ t)
 {
     const VLB_CONST_AS BatchTable &tb = *uniform_ptr(t);
     const uint32_t b = block_id(1, 0);  // one contiguous range of blocks per XCD
