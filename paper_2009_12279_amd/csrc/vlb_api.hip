@@ -32,7 +32,7 @@ uint64_t plane_pad()
             if (v >= 0)
                 return static_cast<uint64_t>(v) / kPlaneAlign * kPlaneAlign;
         }
-        return static_cast<uint64_t>(5 * kPlaneAlign);
+        return static_cast<uint64_t>(9 * kPlaneAlign);
     }();
     return pad;
 }
@@ -55,6 +55,20 @@ int remap_blocks(const vlb::Geom &g, uint32_t &slab_blocks)
     if (mode == 2 && !slabs_fit)
         mode = 1;
     return mode;
+}
+
+// Block order of stream-collide: the hardware's (0), measured faster than
+// the XCD-aware orders the stress update keeps, unless VLB_LB_REMAP (0, 1,
+// 2) asks for one of those.
+int lb_remap_blocks(const vlb::Geom &g)
+{
+    static int forced = [] {
+        const char *e = std::getenv("VLB_LB_REMAP");
+        return e ? std::atoi(e) : 0;
+    }();
+    uint32_t slab_blocks = 0;
+    const int fitted = remap_blocks(g, slab_blocks);
+    return forced == 2 ? fitted : (forced == 1 ? 1 : 0);
 }
 
 // Stress-update kernel: tiled (64 x 4 tiles marching through 16 planes)
@@ -941,6 +955,7 @@ vlb_status vlb_step(vlb_lattice *lat, int64_t n_steps)
     a.scale = lat->scale;
     a.inv_scale = lat->inv_scale;
     a.remap = remap_blocks(lat->g, a.slab_blocks);
+    a.lb_remap = lb_remap_blocks(lat->g);
     const int nev = lat->timing ? 6 : 0;
     if (lat->timing && lat->events.size() < static_cast<size_t>(nev * n_steps)) {
         while (lat->events.size() < static_cast<size_t>(nev * n_steps)) {

@@ -109,6 +109,7 @@ struct StepArgs {
     StressMap sm;            // stored variable -> polymer stress (FENE-P)
     int32_t polymer;
     int32_t remap;           // XCD-aware block order (0 off, 1 ranges, 2 y-slabs)
+    int32_t lb_remap;        // the same for stream-collide alone
     uint32_t slab_blocks;    // remap 2: blocks per XCD per z-plane
     int32_t stochastic;      // stochastic rounding of stored values
     uint32_t step;           // step index (random stream of the rounding); with

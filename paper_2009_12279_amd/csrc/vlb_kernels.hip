@@ -789,7 +789,7 @@ __device__ __forceinline__ void lb_cell(const A &a, uint32_t n, uint32_t step)
 template <int S, bool SR, bool FENE>
 __global__ __launch_bounds__(BLOCK) LB_OCCUPANCY(S) void lb_step_kernel(StepArgs a)
 {
-    const uint32_t n = block_id(a.remap, a.slab_blocks) * BLOCK + threadIdx.x;
+    const uint32_t n = block_id(a.lb_remap, a.slab_blocks) * BLOCK + threadIdx.x;
     if (n >= a.g.N)
         return;
     lb_cell<S, SR, FENE>(a, n, a.step_dev ? *a.step_dev + a.step : a.step);

@@ -260,6 +260,7 @@ void make_args(vlb_server *srv, Slot &sl, const Request &rq)
         a.scale = 1.f;
         a.inv_scale = 1.f;
         a.remap = 0;
+        a.lb_remap = 0;
         a.stochastic = srv->stochastic;
         a.seed = rq.seed;
     }
