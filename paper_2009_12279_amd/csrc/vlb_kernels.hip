@@ -1218,7 +1218,7 @@ template <bool SR>
 __global__ __launch_bounds__(BLOCK) LB_OCCUPANCY(ST_F32) void lb_batch_kernel(const BatchTable *__restrict__ t)
 {
     const VLB_CONST_AS BatchTable &tb = *uniform_ptr(t);
-    const uint32_t b = block_id(1, 0);  // one contiguous range of blocks per XCD
+    const uint32_t b = blockIdx.x;  // hardware order, as for a single lattice
     if (b >= tb.total_blocks)
         return;
     const uint32_t s = uniform_ptr(tb.block_solve)[b];
