@@ -2131,16 +2131,17 @@ hipError_t launch_fv_step(int storage, const StepArgs &a, hipStream_t s, int til
 {
     (void)storage;
     // The tiled kernel needs x rows that fill its 64-wide tiles and enough
-    // blocks to fill the chip (chunks are shortened down to 4 planes for
-    // that); small lattices take the per-cell kernel unless the tiled one is
-    // forced (negative tile_rows).
+    // blocks to fill the chip (chunks are shortened down to 8 planes for
+    // that: with 4-plane chunks the column and ring loads at each chunk's
+    // start cost more than tiling saves); small lattices take the per-cell
+    // kernel unless the tiled one is forced (negative tile_rows).
     const bool force = tile_rows < 0;
     if (force)
         tile_rows = -tile_rows;
     const uint32_t rows = tile_rows > 0 ? static_cast<uint32_t>(tile_rows) : 1u;
     const uint32_t tiles_xy = ((a.g.nx + FV_TX - 1) / FV_TX) * ((a.g.ny + rows - 1) / rows);
     uint32_t zc = z_chunk ? z_chunk : 16u;
-    while (!force && zc > 4 && tiles_xy * ((a.g.nz + zc - 1) / zc) < 2048)
+    while (!force && zc > 8 && tiles_xy * ((a.g.nz + zc - 1) / zc) < 2048)
         zc /= 2;
     // at most an eighth of the tile lanes beyond the end of the rows
     const uint32_t lanes_x = ((a.g.nx + FV_TX - 1) / FV_TX) * FV_TX;
