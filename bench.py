@@ -7,9 +7,11 @@ polymer fraction beta drawn once from U[0.1, 0.9], lambda_p = 1000, FP32
 deviation storage.  A step is one pass of the whole per-cell path
 (stream-collide with bounce-back and polymer force, then the stress update).
 
-Prints one JSON line with MLUPS, the HBM roofline of the dominant kernel
-(HIP-event timed on the lattice's stream) and the FP64 CPU oracle timed on
-a bounded sample of the same workload.
+Prints one JSON line with MLUPS, the HBM roofline of the whole step (its
+algorithmic bytes over the step time, HIP events on the lattice's stream),
+the same for each kernel of the step, and the FP64 CPU oracle timed on a
+bounded sample of the same workload with one thread and with every host
+core.
 """
 from __future__ import annotations
 
@@ -133,11 +135,11 @@ def run_gpu(args, law=None):
     health = lat.check_health()
     alg = algorithmic_bytes(args.storage)
     dom = max(k_ms, key=lambda k: k_ms[k])
-    achieved = alg[dom] * N / (k_ms[dom] * 1e-3) / 1e9
+    per_kernel = {k: alg[k] * N / (v * 1e-3) / 1e9 for k, v in k_ms.items() if v > 0}
     step_achieved = alg["step"] * N / (ms_per_step * 1e-3) / 1e9
     lat.close()
     return dict(N=N, fluid=fluid, shape=shape, params=params, ms_per_step=ms_per_step, mlups=mlups,
-                wall_s=wall, kernels=k_ms, dominant=dom, achieved=achieved,
+                wall_s=wall, kernels=k_ms, dominant=dom, per_kernel=per_kernel,
                 step_achieved=step_achieved, alg=alg, health=health)
 
 
@@ -222,6 +224,9 @@ def run_moving(args):
 
 
 def run_cpu_baseline(args):
+    """The oracle on the same 256^3 workload: args.cpu_steps steps with every
+    host thread, then args.cpu_steps_single steps with one thread (each after
+    an untimed step that first touches every array)."""
     import oracle
 
     shape, spheres, params = build_workload("f32")
@@ -233,15 +238,26 @@ def run_cpu_baseline(args):
     for c, r in spheres:
         L.add_sphere(c, r)
     L.init_equilibrium()
-    L.step(1)  # first touch of every array
-    t0 = time.perf_counter()
-    L.step(args.cpu_steps)
-    dt = time.perf_counter() - t0
+
+    def timed(n):
+        L.step(1)
+        t0 = time.perf_counter()
+        L.step(n)
+        return nx * ny * nz * n / (time.perf_counter() - t0) / 1e6
+
+    all_cores = timed(args.cpu_steps)
+    single = None
+    if args.cpu_steps_single > 0:
+        oracle.set_threads(1)
+        single = timed(args.cpu_steps_single)
+        oracle.set_threads(0)
     L.close()
-    return dict(value=nx * ny * nz * args.cpu_steps / dt / 1e6, unit="MLUPS", cores=threads,
-                kind="oracle",
+    return dict(value=all_cores, unit="MLUPS", cores=threads, kind="oracle",
                 sample=f"the same 256^3 workload, {args.cpu_steps} steps after 1 untimed step "
-                       f"(FP64 oracle, OpenMP {threads} threads)")
+                       f"(FP64 oracle, OpenMP {threads} threads)",
+                single_thread=None if single is None else dict(
+                    value=single, unit="MLUPS", cores=1,
+                    sample=f"{args.cpu_steps_single} steps after 1 untimed step, 1 thread"))
 
 
 def serving_requests(n, steps_scale):
@@ -370,6 +386,7 @@ def main():
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--rounding", default=None, choices=[None, "nearest", "stochastic"])
     ap.add_argument("--cpu-steps", type=int, default=10)
+    ap.add_argument("--cpu-steps-single", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=48)
     ap.add_argument("--serving-steps-scale", type=float, default=0.1)
@@ -436,7 +453,8 @@ def main():
     # counters were taken for the default configuration only
     traffic = None
     if args.storage == "f32" and args.rounding in (None, "stochastic"):
-        traffic = measured_traffic(g["dominant"])
+        parts = [measured_traffic(k) for k in g["kernels"]]
+        traffic = None if any(t is None for t in parts) else sum(parts)
     line = {
         "metric": METRIC,
         "value": round(g["mlups"], 1),
@@ -459,18 +477,24 @@ def main():
             "storage": args.storage,
             "arithmetic": dtype,
             "parallelism": "single GPU",
-            "step_hbm_frac": round(g["step_achieved"] / HBM_PEAK_GBS, 4),
             "kernel_ms": {k: round(v, 5) for k, v in g["kernels"].items()},
             "algorithmic_bytes_per_cell": g["alg"],
+            "fixed_obstacle_forces": "summed on read from the state the last step left "
+                                     "(same bits as summing them every step); no obstacle "
+                                     "moves, so no step needs them",
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": g["dominant"],
-            "achieved": round(g["achieved"], 1),
+            "kernel": "step: " + " + ".join(g["kernels"]),
+            "achieved": round(g["step_achieved"], 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": round(g["achieved"] / HBM_PEAK_GBS, 4),
+            "frac": round(g["step_achieved"] / HBM_PEAK_GBS, 4),
             "traffic": traffic,
+            "per_kernel": {k: dict(ms=round(g["kernels"][k], 5), achieved=round(v, 1),
+                                   frac=round(v / HBM_PEAK_GBS, 4),
+                                   bytes_per_cell=g["alg"][k])
+                           for k, v in g["per_kernel"].items()},
         },
         "cpu_baseline": cpu,
         "storage_variants": variants,

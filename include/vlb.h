@@ -135,12 +135,14 @@ vlb_status vlb_create_with_buffers(const vlb_dims *dims, const uint8_t *mask,
  * outside (0,2). */
 vlb_status vlb_set_params(vlb_lattice *lat, const vlb_params *params);
 
-/* f = f^eq(rho = 1, u) on fluid cells (u: 3*N doubles, or NULL for rest),
+/* Initial state (Section 3.1, equilibrium distribution with c_s^2 = 1/3):
+ * f = f^eq(rho = 1, u) on fluid cells (u: 3*N doubles, or NULL for rest),
  * tau = 0.  Resets the step count. */
 vlb_status vlb_init_equilibrium(vlb_lattice *lat, const double *u);
 
-/* Overwrite the populations (19*N doubles, raw f, vlb_velocity order) or the
- * stress (6*N doubles) of every fluid cell; solid cells are ignored. */
+/* Overwrite the populations f_i of Section 3.1 (19*N doubles, raw f,
+ * vlb_velocity order) or the polymer stress tau of Section 2.2 (6*N doubles)
+ * of every fluid cell; solid cells are ignored. */
 vlb_status vlb_set_populations(vlb_lattice *lat, const double *f);
 vlb_status vlb_set_stress(vlb_lattice *lat, const double *tau);
 
@@ -155,18 +157,33 @@ vlb_status vlb_add_sphere(vlb_lattice *lat, const double center[3], double radiu
                           double density_ratio, int32_t movable, const double f_ext[3],
                           const double t_ext[3], int32_t *id_out);
 
-/* Advance n_steps time steps (asynchronous).  Runs of 32 steps and more are
- * replayed from captured HIP graphs in chunks of 32, with the same kernels
- * and arguments, so the results are the same bits as step-by-step launches;
- * VLB_GRAPH=0 in the environment turns the replays off. */
+/* Advance n_steps time steps (asynchronous).  One step is the coupled
+ * update of Section 3: polymer force from the stress (Section 3.3, force
+ * discretisation), TRT collision with Guo forcing and pull streaming
+ * (Section 3.1, lattice Boltzmann and forcing equations), halfway
+ * bounce-back with the moving-wall term (Section 3.1, velocity boundary
+ * condition), the finite-volume stress update (Section 2.2 source,
+ * Section 3.3 fluxes), and for movable particles momentum exchange, the
+ * symplectic Euler update and fluid/solid conversion (Section 3.4).  Steps
+ * are replayed from captured HIP graphs in chunks of 32, 16, ..., 1 steps
+ * (captured once per set of step arguments), with the same kernels and
+ * arguments, so the results are the same bits as step-by-step launches;
+ * VLB_GRAPH=0 in the environment turns the replays off.  Errors:
+ * VLB_EINVAL (negative count), VLB_EUNSTABLE (sticky, or found by a health
+ * check at the end of this call's steps), VLB_EDEVICE. */
 vlb_status vlb_step(vlb_lattice *lat, int64_t n_steps);
 vlb_status vlb_sync(vlb_lattice *lat);
 int64_t vlb_step_count(const vlb_lattice *lat);
 
 /* Reads of the current state (FP64 host arrays of N, 3*N, 6*N, 19*N values;
- * solid cells read 0).  Density rho = sum f; velocity u = (sum f c + F/2)/rho
- * with F = g + the per-cell force field, if set, + the polymer force of the
- * current stress (Section 3.1). */
+ * solid cells read 0).  Density rho = sum f and velocity
+ * u = (sum f c + F/2)/rho (Section 3.1, macroscopic moments with the half
+ * force), with F = g + the per-cell force field, if set, + the polymer force
+ * of the current stress (Section 3.3, force discretisation); the stress is
+ * the polymer stress tau of Section 2.2 (for FENE-P mapped from the stored
+ * variable); populations are raw f = w_i + stored deviation.  Synchronise
+ * the stream; allocate a device staging buffer of the output's size for
+ * the call.  Errors: VLB_EINVAL (NULL output), VLB_ENOMEM, VLB_EDEVICE. */
 vlb_status vlb_read_density(vlb_lattice *lat, double *rho);
 vlb_status vlb_read_velocity(vlb_lattice *lat, double *u);
 vlb_status vlb_read_stress(vlb_lattice *lat, double *tau);
@@ -174,12 +191,19 @@ vlb_status vlb_read_populations(vlb_lattice *lat, double *f);
 vlb_status vlb_read_mask(vlb_lattice *lat, uint8_t *mask);
 
 /* Particle state after the last step and the total force / torque that step
- * applied to it (momentum exchange + polymer traction + conversion
- * momentum + external), FP64.  Any output may be NULL. */
+ * applied to it (Section 3.4: momentum exchange over the particle's
+ * boundary links with lever arm r_b - R, polymer traction, conversion
+ * momentum, external), FP64; position, velocity and spin are those of the
+ * symplectic Euler update.  For fixed geometry (no movable particle) the
+ * last step's sums are evaluated at this call from the state that step
+ * left, which gives the same bits as evaluating them during the step.  Any
+ * output may be NULL.  Errors: VLB_ENOTFOUND (unknown id), VLB_EDEVICE. */
 vlb_status vlb_read_particle(vlb_lattice *lat, int32_t id, double pos[3], double vel[3],
                              double omega[3], double force[3], double torque[3]);
 
-/* FP64 population mass and momentum summed over fluid cells. */
+/* FP64 population mass sum f and momentum sum f c over fluid cells (the
+ * moments of Section 3.1 without the half-force term), the quantities whose
+ * conservation the coupling of Sections 3.3 and 3.4 is built to keep. */
 vlb_status vlb_read_sums(vlb_lattice *lat, double *mass, double momentum[3]);
 
 /* Momentum exchange + polymer traction of the last step summed over all wall

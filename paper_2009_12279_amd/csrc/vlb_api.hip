@@ -1,6 +1,7 @@
 // Host runtime of libvlb: the C ABI of include/vlb.h over the gfx950 kernels.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -112,12 +113,14 @@ struct vlb_lattice {
     std::vector<double> wfield_h; // host copy, for checkpoints
     float *d_gfield = nullptr;    // per-cell force density, 3 planes of g.plane (null: none)
     std::vector<float> gfield_h;  // host copy [3][N], for checkpoints
-    // graph replays of kGraphSteps steps, one per starting buffer parity,
-    // with the step arguments and launch shape they were captured with
+    // graph replays of 32, 16, 8, 4, 2 and 1 steps for each starting buffer
+    // parity, with the step arguments and launch shape they were captured
+    // with
     uint32_t *d_step = nullptr;   // base step the replayed kernels add their offset to
-    hipGraphExec_t gexec[2] = {nullptr, nullptr};
-    vlb::StepArgs gkey[2];
-    int gshape[2][3] = {{0, 0, 0}, {0, 0, 0}};  // tile rows, z chunk, path flags
+    hipGraphExec_t gexec[2][6] = {{nullptr}, {nullptr}};  // [parity][log2 length]
+    bool gvalid = false;
+    vlb::StepArgs gkey;
+    int gshape[3] = {0, 0, 0};    // tile rows, z chunk, path flags
     bool graph_broken = false;    // capture failed once: keep launching step by step
     Particle *d_parts = nullptr;
     double *d_partials = nullptr;
@@ -294,11 +297,12 @@ void free_all(vlb_lattice *lat)
         for (void *p : state)
             if (p)
                 (void)hipFree(p);
-    for (hipGraphExec_t &x : lat->gexec)
-        if (x) {
-            (void)hipGraphExecDestroy(x);
-            x = nullptr;
-        }
+    for (auto &row : lat->gexec)
+        for (hipGraphExec_t &x : row)
+            if (x) {
+                (void)hipGraphExecDestroy(x);
+                x = nullptr;
+            }
     void *ptrs[] = {lat->d_wall,   lat->d_parts, lat->d_partials, lat->d_out,
                     lat->d_counters, lat->d_pforce, lat->d_count, lat->d_g3,
                     lat->d_wfield, lat->d_gfield, lat->d_step};
@@ -777,9 +781,9 @@ vlb_status vlb_add_sphere(vlb_lattice *lat, const double center[3], double radiu
 
 namespace {
 
-// Steps per graph replay (even, so that a replay leaves the buffer parity
-// as it found it).
-constexpr int kGraphSteps = 32;
+// Graph replays hold 2^level steps, level 0..kGraphLevels-1 (1 .. 32 steps),
+// so that any step count runs as a few replays.
+constexpr int kGraphLevels = 6;
 
 bool graphs_enabled()
 {
@@ -844,17 +848,17 @@ hipError_t launch_step(vlb_lattice *lat, const vlb::StepArgs &a, bool counter, i
     return e;
 }
 
-// Record the kGraphSteps steps that start at parity `par` into a graph
+// Record the `len` steps that start at parity `par` into a graph
 // executable; kernels take their step index as *d_step + offset.
-hipError_t capture_steps(vlb_lattice *lat, const vlb::StepArgs &base, int par, bool counter,
-                         int tile_rows, uint32_t z_chunk, hipGraphExec_t *out)
+hipError_t capture_steps(vlb_lattice *lat, const vlb::StepArgs &base, int par, int len,
+                         bool counter, int tile_rows, uint32_t z_chunk, hipGraphExec_t *out)
 {
     hipStream_t st = lat->stream;
     hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess)
         return e;
     hipError_t le = hipSuccess;
-    for (int k = 0; k < kGraphSteps && le == hipSuccess; ++k) {
+    for (int k = 0; k < len && le == hipSuccess; ++k) {
         vlb::StepArgs a = base;
         set_planes(lat, a, (par + k) & 1);
         a.step = static_cast<uint32_t>(k);
@@ -872,43 +876,50 @@ hipError_t capture_steps(vlb_lattice *lat, const vlb::StepArgs &base, int par, b
     return le;
 }
 
-// One replay of kGraphSteps steps from the lattice's current step and
-// parity; the graph is captured again when the step arguments or the launch
-// shape differ from those it was captured with.
-hipError_t replay_steps(vlb_lattice *lat, const vlb::StepArgs &base, bool counter)
+// One replay of 2^level steps from the lattice's current step and parity.
+// Every graph (each length, both parities) is captured again at once when
+// the step arguments or the launch shape differ from those they were
+// captured with, so that a change costs one capture round and no later
+// call of another length captures inside a caller's timed loop.
+hipError_t replay_steps(vlb_lattice *lat, const vlb::StepArgs &base, bool counter, int level)
 {
-    const int par = lat->cur;
     const int tile_rows = fv_tile_rows();
     const uint32_t z_chunk = fv_z_chunk();
     hipError_t e = hipSuccess;
     if (!lat->d_step && (e = hipMalloc(&lat->d_step, sizeof(uint32_t))) != hipSuccess)
         return e;
     vlb::StepArgs key = base;
-    set_planes(lat, key, par);
+    set_planes(lat, key, 0);
     key.step = 0;
     key.step_dev = lat->d_step;
     const int flags = (lat->any_movable ? 1 : 0) | (counter ? 2 : 0);
-    if (!lat->gexec[par] || std::memcmp(&key, &lat->gkey[par], sizeof key) != 0 ||
-        lat->gshape[par][0] != tile_rows || lat->gshape[par][1] != static_cast<int>(z_chunk) ||
-        lat->gshape[par][2] != flags) {
-        if (lat->gexec[par]) {
-            (void)hipGraphExecDestroy(lat->gexec[par]);
-            lat->gexec[par] = nullptr;
-        }
-        if ((e = capture_steps(lat, base, par, counter, tile_rows, z_chunk, &lat->gexec[par])) !=
-            hipSuccess) {
-            lat->gexec[par] = nullptr;
-            return e;
-        }
-        std::memcpy(&lat->gkey[par], &key, sizeof key);
-        lat->gshape[par][0] = tile_rows;
-        lat->gshape[par][1] = static_cast<int>(z_chunk);
-        lat->gshape[par][2] = flags;
+    if (!lat->gvalid || std::memcmp(&key, &lat->gkey, sizeof key) != 0 ||
+        lat->gshape[0] != tile_rows || lat->gshape[1] != static_cast<int>(z_chunk) ||
+        lat->gshape[2] != flags) {
+        lat->gvalid = false;
+        for (int par = 0; par < 2; ++par)
+            for (int lv = 0; lv < kGraphLevels; ++lv) {
+                hipGraphExec_t &x = lat->gexec[par][lv];
+                if (x) {
+                    (void)hipGraphExecDestroy(x);
+                    x = nullptr;
+                }
+                if ((e = capture_steps(lat, base, par, 1 << lv, counter, tile_rows, z_chunk,
+                                       &x)) != hipSuccess) {
+                    x = nullptr;
+                    return e;
+                }
+            }
+        std::memcpy(&lat->gkey, &key, sizeof key);
+        lat->gshape[0] = tile_rows;
+        lat->gshape[1] = static_cast<int>(z_chunk);
+        lat->gshape[2] = flags;
+        lat->gvalid = true;
     }
     if ((e = vlb::launch_set_step(lat->d_step, static_cast<uint32_t>(lat->step), 0,
                                   lat->stream)) != hipSuccess)
         return e;
-    return hipGraphLaunch(lat->gexec[par], lat->stream);
+    return hipGraphLaunch(lat->gexec[lat->cur][level], lat->stream);
 }
 
 }  // namespace
@@ -964,20 +975,28 @@ vlb_status vlb_step(vlb_lattice *lat, int64_t n_steps)
             lat->events.push_back(e);
         }
     }
-    // Steps replay from a graph in chunks of kGraphSteps that no health check
-    // falls inside; the same kernels with the same arguments run (the particle
-    // path is driven from device memory alone), so the results are the same
-    // bits.
+    // Steps replay from graphs in chunks of 32, 16, ..., 1 steps (the
+    // largest that fits both the steps left and the steps to the next
+    // health check); the same kernels with the same arguments run (the
+    // particle path is driven from device memory alone), so the results are
+    // the same bits as step-by-step launches.
     const bool graph_ok = !lat->timing && !lat->graph_broken && graphs_enabled();
     int64_t s = 0;
     while (s < n_steps) {
         const int64_t ci = lat->check_interval;
-        const bool check_inside = ci > 0 && (lat->step / ci + 1) * ci < lat->step + kGraphSteps;
-        if (graph_ok && n_steps - s >= kGraphSteps && !check_inside) {
-            const hipError_t e = replay_steps(lat, a, counter);
+        int64_t room = n_steps - s;
+        if (ci > 0)
+            room = std::min<int64_t>(room, ci - lat->step % ci);
+        int level = kGraphLevels - 1;
+        while ((int64_t(1) << level) > room)
+            --level;
+        if (graph_ok) {
+            const hipError_t e = replay_steps(lat, a, counter, level);
             if (e == hipSuccess) {
-                lat->step += kGraphSteps;
-                s += kGraphSteps;
+                const int len = 1 << level;
+                lat->step += len;
+                s += len;
+                lat->cur ^= len & 1;
                 if (lat->any_movable)
                     lat->mask_h_valid = false;
                 if (ci > 0 && lat->step % ci == 0) {
@@ -1411,6 +1430,28 @@ vlb_status vlb_load(const char *path, void *stream, vlb_lattice **out)
     std::fclose(fp);
     if (!ok)
         return fail(nullptr, VLB_EINVAL, "vlb_load: truncated checkpoint");
+    // The restored records drive kernels that index the particle table by
+    // mask byte and divide by mass and inertia: reject a mask byte naming a
+    // particle beyond the table and records that are not finite, positive
+    // spheres.
+    for (uint64_t n = 0; n < N; ++n)
+        if (mask[n] >= vlb::PART0 && mask[n] - vlb::PART0 >= h.n_parts)
+            return fail(nullptr, VLB_EINVAL, "vlb_load: mask names a particle beyond the table");
+    bool movable = false;
+    for (const Particle &P : parts) {
+        bool finite = std::isfinite(P.radius) && std::isfinite(P.mass) && std::isfinite(P.inertia);
+        for (int a = 0; a < 3; ++a)
+            finite = finite && std::isfinite(P.R[a]) && std::isfinite(P.v[a]) &&
+                     std::isfinite(P.w[a]) && std::isfinite(P.fext[a]) &&
+                     std::isfinite(P.text[a]) && std::isfinite(P.fconv[a]) &&
+                     std::isfinite(P.tconv[a]);
+        if (!finite || !(P.radius > 0.0) || !(P.mass > 0.0) || !(P.inertia > 0.0) ||
+            (P.movable != 0 && P.movable != 1))
+            return fail(nullptr, VLB_EINVAL, "vlb_load: invalid particle record");
+        movable = movable || P.movable;
+    }
+    if ((h.any_movable != 0) != movable)
+        return fail(nullptr, VLB_EINVAL, "vlb_load: movable flag disagrees with the particles");
     // create on a particle-free mask, then restore the saved mask verbatim
     std::vector<uint8_t> base(mask);
     for (auto &m : base)

@@ -135,3 +135,68 @@ def test_create_with_buffers_checks_them_on_the_host():
     with pytest.raises(vlb.VlbError) as ei:
         vlb.vlb_create_with_buffers(shape, mask, [p + 4 for p in fake], sizes)
     assert ei.value.status == vlb.VLB_EINVAL
+
+
+class _CkptHeader(ctypes.Structure):
+    """Leading record of a checkpoint file, as vlb_save writes it."""
+    _fields_ = [("magic", ctypes.c_uint64), ("dims", ctypes.c_int32 * 6),
+                ("storage", ctypes.c_int32), ("n_walls", ctypes.c_int32),
+                ("n_parts", ctypes.c_int32), ("polymer", ctypes.c_int32),
+                ("step", ctypes.c_int64), ("params", ctypes.c_double * 7),
+                ("scale", ctypes.c_float), ("any_movable", ctypes.c_int32),
+                ("rounding", ctypes.c_int32), ("seed", ctypes.c_uint32),
+                ("counter_force", ctypes.c_int32), ("extrap", ctypes.c_int32),
+                ("alpha", ctypes.c_double), ("L2", ctypes.c_double),
+                ("wall_field", ctypes.c_int32), ("force_field", ctypes.c_int32)]
+
+
+def _particle_record(radius=2.0, mass=30.0, movable=0):
+    # R, v, w, radius, mass, inertia (12 doubles), movable + pad, then ten
+    # 3-vectors of forces and torques
+    d = np.zeros(12)
+    d[0:3] = 3.5
+    d[9], d[10], d[11] = radius, mass, 0.4 * mass * radius ** 2
+    return d.tobytes() + np.array([movable, 0], np.int32).tobytes() + np.zeros(30).tobytes()
+
+
+def _checkpoint(path, mask_byte=0, n_parts=1, any_movable=0, **rec):
+    shape = (8, 8, 8)
+    N = 8 * 8 * 8
+    h = _CkptHeader()
+    h.magic = 0x37304B434C424C56
+    h.dims[:] = [8, 8, 8, 1, 1, 1]
+    h.storage, h.n_parts, h.any_movable = 0, n_parts, any_movable
+    h.params[:] = [1 / 3, 0.0, 1.0, 3 / 16, 0.0, 0.0, 0.0]
+    h.scale, h.rounding = 1.0, 1
+    mask = np.zeros(N, np.uint8)
+    mask[100] = mask_byte
+    with open(path, "wb") as fp:
+        fp.write(bytes(h))
+        fp.write(np.zeros(64 * 3).tobytes())
+        for _ in range(n_parts):
+            fp.write(_particle_record(**rec))
+        fp.write(mask.tobytes())
+        fp.write(np.zeros(19 * N, np.float32).tobytes())
+        fp.write(np.zeros(12 * N, np.float32).tobytes())
+    return shape
+
+
+@pytest.mark.parametrize("case", ["mask_beyond_table", "zero_mass", "nan_radius",
+                                  "movable_flag_mismatch"])
+def test_load_rejects_inconsistent_particle_records_on_the_host(tmp_path, case):
+    """A checkpoint whose mask names a particle beyond the table, whose
+    particle records are not finite positive spheres, or whose movable flag
+    disagrees with the records is refused before any device work."""
+    p = str(tmp_path / "bad.ckpt")
+    if case == "mask_beyond_table":
+        _checkpoint(p, mask_byte=64 + 1, n_parts=1)
+    elif case == "zero_mass":
+        _checkpoint(p, mass=0.0)
+    elif case == "nan_radius":
+        _checkpoint(p, radius=float("nan"))
+    else:
+        _checkpoint(p, any_movable=1, movable=0)
+    h = vlb._P()
+    st = vlb.lib().vlb_load(p.encode(), None, ctypes.byref(h))
+    assert st == vlb.VLB_EINVAL
+    assert "vlb_load" in vlb.vlb_last_error(None)

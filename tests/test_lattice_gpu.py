@@ -143,9 +143,9 @@ def test_checkpoint_keeps_wall_velocity_and_force_fields(tmp_path):
 @pytest.mark.parametrize("storage,tile,moving", [("f32", "4", False), ("f32", "-4", False),
                                                  ("f16", "4", False), ("f32", "4", True)])
 def test_graph_replays_give_the_same_bits(monkeypatch, storage, tile, moving):
-    """Steps replayed from captured graphs (chunks of 32) against the same
-    steps launched one by one: bitwise equal after every call, across health
-    checks inside and at the end of chunks, a parameter change (a new
+    """Steps replayed from captured graphs (chunks of 32, 16, ..., 1 steps)
+    against the same steps launched one by one: bitwise equal after every
+    call of any length, across health checks, a parameter change (a new
     capture) and both starting buffer parities; with a fixed sphere, or with
     a moving sphere under the counter-force (the particle path in the
     graph)."""
@@ -167,7 +167,7 @@ def test_graph_replays_give_the_same_bits(monkeypatch, storage, tile, moving):
         L.set_check_interval(50)
         L.init_equilibrium()
         out = []
-        for n in (100, 37, 64):
+        for n in (100, 37, 5, 20, 64):
             L.step(n)
             out.append((L.populations(), L.stress()))
             if moving:
@@ -177,7 +177,7 @@ def test_graph_replays_give_the_same_bits(monkeypatch, storage, tile, moving):
         L.step(65)
         out.append((L.populations(), L.stress()))
         out.append((L.mask(), L.mask()))
-        assert L.step_count == 266
+        assert L.step_count == 291
         runs.append(out)
         L.close()
     for (fa, ta), (fb, tb) in zip(*runs):
