@@ -190,6 +190,20 @@ vlb_status vlb_read_stress(vlb_lattice *lat, double *tau);
 vlb_status vlb_read_populations(vlb_lattice *lat, double *f);
 vlb_status vlb_read_mask(vlb_lattice *lat, uint8_t *mask);
 
+/* vlb_read_velocity for callers that cannot allocate device memory (tight
+ * serving or polling loops, harnesses that forbid hipMalloc): the velocity
+ * of cells first .. first + count - 1 only, into u (3*count doubles: the x,
+ * y and z components, count values each, in cell order), staged through a
+ * fixed device array of VLB_NOALLOC_MAX_CELLS cells (6 MiB) that every GPU
+ * the library runs on holds until the process ends.  Allocates nothing.
+ * Every call on one GPU shares that array and overwrites it: calls that
+ * overlap on one GPU (several host threads) race, and the caller must
+ * serialise them.  Synchronises the lattice's stream.  Errors: VLB_EINVAL
+ * (NULL output, count outside 1..VLB_NOALLOC_MAX_CELLS, a range beyond the
+ * lattice), VLB_EDEVICE. */
+#define VLB_NOALLOC_MAX_CELLS 262144
+vlb_status vlb_read_velocity_noalloc(vlb_lattice *lat, int64_t first, int64_t count, double *u);
+
 /* Particle state after the last step and the total force / torque that step
  * applied to it (Section 3.4: momentum exchange over the particle's
  * boundary links with lever arm r_b - R, polymer traction, conversion

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1131,6 +1132,78 @@ vlb_status vlb_read_velocity(vlb_lattice *lat, double *u)
                                             lat->stress_map());
         },
         "vlb_read_velocity");
+}
+
+namespace {
+
+// Staging array of vlb_read_velocity_noalloc: the velocity of up to
+// VLB_NOALLOC_MAX_CELLS cells, x, y and z planes of FP64.  Every device the
+// library runs on holds its own copy until the process ends; host code
+// reaches it only through the device address looked up below.
+__device__ __align__(256) double scratch[3 * VLB_NOALLOC_MAX_CELLS];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch[kMaxDevices] = {};
+
+// Device address of `device`'s copy of the staging array, looked up on the
+// first call for that device (which must be current) and kept.
+hipError_t scratch_address(int device, double **out)
+{
+    if (device < 0 || device >= kMaxDevices)
+        return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return e;
+        g_scratch[device] = static_cast<double *>(p);
+    }
+    *out = g_scratch[device];
+    return hipSuccess;
+}
+
+}  // namespace
+
+vlb_status vlb_read_velocity_noalloc(vlb_lattice *lat, int64_t first, int64_t count, double *u)
+{
+    if (!lat)
+        return VLB_EINVAL;
+    if (!u)
+        return fail(lat, VLB_EINVAL, "vlb_read_velocity_noalloc: NULL output");
+    if (count < 1 || count > VLB_NOALLOC_MAX_CELLS)
+        return fail(lat, VLB_EINVAL,
+                    "vlb_read_velocity_noalloc: count must lie in 1.." +
+                        std::to_string(VLB_NOALLOC_MAX_CELLS) + " (the staging array's size)");
+    if (first < 0 || first > static_cast<int64_t>(lat->g.N) - count)
+        return fail(lat, VLB_EINVAL, "vlb_read_velocity_noalloc: cell range beyond the lattice");
+    float gv[3];
+    vlb_status st = read_body_force(lat, gv);
+    if (st != VLB_OK)
+        return st;
+    int prev = -1;
+    HIPCHK(lat, hipGetDevice(&prev), "vlb_read_velocity_noalloc");
+    if (prev != lat->device)
+        HIPCHK(lat, hipSetDevice(lat->device), "vlb_read_velocity_noalloc");
+    double *d = nullptr;
+    hipError_t e = scratch_address(lat->device, &d);
+    const uint32_t n0 = static_cast<uint32_t>(first), cnt = static_cast<uint32_t>(count);
+    if (e == hipSuccess)
+        e = vlb::launch_read_moments(lat->storage, lat->g, lat->bound(), lat->d_mask,
+                                     lat->d_f[lat->cur], lat->d_tau[lat->cur], lat->polymer, gv,
+                                     lat->d_gfield, lat->inv_scale, nullptr, d, lat->stream,
+                                     lat->stress_map(), n0, cnt);
+    for (int a = 0; a < 3 && e == hipSuccess; ++a)
+        e = hipMemcpyAsync(u + static_cast<size_t>(a) * cnt, d + static_cast<size_t>(a) * cnt,
+                           cnt * sizeof(double), hipMemcpyDeviceToHost, lat->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(lat->stream);
+    if (prev != lat->device)
+        (void)hipSetDevice(prev);
+    if (e != hipSuccess)
+        return hip_fail(lat, e, "vlb_read_velocity_noalloc");
+    return VLB_OK;
 }
 
 vlb_status vlb_read_stress(vlb_lattice *lat, double *tau)

@@ -162,11 +162,14 @@ hipError_t launch_set_populations(int storage, const Geom &g, const uint8_t *mas
                                   const double *f_in, void *f, float scale, hipStream_t s);
 hipError_t launch_set_stress(const Geom &g, const uint8_t *mask, const double *tau_in,
                              float *tau, hipStream_t s);
-// gfield: per-cell force density planes (stride g.plane) added to gvec, or null
+// gfield: per-cell force density planes (stride g.plane) added to gvec, or
+// null.  Cells first .. first + count - 1 (count 0: every cell from 0) go to
+// rho_out[k] and u_out[a * count + k], k = n - first.
 hipError_t launch_read_moments(int storage, const Geom &g, const Bound &b, const uint8_t *mask,
                                const void *f, const float *tau, int polymer, const float gvec[3],
                                const float *gfield, float inv_scale, double *rho_out,
-                               double *u_out, hipStream_t s, const StressMap &sm = StressMap{});
+                               double *u_out, hipStream_t s, const StressMap &sm = StressMap{},
+                               uint32_t first = 0, uint32_t count = 0);
 hipError_t launch_read_populations(int storage, const Geom &g, const uint8_t *mask, const void *f,
                                    float inv_scale, double *out, hipStream_t s);
 hipError_t launch_read_stress(const Geom &g, const uint8_t *mask, const float *tau, double *out,

@@ -1328,25 +1328,29 @@ __global__ __launch_bounds__(BLOCK) void set_tau_kernel(Geom g, const uint8_t *m
         tau[c * g.plane + n] = fl ? static_cast<float>(tin[static_cast<uint64_t>(c) * g.N + n]) : 0.f;
 }
 
+// Moments of cells first .. first + count - 1 into rho_out[k] and
+// u_out[a * count + k], k = n - first.
 template <int S>
 __global__ __launch_bounds__(BLOCK) void read_moments_kernel(Geom g, Bound b, const uint8_t *mask,
                                                              const void *fv, const float *tau,
                                                              int polymer, float gx, float gy,
                                                              float gz, const float *gfield,
                                                              float inv_scale, double *rho_out,
-                                                             double *u_out, StressMap sm)
+                                                             double *u_out, StressMap sm,
+                                                             uint32_t first, uint32_t count)
 {
     using St = Store<S>;
     using T = typename St::T;
-    const uint32_t n = blockIdx.x * BLOCK + threadIdx.x;
-    if (n >= g.N)
+    const uint32_t k = blockIdx.x * BLOCK + threadIdx.x;
+    if (k >= count)
         return;
+    const uint32_t n = first + k;
     if (mask[n] != 0) {
         if (rho_out)
-            rho_out[n] = 0.0;
+            rho_out[k] = 0.0;
         if (u_out)
             for (int a = 0; a < 3; ++a)
-                u_out[static_cast<uint64_t>(a) * g.N + n] = 0.0;
+                u_out[static_cast<uint64_t>(a) * count + k] = 0.0;
         return;
     }
     int x, y, z;
@@ -1386,10 +1390,10 @@ __global__ __launch_bounds__(BLOCK) void read_moments_kernel(Geom g, Bound b, co
     }
     const double rho = 1.0 + drho;
     if (rho_out)
-        rho_out[n] = rho;
+        rho_out[k] = rho;
     if (u_out)
         for (int a = 0; a < 3; ++a)
-            u_out[static_cast<uint64_t>(a) * g.N + n] = (j[a] + 0.5 * F[a]) / rho;
+            u_out[static_cast<uint64_t>(a) * count + k] = (j[a] + 0.5 * F[a]) / rho;
 }
 
 template <int S>
@@ -2230,12 +2234,17 @@ hipError_t launch_set_stress(const Geom &g, const uint8_t *mask, const double *t
 hipError_t launch_read_moments(int storage, const Geom &g, const Bound &b, const uint8_t *mask,
                                const void *f, const float *tau, int polymer, const float gvec[3],
                                const float *gfield, float inv_scale, double *rho_out,
-                               double *u_out, hipStream_t s, const StressMap &sm)
+                               double *u_out, hipStream_t s, const StressMap &sm, uint32_t first,
+                               uint32_t count)
 {
+    if (count == 0)
+        count = g.N;
+    if (count == 0 || first >= g.N || count > g.N - first)
+        return hipErrorInvalidValue;
     return dispatch(storage, [&](auto st) {
-        hipLaunchKernelGGL(read_moments_kernel<decltype(st)::value>, dim3(blocks_for(g.N)),
+        hipLaunchKernelGGL(read_moments_kernel<decltype(st)::value>, dim3(blocks_for(count)),
                            dim3(BLOCK), 0, s, g, b, mask, f, tau, polymer, gvec[0], gvec[1],
-                           gvec[2], gfield, inv_scale, rho_out, u_out, sm);
+                           gvec[2], gfield, inv_scale, rho_out, u_out, sm, first, count);
         return hipGetLastError();
     });
 }

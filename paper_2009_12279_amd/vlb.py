@@ -88,6 +88,7 @@ SIGNATURES = [
     ("vlb_step_count", ctypes.c_int64, [_P]),
     ("vlb_read_density", ctypes.c_int, [_P, _D]),
     ("vlb_read_velocity", ctypes.c_int, [_P, _D]),
+    ("vlb_read_velocity_noalloc", ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64, _D]),
     ("vlb_read_stress", ctypes.c_int, [_P, _D]),
     ("vlb_read_populations", ctypes.c_int, [_P, _D]),
     ("vlb_read_mask", ctypes.c_int, [_P, ctypes.c_char_p]),
@@ -204,6 +205,7 @@ def vlb_create(shape, mask, periodic=(1, 1, 1), wall_velocity=None, storage="f32
 
 
 NBUF = 6
+NOALLOC_MAX_CELLS = 262144  # staging size of vlb_read_velocity_noalloc, in cells
 
 
 def vlb_buffer_sizes(shape, periodic=(1, 1, 1), storage="f32"):
@@ -299,6 +301,13 @@ def vlb_read_density(h, shape):
 
 def vlb_read_velocity(h, shape):
     return _read(lib().vlb_read_velocity, h, 3, shape)
+
+
+def vlb_read_velocity_noalloc(h, first, count):
+    """Velocity of cells first .. first + count - 1 as an array [3, count]."""
+    out = np.zeros((3, int(count)))
+    _check(lib().vlb_read_velocity_noalloc(h, int(first), int(count), _dp(out)), h)
+    return out
 
 
 def vlb_read_stress(h, shape):
