@@ -39,10 +39,22 @@ POP_BYTES = {"f32": 4, "f16": 2, "bf16": 2}
 def algorithmic_bytes(storage):
     p = POP_BYTES[storage]
     return {
+        "fused_step": 2 * 19 * p + 2 * 6 * 4 + 1,    # the whole step in one kernel
         "stream_collide": 2 * 19 * p + 6 * 4 + 1,   # populations r+w, stress read, mask
         "stress_update": 6 * 4,                      # stress write
         "step": 2 * 19 * p + 2 * 6 * 4 + 1,          # whole step (201 B for FP32)
     }
+
+
+def kernel_times(lat, particles=False):
+    """Per-launch device times (ms) the library measured with HIP events on
+    its stream: the fused step kernel, or stream-collide and stress update
+    when the step ran as two kernels."""
+    t0, t1 = lat.kernel_time_ms(0), lat.kernel_time_ms(1)
+    k = {"fused_step": t0} if t1 < 0 else {"stream_collide": t0, "stress_update": t1}
+    if particles:
+        k["particles"] = lat.kernel_time_ms(2)
+    return k
 
 
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "step_256cubed_hbm_traffic.md")
@@ -130,13 +142,15 @@ def run_gpu(args, law=None):
     lat.set_timing(True)
     lat.step(args.steps)
     torch.cuda.synchronize()
-    k_ms = {"stream_collide": lat.kernel_time_ms(0), "stress_update": lat.kernel_time_ms(1)}
+    k_ms = kernel_times(lat)
     lat.set_timing(False)
     health = lat.check_health()
     alg = algorithmic_bytes(args.storage)
     dom = max(k_ms, key=lambda k: k_ms[k])
     per_kernel = {k: alg[k] * N / (v * 1e-3) / 1e9 for k, v in k_ms.items() if v > 0}
-    step_achieved = alg["step"] * N / (ms_per_step * 1e-3) / 1e9
+    # the step's bytes over the step's kernel time (the events around each
+    # kernel of the step, summed), so that the figure is the kernels' own
+    step_achieved = alg["step"] * N / (sum(k_ms.values()) * 1e-3) / 1e9
     lat.close()
     return dict(N=N, fluid=fluid, shape=shape, params=params, ms_per_step=ms_per_step, mlups=mlups,
                 wall_s=wall, kernels=k_ms, dominant=dom, per_kernel=per_kernel,
@@ -160,8 +174,7 @@ def _time_lattice(lat, args, stream):
     lat.set_timing(True)
     lat.step(args.steps)
     torch.cuda.synchronize()
-    k_ms = {"stream_collide": lat.kernel_time_ms(0), "stress_update": lat.kernel_time_ms(1),
-            "particles": lat.kernel_time_ms(2)}
+    k_ms = kernel_times(lat, particles=True)
     lat.set_timing(False)
     return ms, {k: round(v, 5) for k, v in k_ms.items()}
 
@@ -400,6 +413,8 @@ def main():
                     help="skip timing the same workload with FP16 and BF16 population storage")
     ap.add_argument("--no-law-variants", action="store_true",
                     help="skip timing the same workload with the Giesekus and FENE-P laws")
+    ap.add_argument("--no-fused-prototype", action="store_true",
+                    help="skip timing the fused single-pass step (same bits, slower, opt-in)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (torch) so that hardware byte "
                          "counters can be scaled against a kernel of known traffic")
@@ -418,6 +433,18 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    fused = None
+    if not args.no_fused_prototype:
+        # the fused single-pass step the library runs only when asked
+        os.environ["VLB_FUSED"] = "1"
+        try:
+            v = run_gpu(args)
+        finally:
+            del os.environ["VLB_FUSED"]
+        fused = dict(ms_per_step=round(v["ms_per_step"], 4), mlups=round(v["mlups"], 1),
+                     kernel_ms={k: round(x, 5) for k, x in v["kernels"].items()},
+                     step_hbm_frac=round(v["step_achieved"] / HBM_PEAK_GBS, 4),
+                     note="same bits as the default two-kernel step; opt-in (VLB_FUSED=1)")
     variants = None
     if not args.no_storage_variants:
         # the precision pattern: the same workload with 16-bit population storage
@@ -430,9 +457,7 @@ def main():
                 ms_per_step=round(v["ms_per_step"], 4), mlups=round(v["mlups"], 1),
                 kernel_ms={k: round(x, 5) for k, x in v["kernels"].items()},
                 algorithmic_bytes_per_cell=v["alg"],
-                stream_collide_hbm_frac=round(
-                    v["alg"]["stream_collide"] * v["N"] / (v["kernels"]["stream_collide"] * 1e-3)
-                    / 8e12, 4))
+                step_hbm_frac=round(v["step_achieved"] / HBM_PEAK_GBS, 4))
     laws = None
     if not args.no_law_variants:
         # the other constitutive laws through the same stress update
@@ -497,6 +522,7 @@ def main():
                            for k, v in g["per_kernel"].items()},
         },
         "cpu_baseline": cpu,
+        "fused_step_prototype": fused,
         "storage_variants": variants,
         "law_variants": laws,
         "moving_particle": moving,

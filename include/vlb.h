@@ -248,7 +248,12 @@ const char *vlb_last_error(const vlb_lattice *lat);
 
 /* Average device time of the last vlb_step call per kernel family, measured
  * with HIP events on the lattice's stream when timing is on (ms; -1 when not
- * measured).  which: 0 = stream-collide, 1 = stress update, 2 = particles. */
+ * measured).  which: 0 = stream-collide, or the fused step kernel that also
+ * runs the stress update (VLB_FUSED=1 in the environment selects it for
+ * polymer lattices that fill the chip with its tiles, -1 for every polymer
+ * lattice; it gives the same bits as the two kernels and is slower on
+ * MI355X, so it is off by default), 1 = stress update (-1 when it ran fused
+ * or there is no polymer), 2 = particles. */
 vlb_status vlb_set_timing(vlb_lattice *lat, int32_t on);
 
 /* Giesekus constitutive law (Section 2.2 names it among the models the

@@ -91,6 +91,24 @@ uint32_t fv_z_chunk()
     return static_cast<uint32_t>(v > 0 && v < 65536 ? v : 16);
 }
 
+// Fused step (stream-collide and stress update in one kernel, the same
+// bits, measured slower than the two kernels): 0 (default) never, 1 where
+// the lattice fills the chip with its tiles, -1 for every polymer lattice.
+// VLB_FUSED selects it, VLB_STEP_ZC sets the planes per chunk (0 = the
+// kernel's default); both are read at every step.
+int fused_mode()
+{
+    const char *e = std::getenv("VLB_FUSED");
+    return e ? std::atoi(e) : 0;
+}
+
+uint32_t step_z_chunk()
+{
+    const char *e = std::getenv("VLB_STEP_ZC");
+    const long v = e ? std::atol(e) : 0;
+    return static_cast<uint32_t>(v > 0 && v < 65536 ? v : 0);
+}
+
 size_t storage_bytes(int storage) { return storage == vlb::ST_F32 ? 4 : 2; }
 
 float default_scale(int storage) { return storage == vlb::ST_F16 ? 1024.f : 1.f; }
@@ -163,6 +181,7 @@ struct vlb_lattice {
     int64_t check_interval = 1000;
     bool unstable = false;
     bool timing = false;
+    bool fused_last = false;  // the last step launched ran the fused kernel
     double ktime[3] = {-1.0, -1.0, -1.0};
     std::vector<hipEvent_t> events;
     std::string err = "no error";
@@ -810,6 +829,8 @@ void set_planes(const vlb_lattice *lat, vlb::StepArgs &a, int cur)
     }
     for (int c = 0; c < 3; ++c)
         a.u_p[c] = a.u + c * lat->g.plane;
+    a.fdelta = static_cast<const char *>(a.fout) - static_cast<const char *>(a.fin);
+    a.tdelta = reinterpret_cast<const char *>(a.tout) - reinterpret_cast<const char *>(a.tin);
 }
 
 // The kernels of one step, in order: stream-collide, stress update, and for
@@ -818,7 +839,7 @@ void set_planes(const vlb_lattice *lat, vlb::StepArgs &a, int cur)
 // events before stream-collide, before the stress update, before the
 // particle path and after it.
 hipError_t launch_step(vlb_lattice *lat, const vlb::StepArgs &a, bool counter, int tile_rows,
-                       uint32_t z_chunk, hipEvent_t *ev)
+                       uint32_t z_chunk, hipEvent_t *ev, bool *fused_out = nullptr)
 {
     hipStream_t st = lat->stream;
     hipError_t e = hipSuccess;
@@ -827,10 +848,20 @@ hipError_t launch_step(vlb_lattice *lat, const vlb::StepArgs &a, bool counter, i
             e = hipEventRecord(ev[k], st);
     };
     rec(0);
-    if (e == hipSuccess)
+    const int fm = fused_mode();
+    bool fused = false;
+    if (e == hipSuccess && lat->polymer && fm != 0) {
+        e = vlb::launch_step_fused(lat->storage, a, st, step_z_chunk(), fm < 0);
+        fused = e == hipSuccess;
+        if (e == hipErrorNotSupported)
+            e = hipSuccess;
+    }
+    if (fused_out)
+        *fused_out = fused;
+    if (e == hipSuccess && !fused)
         e = vlb::launch_lb_step(lat->storage, a, st);
     rec(1);
-    if (e == hipSuccess && lat->polymer)
+    if (e == hipSuccess && lat->polymer && !fused)
         e = vlb::launch_fv_step(lat->storage, a, st, tile_rows, z_chunk);
     rec(2);
     if (e == hipSuccess && lat->any_movable) {
@@ -893,7 +924,8 @@ hipError_t replay_steps(vlb_lattice *lat, const vlb::StepArgs &base, bool counte
     set_planes(lat, key, 0);
     key.step = 0;
     key.step_dev = lat->d_step;
-    const int flags = (lat->any_movable ? 1 : 0) | (counter ? 2 : 0);
+    const int flags = (lat->any_movable ? 1 : 0) | (counter ? 2 : 0) | ((fused_mode() + 1) << 2) |
+                      static_cast<int>(step_z_chunk() << 4);
     if (!lat->gvalid || std::memcmp(&key, &lat->gkey, sizeof key) != 0 ||
         lat->gshape[0] != tile_rows || lat->gshape[1] != static_cast<int>(z_chunk) ||
         lat->gshape[2] != flags) {
@@ -1017,7 +1049,10 @@ vlb_status vlb_step(vlb_lattice *lat, int64_t n_steps)
         a.step = static_cast<uint32_t>(lat->step);
         a.step_dev = nullptr;
         hipEvent_t *ev = lat->timing ? &lat->events[nev * s] : nullptr;
-        HIPCHK(lat, launch_step(lat, a, counter, fv_tile_rows(), fv_z_chunk(), ev), "step launch");
+        bool fused = false;
+        HIPCHK(lat, launch_step(lat, a, counter, fv_tile_rows(), fv_z_chunk(), ev, &fused),
+               "step launch");
+        lat->fused_last = fused;
         if (lat->any_movable)
             lat->mask_h_valid = false;
         lat->cur ^= 1;
@@ -1044,6 +1079,8 @@ vlb_status vlb_step(vlb_lattice *lat, int64_t n_steps)
         }
         for (int k = 0; k < 3; ++k)
             lat->ktime[k] = acc[k] / static_cast<double>(n_steps);
+        if (lat->fused_last || !lat->polymer)
+            lat->ktime[1] = -1.0;  // no separate stress-update launch
     }
     return VLB_OK;
 }

@@ -115,6 +115,10 @@ struct StepArgs {
     uint32_t step;           // step index (random stream of the rounding); with
                              // step_dev, the offset added to *step_dev
     const uint32_t *step_dev = nullptr;  // base step read on the device (graph replays)
+    // bytes from the input to the output population and stress buffers: the
+    // fused step reaches its output planes as input plane + offset, so that
+    // it keeps half as many plane pointers in scalar registers
+    int64_t fdelta = 0, tdelta = 0;
     uint32_t seed;
 };
 
@@ -156,6 +160,17 @@ hipError_t launch_batch_step(const BatchTable *t, uint32_t max_blocks, int stoch
 // kernel.
 hipError_t launch_fv_step(int storage, const StepArgs &a, hipStream_t s, int tile_rows,
                           uint32_t z_chunk);
+// Fused stream-collide + stress update of one step (64 x 4 tiles marching
+// through chunks of z_chunk planes, 0 = 32, shortened to fill the chip) for a
+// polymer lattice large enough to fill the chip with such tiles, or any
+// polymer lattice when forced; hipErrorNotSupported, with nothing launched,
+// otherwise.  step_fused_fits tells which without launching.  It gives the
+// bits of the two-kernel step; on MI355X it is slower (the ring of
+// neighbour velocities it recomputes costs more than the velocity round
+// trip it saves), so the step runs it only when asked.
+bool step_fused_fits(const Geom &g, uint32_t z_chunk, bool force, uint32_t *zc_out);
+hipError_t launch_step_fused(int storage, const StepArgs &a, hipStream_t s, uint32_t z_chunk,
+                             bool force);
 hipError_t launch_init_equilibrium(int storage, const Geom &g, const uint8_t *mask,
                                    const double *u, void *f, float scale, hipStream_t s);
 hipError_t launch_set_populations(int storage, const Geom &g, const uint8_t *mask,

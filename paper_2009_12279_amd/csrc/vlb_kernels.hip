@@ -541,45 +541,84 @@ __device__ void reflect_links(const A &a, typename Store<S>::T *fout, uint32_t n
 #define FV_OCCUPANCY
 #endif
 
-// Stream-collide of cell n of the lattice described by `a`, at step `step`
-// (the step only seeds the rounding stream).
-template <int S, bool SR, bool FENE, class A>
-__device__ __forceinline__ void lb_cell(const A &a, uint32_t n, uint32_t step)
-{
-    const Geom g = geom_copy(a.g);
-    using St = Store<S>;
-    using T = typename St::T;
-    using R = typename St::R;
-    const uint8_t *__restrict__ mask = a.mask;
-    int x, y, z;
-    coords(g, n, x, y, z);
-    const Delta d(g, x, y, z);
+// Plane addresses of the step kernels.  ArgPlanes: the argument block's own
+// plane pointers.  BasePlanes (fused step): every plane from one base
+// pointer per buffer and the plane stride, output planes at a fixed offset
+// from the input ones; the fused kernel hides the base from the optimiser
+// once per plane, so that the plane addresses are formed where they are
+// used instead of being held in scalar registers across the whole loop.
+template <class A>
+struct ArgPlanes {
+    const A &a;
+    __device__ __forceinline__ const void *fin(int i) const { return a.fin_p[i]; }
+    __device__ __forceinline__ void *fout(int i) const { return a.fout_p[i]; }
+    __device__ __forceinline__ const float *tin(int c) const { return a.tin_p[c]; }
+    __device__ __forceinline__ float *tout(int c) const { return a.tout_p[c]; }
+};
 
-    // Every load is issued before any result is used (all addresses are in
-    // bounds, also for solid cells), so a wave has all its memory requests
-    // in flight at once.
-    // pull: f_i(x) sits in plane i at x - c_i
+struct BasePlanes {
+    const char *f;   // input population buffer
+    uint64_t fpb;    // bytes per population plane
+    int64_t fdelta;  // output population buffer - input
+    const char *t;   // input stress buffer
+    uint64_t tpb;    // bytes per stress plane
+    int64_t tdelta;  // output stress buffer - input
+    __device__ __forceinline__ const void *fin(int i) const { return f + i * fpb; }
+    __device__ __forceinline__ void *fout(int i) const
+    {
+        return const_cast<char *>(f) + i * fpb + fdelta;
+    }
+    __device__ __forceinline__ const float *tin(int c) const
+    {
+        return reinterpret_cast<const float *>(t + c * tpb);
+    }
+    __device__ __forceinline__ float *tout(int c) const
+    {
+        return reinterpret_cast<float *>(const_cast<char *>(t) + c * tpb + tdelta);
+    }
+};
+
+// Inputs of one cell's stream-collide, all loaded before any is used: the
+// 19 pulled populations, which neighbours are solid (and which of those are
+// particles), and the stored stress of the cell and of its face neighbours.
+template <bool FENE>
+struct LbIn {
     float f[Q];
+    uint32_t links, plinks;  // bit j: the neighbour along c_j is solid / a particle
+    float town[6];           // the cell's stored stress variable
+    float tn[3][2][3];       // row k of the stored stress of the neighbours along +/- e_k
+    float tdg[3][2][2];      // FENE-P: those neighbours' other two diagonal entries
+};
+
+// Issue every load of cell n's stream-collide (all addresses are in bounds,
+// also for solid cells, so a wave has all its memory requests in flight at
+// once).  ALL_LINKS: the solid flag of all 18 neighbours (bounce-back);
+// otherwise only of the six face neighbours (enough for the polymer force).
+template <int S, bool FENE, bool ALL_LINKS, class A, class PL>
+__device__ __forceinline__ void lb_load(const A &a, const PL &pl, uint32_t n, const Delta &d,
+                                        LbIn<FENE> &in)
+{
+    using T = typename Store<S>::T;
+    const uint8_t *__restrict__ mask = a.mask;
+    // pull: f_i(x) sits in plane i at x - c_i
 #pragma unroll
     for (int i = 0; i < Q; ++i)
-        f[i] = ldp<S>(static_cast<const T *>(a.fin_p[i]), d.at(n, -CX[i], -CY[i], -CZ[i]),
-                      a.inv_scale);
-    // solid neighbours along every direction, and which of them are particles
-    uint32_t links = 0, plinks = 0;
+        in.f[i] = ldp<S>(static_cast<const T *>(pl.fin(i)), d.at(n, -CX[i], -CY[i], -CZ[i]),
+                         a.inv_scale);
+    in.links = 0;
+    in.plinks = 0;
 #pragma unroll
     for (int j = 1; j < Q; ++j) {
+        if (!ALL_LINKS && j > 6)
+            continue;
         const uint8_t mj = mask[d.at(n, CX[j], CY[j], CZ[j])];
-        links |= (mj != 0 ? 1u : 0u) << j;
-        plinks |= (mj >= PART0 ? 1u : 0u) << j;
+        in.links |= (mj != 0 ? 1u : 0u) << j;
+        in.plinks |= (mj >= PART0 ? 1u : 0u) << j;
     }
-    // stress of the face neighbours and of the cell itself (for the
-    // constant extrapolation into solid neighbours)
-    float tn[3][2][3], town[6];
-    float tdg[3][2][2];  // FENE-P: the other two diagonal entries of each face neighbour
     if (a.polymer) {
 #pragma unroll
         for (int c = 0; c < 6; ++c)
-            town[c] = *elem(a.tin_p[c], n);
+            in.town[c] = *elem(pl.tin(c), n);
 #pragma unroll
         for (int k = 0; k < 3; ++k)
 #pragma unroll
@@ -588,42 +627,53 @@ __device__ __forceinline__ void lb_cell(const A &a, uint32_t n, uint32_t step)
                 const uint32_t m = d.at(n, sg * (k == 0), sg * (k == 1), sg * (k == 2));
 #pragma unroll
                 for (int j = 0; j < 3; ++j)
-                    tn[k][side][j] = *elem(a.tin_p[TROW[k][j]], m);
+                    in.tn[k][side][j] = *elem(pl.tin(TROW[k][j]), m);
                 if (FENE) {
-                    tdg[k][side][0] = *elem(a.tin_p[(k + 1) % 3], m);
-                    tdg[k][side][1] = *elem(a.tin_p[(k + 2) % 3], m);
+                    in.tdg[k][side][0] = *elem(pl.tin((k + 1) % 3), m);
+                    in.tdg[k][side][1] = *elem(pl.tin((k + 2) % 3), m);
                 }
             }
     }
-    auto pop = [&](int i) -> float { return f[i]; };
-    if (mask[n] != 0)
-        return;
+}
 
-    // polymer force: sum over faces of the face-averaged stress times the
-    // outward normal, a solid face neighbour taking this cell's stress; in
-    // FP32 (a difference of stresses, small next to the populations)
+// Force density on fluid cell n: body force (the device value under the
+// counter-force), per-cell force field, and the polymer force (Section 3.3):
+// the sum over faces of the face-averaged stress times the outward normal, a
+// solid face neighbour taking the extrapolated stress of this cell, formed in
+// FP32 (a difference of stresses, small next to the populations).  With
+// FENE-P the stored variables in `in` are mapped to the polymer stress in
+// place.
+template <class R, bool FENE, class A>
+__device__ __forceinline__ void lb_force(const A &a, uint32_t n, const Delta &d, LbIn<FENE> &in,
+                                         R F[3])
+{
+    // contraction within an expression only (same bits wherever inlined)
+#pragma clang fp contract(on)
+    const Geom g = geom_copy(a.g);
+    const uint8_t *__restrict__ mask = a.mask;
+    const uint32_t links = in.links;
     float Fp[3] = {0.f, 0.f, 0.f};
     if (a.polymer) {
         if (FENE) {
             // polymer stress from the stored variable: T (1 + g1) + epl g1 I,
             // g1 = c tr T / (l2m3 - c tr T), at this cell and its neighbours
             const float c = a.sm.c, l2m3 = a.sm.l2m3, epl = a.sm.epl;
-            const float tr0 = town[0] + town[1] + town[2];
+            const float tr0 = in.town[0] + in.town[1] + in.town[2];
             const float g0 = c * tr0 / (l2m3 - c * tr0);
 #pragma unroll
             for (int k = 0; k < 3; ++k)
 #pragma unroll
                 for (int side = 0; side < 2; ++side) {
-                    const float tr = tn[k][side][k] + tdg[k][side][0] + tdg[k][side][1];
+                    const float tr = in.tn[k][side][k] + in.tdg[k][side][0] + in.tdg[k][side][1];
                     const float g1 = c * tr / (l2m3 - c * tr);
 #pragma unroll
                     for (int j = 0; j < 3; ++j)
-                        tn[k][side][j] = fmaf(tn[k][side][j], g1, tn[k][side][j]) +
-                                         (j == k ? epl * g1 : 0.f);
+                        in.tn[k][side][j] = fmaf(in.tn[k][side][j], g1, in.tn[k][side][j]) +
+                                            (j == k ? epl * g1 : 0.f);
                 }
 #pragma unroll
             for (int q = 0; q < 6; ++q)
-                town[q] = fmaf(town[q], g0, town[q]) + (q < 3 ? epl * g0 : 0.f);
+                in.town[q] = fmaf(in.town[q], g0, in.town[q]) + (q < 3 ? epl * g0 : 0.f);
         }
         // face bits of `links`: +x 1, -x 2, +y 3, -y 4, +z 5, -z 6
         if (a.sm.extrap && ((links >> 1) & 63u)) {
@@ -657,13 +707,13 @@ __device__ __forceinline__ void lb_cell(const A &a, uint32_t n, uint32_t step)
                 }
 #pragma unroll
                 for (int j = 0; j < 3; ++j) {
-                    const float own = town[TROW[k][j]];
-                    const float ep = quad ? fmaf(3.f, own - tn[k][1][j], t2[j])
-                                          : 2.f * own - tn[k][1][j];
-                    const float em = quad ? fmaf(3.f, own - tn[k][0][j], t2[j])
-                                          : 2.f * own - tn[k][0][j];
-                    const float vp = sp ? (sm ? own : ep) : tn[k][0][j];
-                    const float vm = sm ? (sp ? own : em) : tn[k][1][j];
+                    const float own = in.town[TROW[k][j]];
+                    const float ep = quad ? fmaf(3.f, own - in.tn[k][1][j], t2[j])
+                                          : 2.f * own - in.tn[k][1][j];
+                    const float em = quad ? fmaf(3.f, own - in.tn[k][0][j], t2[j])
+                                          : 2.f * own - in.tn[k][0][j];
+                    const float vp = sp ? (sm ? own : ep) : in.tn[k][0][j];
+                    const float vm = sm ? (sp ? own : em) : in.tn[k][1][j];
                     Fp[j] += 0.5f * (vp - vm);
                 }
             }
@@ -673,8 +723,8 @@ __device__ __forceinline__ void lb_cell(const A &a, uint32_t n, uint32_t step)
                 const bool sp = (links >> (2 * k + 1)) & 1u, sm = (links >> (2 * k + 2)) & 1u;
 #pragma unroll
                 for (int j = 0; j < 3; ++j) {
-                    const float own = town[TROW[k][j]];
-                    Fp[j] += 0.5f * ((sp ? own : tn[k][0][j]) - (sm ? own : tn[k][1][j]));
+                    const float own = in.town[TROW[k][j]];
+                    Fp[j] += 0.5f * ((sp ? own : in.tn[k][0][j]) - (sm ? own : in.tn[k][1][j]));
                 }
             }
         }
@@ -696,17 +746,31 @@ __device__ __forceinline__ void lb_cell(const A &a, uint32_t n, uint32_t step)
         g3[1] += static_cast<double>(*elem(a.gf_p[1], n));
         g3[2] += static_cast<double>(*elem(a.gf_p[2], n));
     }
-    const R Fx = static_cast<R>(g3[0]) + static_cast<R>(Fp[0]);
-    const R Fy = static_cast<R>(g3[1]) + static_cast<R>(Fp[1]);
-    const R Fz = static_cast<R>(g3[2]) + static_cast<R>(Fp[2]);
+    F[0] = static_cast<R>(g3[0]) + static_cast<R>(Fp[0]);
+    F[1] = static_cast<R>(g3[1]) + static_cast<R>(Fp[1]);
+    F[2] = static_cast<R>(g3[2]) + static_cast<R>(Fp[2]);
+}
 
-    // moments in deviation form from opposite-pair sums and differences:
-    // rho = 1 + h_0 + sum (h_i + h_o), rho u = sum c_i (h_i - h_o) + F/2
-    R drho = static_cast<R>(pop(0)), jx = 0, jy = 0, jz = 0;
+// Moments in deviation form from opposite-pair sums and differences
+// (Section 3.1 with the half force): rho = 1 + h_0 + sum (h_i + h_o),
+// rho u = sum c_i (h_i - h_o) + F/2.
+template <class R>
+struct Moments {
+    R drho, rho, ux, uy, uz;
+};
+
+template <class R>
+__device__ __forceinline__ Moments<R> lb_moments(const float f[Q], const R F[3])
+{
+    // contraction within an expression only, so that the stream-collide of a
+    // cell and the moments of the same cell computed elsewhere (the ring of
+    // a fused step) give the same bits
+#pragma clang fp contract(on)
+    R drho = static_cast<R>(f[0]), jx = 0, jy = 0, jz = 0;
 #pragma unroll
     for (int k = 0; k < Q / 2; ++k) {
         const int i = 2 * k + 1;
-        const R a_ = static_cast<R>(pop(i)), b_ = static_cast<R>(pop(i + 1));
+        const R a_ = static_cast<R>(f[i]), b_ = static_cast<R>(f[i + 1]);
         drho += a_ + b_;
         const R df = a_ - b_;
         if (CX[i])
@@ -716,11 +780,81 @@ __device__ __forceinline__ void lb_cell(const A &a, uint32_t n, uint32_t step)
         if (CZ[i])
             jz += CZ[i] * df;
     }
-    const R rho = R(1) + drho;
-    const R inv_rho = R(1) / rho;
-    const R ux = (jx + R(0.5) * Fx) * inv_rho;
-    const R uy = (jy + R(0.5) * Fy) * inv_rho;
-    const R uz = (jz + R(0.5) * Fz) * inv_rho;
+    Moments<R> m;
+    m.drho = drho;
+    m.rho = R(1) + drho;
+    const R inv_rho = R(1) / m.rho;
+    m.ux = (jx + R(0.5) * F[0]) * inv_rho;
+    m.uy = (jy + R(0.5) * F[1]) * inv_rho;
+    m.uz = (jz + R(0.5) * F[2]) * inv_rho;
+    return m;
+}
+
+// Velocity u^n of cell n at (x, y, z) alone (the moments of its
+// stream-collide, no stores): into uo, and the cell's stored stress
+// variable into to (zero without polymer).  Returns false for a solid cell
+// (uo zero).
+template <int S, bool FENE, class A, class PL>
+__device__ __forceinline__ bool lb_velocity(const A &a, const PL &pl, uint32_t n, int x, int y,
+                                            int z, float uo[3], float to[6])
+{
+    using R = typename Store<S>::R;
+    const Geom g = geom_copy(a.g);
+    const Delta d(g, x, y, z);
+    LbIn<FENE> in;
+    lb_load<S, FENE, false>(a, pl, n, d, in);
+#pragma unroll
+    for (int c = 0; c < 6; ++c)
+        to[c] = a.polymer ? in.town[c] : 0.f;
+    if (a.mask[n] != 0) {
+        uo[0] = uo[1] = uo[2] = 0.f;
+        return false;
+    }
+    R F[3];
+    lb_force<R, FENE>(a, n, d, in, F);
+    const Moments<R> mo = lb_moments<R>(in.f, F);
+    uo[0] = static_cast<float>(mo.ux);
+    uo[1] = static_cast<float>(mo.uy);
+    uo[2] = static_cast<float>(mo.uz);
+    return true;
+}
+
+// Stream-collide of cell n at (x, y, z) of the lattice described by `a`, at
+// step `step` (the step only seeds the rounding stream).  Arithmetic in R
+// (FP64 for FP32 storage, FP32 for half storage); the pulled populations
+// stay in FP32 registers (exact) to keep occupancy up.  FUSED: the velocity
+// and the cell's stored stress go to uo / to (for a fused stress update)
+// instead of the velocity planes, and the output planes are reached from
+// the input planes.  Returns false for a solid cell.
+template <int S, bool SR, bool FENE, bool FUSED, class A, class PL>
+__device__ __forceinline__ bool lb_cell(const A &a, const PL &pl, uint32_t n, int x, int y, int z,
+                                        uint32_t step, float uo[3], float to[6])
+{
+    const Geom g = geom_copy(a.g);
+    using St = Store<S>;
+    using T = typename St::T;
+    using R = typename St::R;
+    const Delta d(g, x, y, z);
+    auto out_plane = [&](int i) -> T * { return static_cast<T *>(pl.fout(i)); };
+    LbIn<FENE> in;
+    lb_load<S, FENE, true>(a, pl, n, d, in);
+    if (FUSED) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c)
+            to[c] = a.polymer ? in.town[c] : 0.f;
+    }
+    if (a.mask[n] != 0) {
+        if (FUSED)
+            uo[0] = uo[1] = uo[2] = 0.f;
+        return false;
+    }
+    R F[3];
+    lb_force<R, FENE>(a, n, d, in, F);
+    const R Fx = F[0], Fy = F[1], Fz = F[2];
+    const Moments<R> mo = lb_moments<R>(in.f, F);
+    const R drho = mo.drho, rho = mo.rho, ux = mo.ux, uy = mo.uy, uz = mo.uz;
+    auto pop = [&](int i) -> float { return in.f[i]; };
+    const uint32_t links = in.links, plinks = in.plinks;
     const R uu = ux * ux + uy * uy + uz * uz;
     const R uF = ux * Fx + uy * Fy + uz * Fz;
     const R wp = static_cast<R>(a.wp), wm = static_cast<R>(a.wm);
@@ -750,7 +884,7 @@ __device__ __forceinline__ void lb_cell(const A &a, uint32_t n, uint32_t step)
                                       : (a.b.moving ? (a.b.walls_move ? links : plinks) : 0u);
     const uint32_t fast = links & ~slow;
     Rng rng(n, step, a.seed);
-    stp<S, SR>(static_cast<T *>(a.fout_p[0]), n,
+    stp<S, SR>(out_plane(0), n,
                R(2) * a1 * static_cast<R>(pop(0)) + static_cast<R>(WD[0]) * P1, a.scale,
                rhi(rng.next32()));
     // one 32-bit random word per opposite pair, a 16-bit half each
@@ -763,8 +897,8 @@ __device__ __forceinline__ void lb_cell(const A &a, uint32_t n, uint32_t step)
         const R cF = CX[i] * Fx + CY[i] * Fy + CZ[i] * Fz;
         const R np = a1 * (a_ + b_) + w * (P1 + cu * (Q1 * cu + C9 * cF));
         const R nm = b1 * (a_ - b_) + w * (M3 * cu + C3 * cF);
-        T *pi = static_cast<T *>(a.fout_p[i]);
-        T *po = static_cast<T *>(a.fout_p[o]);
+        T *pi = out_plane(i);
+        T *po = out_plane(o);
         const uint32_t r = rng.next32();
         stp<S, SR>(pi, n, np + nm, a.scale, rhi(r));
         stp<S, SR>(po, n, np - nm, a.scale, rlo(r));
@@ -779,11 +913,16 @@ __device__ __forceinline__ void lb_cell(const A &a, uint32_t n, uint32_t step)
     if (slow)
         reflect_links<S, SR>(a, static_cast<T *>(a.fout), n, d, slow, rho, rng);
 
-    if (a.polymer) {
+    if (FUSED) {
+        uo[0] = static_cast<float>(ux);
+        uo[1] = static_cast<float>(uy);
+        uo[2] = static_cast<float>(uz);
+    } else if (a.polymer) {
         *elem(a.u_p[0], n) = static_cast<float>(ux);
         *elem(a.u_p[1], n) = static_cast<float>(uy);
         *elem(a.u_p[2], n) = static_cast<float>(uz);
     }
+    return true;
 }
 
 template <int S, bool SR, bool FENE>
@@ -792,7 +931,10 @@ __global__ __launch_bounds__(BLOCK) LB_OCCUPANCY(S) void lb_step_kernel(StepArgs
     const uint32_t n = block_id(a.lb_remap, a.slab_blocks) * BLOCK + threadIdx.x;
     if (n >= a.g.N)
         return;
-    lb_cell<S, SR, FENE>(a, n, a.step_dev ? *a.step_dev + a.step : a.step);
+    int x, y, z;
+    coords(a.g, n, x, y, z);
+    lb_cell<S, SR, FENE, false>(a, ArgPlanes<StepArgs>{a}, n, x, y, z,
+                                a.step_dev ? *a.step_dev + a.step : a.step, nullptr, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -807,8 +949,8 @@ __global__ __launch_bounds__(BLOCK) LB_OCCUPANCY(S) void lb_step_kernel(StepArgs
 // the same bits.  LAW selects the constitutive law at compile time: 0
 // Oldroyd-B, 1 Giesekus, 2 FENE-P.
 constexpr int LAW_OB = 0, LAW_GIESEKUS = 1, LAW_FENE = 2;
-template <bool SR, int LAW, class A>
-__device__ __forceinline__ void fv_compute(const A &a, const Geom &g, uint32_t n, int x, int y, int z,
+template <bool SR, int LAW, class A, class PL>
+__device__ __forceinline__ void fv_compute(const PL &pl, const A &a, const Geom &g, uint32_t n, int x, int y, int z,
                                            uint32_t step, const float u0[3], const float t0[6],
                                            float un[3][2][3], const float tn[3][2][6],
                                            uint32_t solid)
@@ -933,7 +1075,7 @@ __device__ __forceinline__ void fv_compute(const A &a, const Geom &g, uint32_t n
         const double v = static_cast<double>(t0[c]) + static_cast<double>(inc);
         if (!(c & 1))
             r = rng.next32();
-        stp<ST_F32, SR>(a.tout_p[c], n, v, 1.f, (c & 1) ? rlo(r) : rhi(r));
+        stp<ST_F32, SR>(pl.tout(c), n, v, 1.f, (c & 1) ? rlo(r) : rhi(r));
     }
 }
 
@@ -970,7 +1112,7 @@ __device__ __forceinline__ void fv_cell(const A &a, uint32_t n, uint32_t step)
         }
     if (mask[n] != 0)
         return;
-    fv_compute<SR, LAW>(a, g, n, x, y, z, step, u0, t0, un, tn, solid);
+    fv_compute<SR, LAW>(ArgPlanes<A>{a}, a, g, n, x, y, z, step, u0, t0, un, tn, solid);
 }
 
 template <bool SR, int LAW>
@@ -1178,7 +1320,8 @@ __global__ __launch_bounds__(FV_TX * TY) FV_OCCUPANCY void fv_tile_kernel(StepAr
             solid |= (N[9] != 0.f ? 1u : 0u) << 4;
             solid |= (P[9] != 0.f ? 1u : 0u) << 5;
             const uint32_t n = own_xy + static_cast<uint32_t>(z) * nxy;
-            fv_compute<SR, LAW>(a, g, n, x, y, z, step, u0, t0, un, tn, solid);
+            fv_compute<SR, LAW>(ArgPlanes<StepArgs>{a}, a, g, n, x, y, z, step, u0, t0, un, tn,
+                                solid);
         }
         if (more) {
 #pragma unroll
@@ -1192,6 +1335,184 @@ __global__ __launch_bounds__(FV_TX * TY) FV_OCCUPANCY void fv_tile_kernel(StepAr
             if (hslot >= 0)
                 fv_load(a, halo_xy + static_cast<uint32_t>(z + 1) * nxy, HV);
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Fused step: stream-collide and stress update in one pass.  The stress
+// update of a cell needs the velocity u^n of its six face neighbours, which
+// the same step computes; instead of a round trip through HBM the block
+// computes what it needs itself.  A block owns a 64 x TY tile of the x-y
+// plane and marches through a chunk of z-planes.  For plane z it runs the
+// stream-collide of its tile cells, computes only the moments (u^n) of the
+// one-cell ring of x-y face neighbours around the tile from their pulled
+// populations (the same code the owner runs, so the same bits), and stages
+// velocity, stored stress and solid flag of tile and ring in LDS.  The stress
+// update of plane z - 1 follows, from the staged planes z - 2, z - 1 and z.
+// The tile's columns at the planes just outside the chunk get moments only.
+// Per cell HBM sees the populations read and written once, the stress read
+// once and written once and the mask: the algorithmic bytes; the ring's
+// pulls are L2 hits on data the neighbouring tiles read.
+//
+// LDS holds three planes: the write of plane z + 1 can then overlap the
+// stress update of plane z - 1 in other waves, so one barrier per plane
+// suffices (a thread reads other threads' slots only in plane z - 1, and
+// its own slot in planes z - 2 and z).
+
+
+#ifdef VLB_STEP_WAVES
+#define STEP_OCCUPANCY __attribute__((amdgpu_waves_per_eu(VLB_STEP_WAVES)))
+#else
+// Three waves per SIMD, the most the three LDS planes of a 256-thread block
+// allow (at most 168 VGPRs; the compiler's own choice is two)
+#define STEP_OCCUPANCY __attribute__((amdgpu_waves_per_eu(3)))
+#endif
+
+template <int S, bool SR, int LAW, int TX, int TY>
+__global__ __launch_bounds__(TX * TY) STEP_OCCUPANCY void step_tile_kernel(StepArgs a, uint32_t zc)
+{
+    constexpr bool FENE = LAW == LAW_FENE;
+    constexpr int W = TX + 2, SL = W * (TY + 2);
+    constexpr int NRING = 2 * TX + 2 * TY;
+    static_assert(NRING <= TX * TY, "ring larger than the block");
+    __shared__ float lds[3][FV_NV][SL];
+    const Geom g = a.g;
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const uint32_t nxy = static_cast<uint32_t>(nx) * ny;
+    const uint32_t tiles_x = (nx + TX - 1) / TX, tiles_y = (ny + TY - 1) / TY;
+    // block -> (x tile, y tile, z chunk); with the XCD-aware order each of the
+    // 8 XCDs takes a slab of y tiles of every chunk, so the ring rows pulled
+    // from neighbouring tiles are read through its own L2
+    uint32_t tx, ty, cz;
+    const uint32_t b = blockIdx.x;
+    if (a.remap && (tiles_y & 7u) == 0) {
+        const uint32_t y8 = tiles_y >> 3, k = b & 7u, q = b >> 3, per = tiles_x * y8;
+        cz = q / per;
+        const uint32_t r = q - cz * per;
+        ty = k * y8 + r / tiles_x;
+        tx = r % tiles_x;
+    } else {
+        tx = b % tiles_x;
+        const uint32_t t = b / tiles_x;
+        ty = t % tiles_y;
+        cz = t / tiles_y;
+    }
+    const int tid = threadIdx.x, lx = tid % TX, ly = tid / TX;
+    const int x = static_cast<int>(tx) * TX + lx, y = static_cast<int>(ty) * TY + ly;
+    const bool in_tile = x < nx && y < ny;
+    // slots of lanes past the lattice's edge hold the periodically wrapped
+    // cell, as the neighbour deltas of the per-cell kernels do
+    const int wx = wrap_coord(x, nx), wy = wrap_coord(y, ny);
+    const uint32_t own_xy = wx + static_cast<uint32_t>(nx) * wy;
+    const int own_slot = (ly + 1) * W + lx + 1;
+    // ring cell of this thread, if any: thread r takes ring cell r, so the
+    // ring's moments occupy as few waves as possible (a wave issues the same
+    // instructions however many of its lanes are active)
+    int rslot = -1, rx = 0, ry = 0;
+    uint32_t ring_xy = 0;
+    {
+        const int r = tid;
+        if (r < NRING) {
+            const int x0 = static_cast<int>(tx) * TX, y0 = static_cast<int>(ty) * TY;
+            int hx, hy;
+            if (r < 2 * TX) {
+                const int top = r >= TX, c = r % TX;
+                hx = x0 + c;
+                hy = top ? y0 + TY : y0 - 1;
+                rslot = (top ? TY + 1 : 0) * W + c + 1;
+            } else {
+                const int j = r - 2 * TX, right = j >= TY, row = j % TY;
+                hx = right ? x0 + TX : x0 - 1;
+                hy = y0 + row;
+                rslot = (row + 1) * W + (right ? W - 1 : 0);
+            }
+            rx = wrap_coord(hx, nx);
+            ry = wrap_coord(hy, ny);
+            ring_xy = rx + static_cast<uint32_t>(nx) * ry;
+        }
+    }
+    const int z0 = static_cast<int>(cz * zc);
+    const int z1 = min(z0 + static_cast<int>(zc), nz);
+    const uint32_t step = a.step_dev ? *a.step_dev + a.step : a.step;
+    auto put = [&](int buf, int slot, const float u[3], const float t[6], bool fluid) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            lds[buf][j][slot] = u[j];
+#pragma unroll
+        for (int c = 0; c < 6; ++c)
+            lds[buf][3 + c][slot] = t[c];
+        lds[buf][9][slot] = fluid ? 0.f : 1.f;
+    };
+    // plane strides in bytes (every plane is below 4 GiB)
+    const uint32_t fpb = static_cast<uint32_t>(g.plane * sizeof(typename Store<S>::T));
+    const uint32_t tpb = static_cast<uint32_t>(g.plane * sizeof(float));
+    for (int z = z0 - 1; z <= z1; ++z) {
+        const int zz = wrap_coord(z, nz);
+        const int buf = (z - z0 + 1) % 3;
+        const bool body = z >= z0 && z < z1;
+        // plane addresses of this plane, formed where they are used
+        const char *fb = static_cast<const char *>(a.fin);
+        const char *tb = reinterpret_cast<const char *>(a.tin);
+        uint32_t fs = fpb, ts = tpb;
+        asm volatile("" : "+s"(fb), "+s"(tb), "+s"(fs), "+s"(ts));
+        const BasePlanes pl{fb, fs, a.fdelta, tb, ts, a.tdelta};
+        {
+            float uo[3], to[6];
+            const uint32_t n = own_xy + static_cast<uint32_t>(zz) * nxy;
+            const bool fl = (body && in_tile)
+                                ? lb_cell<S, SR, FENE, true>(a, pl, n, x, y, zz, step, uo, to)
+                                : lb_velocity<S, FENE>(a, pl, n, wx, wy, zz, uo, to);
+            put(buf, own_slot, uo, to, fl);
+        }
+        if (body && rslot >= 0) {
+            float uo[3], to[6];
+            const bool fl = lb_velocity<S, FENE>(a, pl, ring_xy + static_cast<uint32_t>(zz) * nxy,
+                                                 rx, ry, zz, uo, to);
+            put(buf, rslot, uo, to, fl);
+        }
+        __syncthreads();
+        // stress update of plane z - 1
+        const int zf = z - 1;
+        if (zf < z0 || zf >= z1 || !in_tile)
+            continue;
+        const int bc = (zf - z0 + 1) % 3, bm = (zf - z0 + 3) % 3, bp = (zf - z0 + 2) % 3;
+        if (lds[bc][9][own_slot] != 0.f)
+            continue;
+        const float u0[3] = {lds[bc][0][own_slot], lds[bc][1][own_slot], lds[bc][2][own_slot]};
+        float t0[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c)
+            t0[c] = lds[bc][3 + c][own_slot];
+        float un[3][2][3], tn[3][2][6];
+        uint32_t solid = 0;
+        const int sl[2][2] = {{own_slot + 1, own_slot - 1}, {own_slot + W, own_slot - W}};
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                const int q = sl[k][side];
+#pragma unroll
+                for (int j = 0; j < 3; ++j)
+                    un[k][side][j] = lds[bc][j][q];
+#pragma unroll
+                for (int c = 0; c < 6; ++c)
+                    tn[k][side][c] = lds[bc][3 + c][q];
+                solid |= (lds[bc][9][q] != 0.f ? 1u : 0u) << (2 * k + side);
+            }
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const int bz = side == 0 ? bp : bm;
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                un[2][side][j] = lds[bz][j][own_slot];
+#pragma unroll
+            for (int c = 0; c < 6; ++c)
+                tn[2][side][c] = lds[bz][3 + c][own_slot];
+            solid |= (lds[bz][9][own_slot] != 0.f ? 1u : 0u) << (4 + side);
+        }
+        const int zfw = wrap_coord(zf, nz);
+        const uint32_t n = own_xy + static_cast<uint32_t>(zfw) * nxy;
+        fv_compute<SR, LAW>(pl, a, g, n, x, y, zfw, step, u0, t0, un, tn, solid);
     }
 }
 
@@ -1230,7 +1551,10 @@ __global__ __launch_bounds__(BLOCK) LB_OCCUPANCY(ST_F32) void lb_batch_kernel(co
     const uint32_t n = (b - bs.first_block) * BLOCK + threadIdx.x;
     if (n >= a.g.N)
         return;
-    lb_cell<ST_F32, SR, false>(a, n, step);
+    int x, y, z;
+    coords(geom_copy(a.g), n, x, y, z);
+    lb_cell<ST_F32, SR, false, false>(a, ArgPlanes<VLB_CONST_AS StepArgs>{a}, n, x, y, z, step,
+                                      nullptr, nullptr);
 }
 
 template <bool SR>
@@ -2177,6 +2501,62 @@ hipError_t launch_fv_step(int storage, const StepArgs &a, hipStream_t s, int til
     else
         with_law(std::false_type{});
     return hipGetLastError();
+}
+
+// Tile of the fused step: 64 x 4 cells (measured faster than 16 x 4, 32 x 4,
+// 64 x 6, 64 x 8 and 64 x 12).
+constexpr int STEP_TX = 64, STEP_TY = 4;
+
+bool step_fused_fits(const Geom &g, uint32_t z_chunk, bool force, uint32_t *zc_out)
+{
+    const int TX = STEP_TX, TY = STEP_TY;
+    // rows that fill the tiles, and enough blocks to fill the chip (chunks
+    // shortened down to 8 planes for that: each chunk computes the moments
+    // of the two planes around it once more)
+    const uint32_t tiles_xy = ((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY);
+    const uint32_t want = 2048u * (256u / (TX * TY));
+    uint32_t zc = z_chunk ? z_chunk : 32u;
+    while (!force && zc > 8 && tiles_xy * ((g.nz + zc - 1) / zc) < want)
+        zc /= 2;
+    const uint32_t lanes_x = ((g.nx + TX - 1) / TX) * TX;
+    const bool rows_fill = 8u * (lanes_x - g.nx) <= lanes_x;
+    if (zc_out)
+        *zc_out = zc;
+    return force || (rows_fill && tiles_xy * ((g.nz + zc - 1) / zc) >= want / 2);
+}
+
+hipError_t launch_step_fused(int storage, const StepArgs &a, hipStream_t s, uint32_t z_chunk,
+                             bool force)
+{
+    uint32_t zc = 0;
+    if (!a.polymer || !step_fused_fits(a.g, z_chunk, force, &zc))
+        return hipErrorNotSupported;
+    const int TX = STEP_TX, TY = STEP_TY;
+    const uint32_t tiles =
+        ((a.g.nx + TX - 1) / TX) * ((a.g.ny + TY - 1) / TY) * ((a.g.nz + zc - 1) / zc);
+    const int law = a.sm.l2m3 > 0.f ? LAW_FENE : (a.gk != 0.f ? LAW_GIESEKUS : LAW_OB);
+    return dispatch(storage, [&](auto st) {
+        constexpr int S = decltype(st)::value;
+        auto go = [&](auto sr, auto lw) {
+            constexpr bool SR = decltype(sr)::value;
+            constexpr int LAW = decltype(lw)::value;
+            hipLaunchKernelGGL((step_tile_kernel<S, SR, LAW, STEP_TX, STEP_TY>), dim3(tiles),
+                               dim3(STEP_TX * STEP_TY), 0, s, a, zc);
+        };
+        auto with_law = [&](auto sr) {
+            if (law == LAW_FENE)
+                go(sr, std::integral_constant<int, LAW_FENE>{});
+            else if (law == LAW_GIESEKUS)
+                go(sr, std::integral_constant<int, LAW_GIESEKUS>{});
+            else
+                go(sr, std::integral_constant<int, LAW_OB>{});
+        };
+        if (a.stochastic)
+            with_law(std::true_type{});
+        else
+            with_law(std::false_type{});
+        return hipGetLastError();
+    });
 }
 
 hipError_t launch_set_step(uint32_t *step, uint32_t value, int add, hipStream_t s)
