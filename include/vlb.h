@@ -300,6 +300,21 @@ vlb_status vlb_set_force_field(vlb_lattice *lat, const double *F);
  * Errors: VLB_EINVAL (non-finite value), VLB_ENOMEM.  Kept in checkpoints. */
 vlb_status vlb_set_wall_velocity_field(vlb_lattice *lat, const double *u);
 
+/* Overlap-fraction smoothing of fluid/solid conversions (Section 3.4 names
+ * smoothing conversions with the fraction of a cell a particle overlaps;
+ * the rule here is this library's reading).  samples = n: each cell's
+ * overlap phi with a movable particle is the share of n^3 evenly spaced
+ * points in the cell that lie inside the sphere.  Each step, a cell that is
+ * fluid and stays fluid while the particle's move raised its overlap from
+ * phi_old to phi_new hands the share (phi_new - phi_old) / (1 - phi_old) of
+ * its stress, in equal parts, to its D3Q19 neighbours that stay fluid;
+ * what a cell still holds when it is covered follows the binary rule.  The
+ * total stress of the fluid is unchanged and the populations are not
+ * touched.  0 (the default) is the binary conversion; 1 samples the cell
+ * centre only and gives the binary conversion's bits through the smoothing
+ * path.  VLB_EINVAL for samples outside 0..8.  Kept in checkpoints. */
+vlb_status vlb_set_conversion_smoothing(vlb_lattice *lat, int32_t samples);
+
 /* Counter-force for periodic systems with free particles (Section 4.5):
  * when on, every step subtracts the summed external force of the movable
  * particles from the body force, spread evenly over the cells that are

@@ -84,6 +84,10 @@ def lib():
         L.or_set_wall_velocity_field.argtypes = [P, D]
         L.or_set_force_field.argtypes = [P, D]
         L.or_set_extrapolation.argtypes = [P, I]
+        L.or_set_conversion_smoothing.restype = I
+        L.or_set_conversion_smoothing.argtypes = [P, I]
+        L.or_overlap_fraction.restype = ctypes.c_double
+        L.or_overlap_fraction.argtypes = [P, I, I, I, I, I]
         L.or_set_threads.argtypes = [I]
         L.or_get_threads.restype = I
         _lib = L
@@ -245,6 +249,16 @@ class Lattice:
     def set_fene_p(self, L2):
         if lib().or_set_fene_p(self._h, float(L2)) != 0:
             raise ValueError("oracle: FENE-P needs L^2 > 3 (or 0 for off)")
+
+    def set_conversion_smoothing(self, samples):
+        """Overlap-fraction smoothing of conversions with samples^3
+        sub-samples per cell (0: binary conversion)."""
+        if lib().or_set_conversion_smoothing(self._h, int(samples)) != 0:
+            raise ValueError("oracle: smoothing samples must lie in 0..8")
+
+    def overlap_fraction(self, pid, x, y, z, samples):
+        return float(lib().or_overlap_fraction(self._h, int(pid), int(x), int(y), int(z),
+                                               int(samples)))
 
     def init_equilibrium(self, u=None):
         if u is None:

@@ -440,6 +440,7 @@ typedef struct {
     double ftau[3], ttau[3];         /* last step: polymer traction */
     double fconv_used[3];            /* last step: conversion momentum applied */
     double ftot[3], ttot[3];         /* last step totals */
+    double Rprev[3];                 /* position before the last update */
 } or_particle;
 
 struct or_lattice {
@@ -468,6 +469,7 @@ struct or_lattice {
     double dropped[6];
     double conv_tau_before[6], conv_tau_after[6];
     int conv_counts[2];
+    int smooth_ns;                   /* overlap sub-samples per axis (0: binary conversion) */
     long step;
 };
 
@@ -622,6 +624,8 @@ int or_add_sphere(or_lattice *L, const double center[3], double radius, double d
     P.mass = density_ratio * 4.0 / 3.0 * M_PI * radius * radius * radius;
     P.inertia = 0.4 * P.mass * radius * radius;
     P.movable = movable ? 1 : 0;
+    for (int a = 0; a < 3; ++a)
+        P.Rprev[a] = center[a];
     int nx = L->n[0], ny = L->n[1], nz = L->n[2];
     /* first pass: refuse overlap with any non-fluid cell */
     for (int z = 0; z < nz; ++z)
@@ -962,6 +966,7 @@ void or_step(or_lattice *L, long n_steps)
             if (!P->movable)
                 continue;
             for (int a = 0; a < 3; ++a) {
+                P->Rprev[a] = P->R[a];
                 P->v[a] += P->ftot[a] / P->mass;
                 P->w[a] += P->ttot[a] / P->inertia;
             }
@@ -989,6 +994,110 @@ void or_step(or_lattice *L, long n_steps)
 
 /* ------------------------------------------------------------------ */
 /* S7: conversion between fluid and solid (Section 3.4) */
+
+/* Fraction of the unit cell around (x, y, z) that a sphere of the given
+ * radius centred at R overlaps, sub-sampled at ns^3 evenly spaced points
+ * (ns = 1: the cell centre alone, i.e. the coverage test itself). */
+static double overlap_fraction(const or_lattice *L, const double R[3], double radius, int x, int y,
+                               int z, int ns)
+{
+    int in = 0;
+    for (int i = 0; i < ns; ++i)
+        for (int j = 0; j < ns; ++j)
+            for (int k = 0; k < ns; ++k) {
+                double pt[3] = {(double)x + ((double)i + 0.5) / (double)ns - 0.5,
+                                (double)y + ((double)j + 0.5) / (double)ns - 0.5,
+                                (double)z + ((double)k + 0.5) / (double)ns - 0.5};
+                double d[3];
+                min_image(L, R, pt, d);
+                double d2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+                if (d2 < radius * radius)
+                    ++in;
+            }
+    return (double)in / (double)(ns * ns * ns);
+}
+
+/* Overlap-fraction smoothing of the stress conversion (Section 3.4 mentions
+ * smoothing conversions with the overlapped fraction of a cell; the reading
+ * is ours).  A cell that is fluid and stays fluid while particle P overlaps
+ * more of it, from phi_old (P at its previous position) to phi_new, hands
+ * the share (phi_new - phi_old) / (1 - phi_old) of its stress, in equal
+ * parts, to its D3Q19 neighbours that stay fluid.  The stress a cell still
+ * holds when it is covered follows the binary rule.  Transfers only, so the
+ * fluid's total stress is unchanged; with one sample per cell phi is 0 or
+ * 1 and nothing is handed over. */
+static void shed_stress(or_lattice *L, const or_particle *P, const unsigned char *old,
+                        const unsigned char *nw)
+{
+    const int nx = L->n[0], ny = L->n[1], nz = L->n[2];
+    const long N = L->N;
+    const int ns = L->smooth_ns;
+    double *share = (double *)calloc((size_t)N, sizeof(double));
+    double *keep = (double *)malloc(sizeof(double) * N);
+    for (long n = 0; n < N; ++n)
+        keep[n] = 1.0;
+#define STAYS(mm) (old[mm] == 0 && nw[mm] == 0)
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                long n = cell(nx, ny, x, y, z);
+                if (!STAYS(n))
+                    continue;
+                double fo = overlap_fraction(L, P->Rprev, P->radius, x, y, z, ns);
+                double fn = overlap_fraction(L, P->R, P->radius, x, y, z, ns);
+                if (!(fn > fo) || !(fo < 1.0))
+                    continue;
+                double q = (fn - fo) / (1.0 - fo);
+                int nf = 0;
+                for (int j = 0; j < Q; ++j)
+                    if (j != REST && STAYS(nbr(nx, ny, nz, x, y, z, C[j])))
+                        ++nf;
+                if (nf == 0)
+                    continue;
+                share[n] = q / nf;
+                keep[n] = 1.0 - q;
+            }
+    double *recv = (double *)malloc(sizeof(double) * N);
+    double *tau = L->tau;
+    for (int c = 0; c < 6; ++c) {
+        for (int z = 0; z < nz; ++z)
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x) {
+                    long n = cell(nx, ny, x, y, z);
+                    recv[n] = 0.0;
+                    if (!STAYS(n))
+                        continue;
+                    for (int j = 0; j < Q; ++j) {
+                        if (j == REST)
+                            continue;
+                        long m = nbr(nx, ny, nz, x, y, z, C[j]);
+                        recv[n] += share[m] * tau[c * N + m];
+                    }
+                }
+        for (long n = 0; n < N; ++n)
+            if (STAYS(n))
+                tau[c * N + n] = keep[n] * tau[c * N + n] + recv[n];
+    }
+#undef STAYS
+    free(recv);
+    free(keep);
+    free(share);
+}
+
+int or_set_conversion_smoothing(or_lattice *L, int ns)
+{
+    if (ns < 0 || ns > 8)
+        return -1;
+    L->smooth_ns = ns;
+    return 0;
+}
+
+double or_overlap_fraction(const or_lattice *L, int id, int x, int y, int z, int ns)
+{
+    if (id < 0 || id >= L->np || ns < 1)
+        return -1.0;
+    return overlap_fraction(L, L->p[id].R, L->p[id].radius, x, y, z, ns);
+}
 
 static void conversion(or_lattice *L)
 {
@@ -1028,6 +1137,10 @@ static void conversion(or_lattice *L)
             if (old[n] == 0)
                 L->conv_tau_before[c] += tau[c * N + n];
     }
+    if (L->smooth_ns > 0)
+        for (int k = 0; k < L->np; ++k)
+            if (L->p[k].movable)
+                shed_stress(L, &L->p[k], old, nw);
     /* covers: populations deleted, their momentum goes to the particle, the
      * stress is shared among the neighbours that stay fluid */
     for (int z = 0; z < nz; ++z)

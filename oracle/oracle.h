@@ -131,6 +131,15 @@ long or_step_count(const or_lattice *L);
  * summed over fluid cells just before and just after it. */
 void or_read_conversion_stats(const or_lattice *L, int counts[2], double tau_before[6],
                               double tau_after[6]);
+/* Overlap-fraction smoothing of conversions (Section 3.4): ns sub-samples
+ * per axis of each cell's overlap with a moving particle, 1..8, or 0 for
+ * the binary conversion (the default).  While a particle overlaps more of
+ * a cell that stays fluid, the cell hands that share of its stress to its
+ * neighbours that stay fluid.  -1 for ns outside 0..8. */
+int or_set_conversion_smoothing(or_lattice *L, int ns);
+/* Overlap fraction of cell (x, y, z) with particle id at its current
+ * position, ns^3 sub-samples (-1 for an unknown id or ns < 1). */
+double or_overlap_fraction(const or_lattice *L, int id, int x, int y, int z, int ns);
 /* Number of threads the oracle's loops may use (OpenMP); 0 = runtime default. */
 void or_set_threads(int n);
 int or_get_threads(void);

@@ -150,6 +150,7 @@ struct vlb_lattice {
     double alpha = 0.0;           // Giesekus mobility
     double L2 = 0.0;              // FENE-P extensibility (0: off)
     int extrap = 0;               // stress extrapolation into solid neighbours
+    int smooth_ns = 0;            // overlap sub-samples per axis of smoothed conversions (0: off)
     vlb::StressMap stress_map() const
     {
         vlb::StressMap m;
@@ -196,6 +197,7 @@ struct vlb_lattice {
         b.n_parts = static_cast<int32_t>(parts_h.size());
         b.moving = (any_movable || moving_walls) ? 1 : 0;
         b.walls_move = moving_walls ? 1 : 0;
+        b.smooth_ns = smooth_ns;
         return b;
     }
 };
@@ -744,6 +746,8 @@ vlb_status vlb_add_sphere(vlb_lattice *lat, const double center[3], double radiu
     P.mass = density_ratio * 4.0 / 3.0 * M_PI * radius * radius * radius;
     P.inertia = 0.4 * P.mass * radius * radius;
     P.movable = movable ? 1 : 0;
+    for (int a = 0; a < 3; ++a)
+        P.Rprev[a] = center[a];
     const int id = static_cast<int>(cur.size());
     const int n[3] = {lat->g.nx, lat->g.ny, lat->g.nz};
     // cells with |x - R|^2 < r^2, searched over the sphere's bounding box
@@ -871,7 +875,7 @@ hipError_t launch_step(vlb_lattice *lat, const vlb::StepArgs &a, bool counter, i
                                         lat->d_pforce, st, lat->stress_map());
         if (e == hipSuccess)
             e = vlb::launch_conversion(lat->storage, lat->g, a.b, lat->d_mask, a.fout, a.tout,
-                                       lat->scale, lat->inv_scale, lat->d_counters, st);
+                                       lat->scale, lat->inv_scale, lat->d_counters, lat->d_u, st);
         if (e == hipSuccess && counter)
             e = vlb::launch_body_force(lat->g, lat->d_mask, lat->d_parts, np,
                                        lat->params.body_force, lat->d_count, lat->d_g3, st);
@@ -1396,7 +1400,7 @@ vlb_status vlb_set_check_interval(vlb_lattice *lat, int64_t steps)
 // checkpoint
 
 namespace {
-constexpr uint64_t kMagic = 0x37304B434C424C56ull;  // "VLBLCK07"
+constexpr uint64_t kMagic = 0x38304B434C424C56ull;  // "VLBLCK08"
 
 struct FileHeader {
     uint64_t magic;
@@ -1414,6 +1418,8 @@ struct FileHeader {
     double L2;
     int32_t wall_field;   // 1: 3*N doubles of per-cell wall velocity follow the walls
     int32_t force_field;  // 1: 3*N floats of per-cell force density follow
+    int32_t smooth_ns;    // overlap-fraction smoothing of conversions
+    int32_t pad;
 
 };
 }  // namespace
@@ -1475,6 +1481,7 @@ vlb_status vlb_save(vlb_lattice *lat, const char *path)
     h.extrap = lat->extrap;
     h.wall_field = lat->d_wfield ? 1 : 0;
     h.force_field = lat->d_gfield ? 1 : 0;
+    h.smooth_ns = lat->smooth_ns;
     bool ok = std::fwrite(&h, sizeof h, 1, fp) == 1;
     ok = ok && std::fwrite(lat->wall_h.data(), sizeof(double), 64 * 3, fp) == 64 * 3;
     ok = ok && (!h.wall_field || std::fwrite(lat->wfield_h.data(), sizeof(double), 3 * N, fp) ==
@@ -1597,6 +1604,7 @@ vlb_status vlb_load(const char *path, void *stream, vlb_lattice **out)
     lat->alpha = (h.alpha >= 0.0 && h.alpha <= 0.5) ? h.alpha : 0.0;
     lat->L2 = (h.L2 > 3.0 && std::isfinite(h.L2)) ? h.L2 : 0.0;
     lat->extrap = (h.extrap >= 0 && h.extrap <= 2) ? h.extrap : 0;
+    lat->smooth_ns = (h.smooth_ns >= 0 && h.smooth_ns <= 8) ? h.smooth_ns : 0;
     lat->scale = h.scale;
     lat->inv_scale = 1.f / h.scale;
     hipError_t e = hipMemcpyAsync(lat->d_mask, mask.data(), N, hipMemcpyHostToDevice, lat->stream);
@@ -1742,6 +1750,16 @@ vlb_status vlb_set_wall_velocity_field(vlb_lattice *lat, const double *u)
             moving = u[n] != 0.0 || u[N + n] != 0.0 || u[2 * N + n] != 0.0;
     }
     lat->moving_walls = moving;
+    return VLB_OK;
+}
+
+vlb_status vlb_set_conversion_smoothing(vlb_lattice *lat, int32_t samples)
+{
+    if (!lat)
+        return VLB_EINVAL;
+    if (samples < 0 || samples > 8)
+        return fail(lat, VLB_EINVAL, "vlb_set_conversion_smoothing: samples must lie in 0..8");
+    lat->smooth_ns = samples;
     return VLB_OK;
 }
 

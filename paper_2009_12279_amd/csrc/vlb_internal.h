@@ -45,6 +45,7 @@ struct Particle {
     double fmex[3], tmex[3];    // last step: momentum exchange
     double ftau[3], ttau[3];    // last step: polymer traction
     double ftot[3], ttot[3];    // last step: total applied
+    double Rprev[3];            // position before the last update
 };
 
 // Geometry common to every kernel.
@@ -65,6 +66,9 @@ struct Bound {
     int32_t n_parts;
     int32_t moving;          // any moving wall or movable particle
     int32_t walls_move = 0;  // some wall moves (a nonzero table entry or a per-cell field)
+    // overlap-fraction smoothing of conversions: sub-samples per axis of a
+    // cell's overlap with a moving particle (0: binary conversion)
+    int32_t smooth_ns = 0;
 };
 
 // Map from the stored stress variable to the polymer stress.  Identity for
@@ -208,9 +212,11 @@ hipError_t launch_particle_forces(int storage, const Geom &g, const uint8_t *mas
 hipError_t launch_wall_force(int storage, const Geom &g, const uint8_t *mask, const void *f,
                              const float *tau_n, int polymer, float inv_scale, double *partials,
                              double *out, hipStream_t s, const StressMap &sm = StressMap{});
-// Fluid/solid conversion around every movable particle.
+// Fluid/solid conversion around every movable particle.  scratch: 3 float
+// planes (stride g.plane) the smoothing may overwrite (the step's velocity
+// planes, dead by then).
 hipError_t launch_conversion(int storage, const Geom &g, const Bound &b, uint8_t *mask, void *f,
                              float *tau, float scale, float inv_scale, int32_t *counters,
-                             hipStream_t s);
+                             float *scratch, hipStream_t s);
 
 }  // namespace vlb

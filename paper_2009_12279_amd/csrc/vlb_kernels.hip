@@ -490,6 +490,7 @@ __device__ __forceinline__ Bound bound_copy(const B &b)
     r.n_parts = b.n_parts;
     r.moving = b.moving;
     r.walls_move = b.walls_move;
+    r.smooth_ns = b.smooth_ns;
     return r;
 }
 
@@ -2036,6 +2037,7 @@ __global__ __launch_bounds__(64) void particle_reduce_update_kernel(Geom g, Part
         return;
     const int len[3] = {g.nx, g.ny, g.nz};
     for (int a = 0; a < 3; ++a) {
+        P.Rprev[a] = P.R[a];
         P.v[a] += P.ftot[a] / P.mass;
         P.w[a] += P.ttot[a] / P.inertia;
     }
@@ -2165,10 +2167,54 @@ __global__ __launch_bounds__(BLOCK) void conversion_check_kernel(Geom g, const P
         atomicOr(flag, 1);
 }
 
+// Fraction of the unit cell around (x, y, z) that a sphere of radius r at
+// Rc overlaps, sub-sampled at ns^3 evenly spaced points (ns = 1: the cell
+// centre, the coverage test itself).  Minimum image on periodic axes.
+__device__ double overlap_fraction(const Geom &g, const double Rc[3], double r, int x, int y, int z,
+                                   int ns)
+{
+#pragma clang fp contract(off)
+    const int len[3] = {g.nx, g.ny, g.nz};
+    const int c[3] = {x, y, z};
+    int in = 0;
+    for (int i = 0; i < ns; ++i)
+        for (int j = 0; j < ns; ++j)
+            for (int k = 0; k < ns; ++k) {
+                const int o[3] = {i, j, k};
+                double d2 = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    const double pt =
+                        static_cast<double>(c[a]) + (static_cast<double>(o[a]) + 0.5) / ns - 0.5;
+                    double d = pt - Rc[a];
+                    if (g.per[a]) {
+                        const double L = static_cast<double>(len[a]);
+                        d -= L * floor(d / L + 0.5);
+                    }
+                    d2 = a == 0 ? d * d : d2 + d * d;
+                }
+                in += d2 < r * r ? 1 : 0;
+            }
+    return static_cast<double>(in) / static_cast<double>(ns * ns * ns);
+}
+
+// Is (x, y, z) inside the (possibly wrapped) box?
+__device__ __forceinline__ bool in_box(const Geom &g, const Box &bx, int x, int y, int z)
+{
+    const int c[3] = {x, y, z}, len[3] = {g.nx, g.ny, g.nz};
+    for (int a = 0; a < 3; ++a) {
+        int off = (c[a] - bx.lo[a]) % len[a];
+        off = off < 0 ? off + len[a] : off;
+        if (off >= bx.ext[a])
+            return false;
+    }
+    return true;
+}
+
 template <int S>
 __global__ __launch_bounds__(CONV_THREADS) void conversion_kernel(Geom g, Bound b, uint8_t *mask,
                                                                   void *fv, float *tau, float scale,
-                                                                  float inv_scale, int32_t *counters)
+                                                                  float inv_scale, int32_t *counters,
+                                                                  float *scratch)
 {
     using St = Store<S>;
     using T = typename St::T;
@@ -2183,7 +2229,7 @@ __global__ __launch_bounds__(CONV_THREADS) void conversion_kernel(Geom g, Bound 
         counters[3] = 0;
     }
     __syncthreads();
-    if (!go)
+    if (!go && b.smooth_ns <= 0)
         return;
     if (threadIdx.x == 0) {
         int k = 0;
@@ -2199,6 +2245,69 @@ __global__ __launch_bounds__(CONV_THREADS) void conversion_kernel(Geom g, Bound 
         return static_cast<uint32_t>(x) + static_cast<uint32_t>(g.nx) * (y + static_cast<uint32_t>(g.ny) * z);
     };
 
+    // Phase 0 (overlap-fraction smoothing, particle by particle): a cell
+    // that is fluid, stays fluid and is overlapped more by the particle than
+    // before its last move hands the share (phi_new - phi_old) /
+    // (1 - phi_old) of its stress, in equal parts, to its neighbours that
+    // stay fluid.  Per box cell the share per neighbour and the kept
+    // fraction go to scratch planes 0 and 1; then, one stress component at a
+    // time, every receiver gathers into plane 2 and every cell applies.
+    if (b.smooth_ns > 0)
+        for (int q = 0; q < n_moving; ++q) {
+            const Particle P = parts[moving[q]];
+            const Box bx = particle_box(g, P, 2);
+            const uint32_t vol = static_cast<uint32_t>(bx.ext[0]) * bx.ext[1] * bx.ext[2];
+            for (uint32_t k = threadIdx.x; k < vol; k += CONV_THREADS) {
+                int x, y, z;
+                box_cell(g, bx, k, x, y, z);
+                const uint32_t n = cell(x, y, z);
+                float share = 0.f, keep = 1.f;
+                if (stays_fluid(c, n, x, y, z)) {
+                    const double fo = overlap_fraction(g, P.Rprev, P.radius, x, y, z, b.smooth_ns);
+                    const double fn = overlap_fraction(g, P.R, P.radius, x, y, z, b.smooth_ns);
+                    if (fn > fo && fo < 1.0) {
+                        const double qf = (fn - fo) / (1.0 - fo);
+                        const int nf = fluid_neighbours(c, Nbr(g, x, y, z));
+                        if (nf > 0) {
+                            share = static_cast<float>(qf / nf);
+                            keep = static_cast<float>(1.0 - qf);
+                        }
+                    }
+                }
+                scratch[n] = share;
+                scratch[PL + n] = keep;
+            }
+            __syncthreads();
+            for (int cc = 0; cc < 6; ++cc) {
+                for (uint32_t k = threadIdx.x; k < vol; k += CONV_THREADS) {
+                    int x, y, z;
+                    box_cell(g, bx, k, x, y, z);
+                    const uint32_t n = cell(x, y, z);
+                    if (!stays_fluid(c, n, x, y, z))
+                        continue;
+                    const Nbr nb(g, x, y, z);
+                    float recv = 0.f;
+                    for (int j = 1; j < Q; ++j) {
+                        const int mx = nb.xc[CX[j] + 1], my = nb.yc[CY[j] + 1],
+                                  mz = nb.zc[CZ[j] + 1];
+                        if (!in_box(g, bx, mx, my, mz))
+                            continue;
+                        const uint32_t m = nb.at(CX[j], CY[j], CZ[j]);
+                        recv += scratch[m] * tau[cc * PL + m];
+                    }
+                    scratch[2 * PL + n] = recv;
+                }
+                __syncthreads();
+                for (uint32_t k = threadIdx.x; k < vol; k += CONV_THREADS) {
+                    int x, y, z;
+                    box_cell(g, bx, k, x, y, z);
+                    const uint32_t n = cell(x, y, z);
+                    if (stays_fluid(c, n, x, y, z))
+                        tau[cc * PL + n] = scratch[PL + n] * tau[cc * PL + n] + scratch[2 * PL + n];
+                }
+                __syncthreads();
+            }
+        }
     // Phase 1: covers.  The populations' momentum goes to the particle; the
     // stress is shared among the D3Q19 neighbours that stay fluid (gathered
     // by each receiver).
@@ -2721,7 +2830,7 @@ hipError_t launch_body_force(const Geom &g, const uint8_t *mask, const Particle 
 
 hipError_t launch_conversion(int storage, const Geom &g, const Bound &b, uint8_t *mask, void *f,
                              float *tau, float scale, float inv_scale, int32_t *counters,
-                             hipStream_t s)
+                             float *scratch, hipStream_t s)
 {
     if (b.n_parts > 0) {
         hipLaunchKernelGGL(conversion_check_kernel, dim3(CONV_CHECK_BLOCKS, b.n_parts), dim3(BLOCK),
@@ -2732,7 +2841,7 @@ hipError_t launch_conversion(int storage, const Geom &g, const Bound &b, uint8_t
     }
     return dispatch(storage, [&](auto st) {
         hipLaunchKernelGGL(conversion_kernel<decltype(st)::value>, dim3(1), dim3(CONV_THREADS), 0,
-                           s, g, b, mask, f, tau, scale, inv_scale, counters);
+                           s, g, b, mask, f, tau, scale, inv_scale, counters, scratch);
         return hipGetLastError();
     });
 }

@@ -105,6 +105,7 @@ SIGNATURES = [
     ("vlb_kernel_time_ms", ctypes.c_double, [_P, ctypes.c_int32]),
     ("vlb_set_rounding", ctypes.c_int, [_P, ctypes.c_int, ctypes.c_uint32]),
     ("vlb_set_counter_force", ctypes.c_int, [_P, ctypes.c_int32]),
+    ("vlb_set_conversion_smoothing", ctypes.c_int, [_P, ctypes.c_int32]),
     ("vlb_set_giesekus", ctypes.c_int, [_P, ctypes.c_double]),
     ("vlb_set_fene_p", ctypes.c_int, [_P, ctypes.c_double]),
     ("vlb_set_stress_extrapolation", ctypes.c_int, [_P, ctypes.c_int32]),
@@ -395,6 +396,10 @@ def vlb_set_fene_p(h, L2):
     return _check(lib().vlb_set_fene_p(h, float(L2)), h)
 
 
+def vlb_set_conversion_smoothing(h, samples):
+    return _check(lib().vlb_set_conversion_smoothing(h, int(samples)), h)
+
+
 def vlb_set_stress_extrapolation(h, order):
     return _check(lib().vlb_set_stress_extrapolation(h, int(order)), h)
 
@@ -548,6 +553,11 @@ class Lattice:
 
     def set_extrapolation(self, order):
         vlb_set_stress_extrapolation(self._h, order)
+
+    def set_conversion_smoothing(self, samples):
+        """Overlap-fraction smoothing of conversions with samples^3
+        sub-samples per cell (0: binary conversion)."""
+        vlb_set_conversion_smoothing(self._h, samples)
 
     def set_force_field(self, F):
         """Per-cell force density added to the body force, shape

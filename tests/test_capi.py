@@ -147,23 +147,25 @@ class _CkptHeader(ctypes.Structure):
                 ("rounding", ctypes.c_int32), ("seed", ctypes.c_uint32),
                 ("counter_force", ctypes.c_int32), ("extrap", ctypes.c_int32),
                 ("alpha", ctypes.c_double), ("L2", ctypes.c_double),
-                ("wall_field", ctypes.c_int32), ("force_field", ctypes.c_int32)]
+                ("wall_field", ctypes.c_int32), ("force_field", ctypes.c_int32),
+                ("smooth_ns", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 def _particle_record(radius=2.0, mass=30.0, movable=0):
     # R, v, w, radius, mass, inertia (12 doubles), movable + pad, then ten
-    # 3-vectors of forces and torques
+    # 3-vectors of forces and torques and the previous position
     d = np.zeros(12)
     d[0:3] = 3.5
     d[9], d[10], d[11] = radius, mass, 0.4 * mass * radius ** 2
-    return d.tobytes() + np.array([movable, 0], np.int32).tobytes() + np.zeros(30).tobytes()
+    return (d.tobytes() + np.array([movable, 0], np.int32).tobytes() + np.zeros(30).tobytes()
+            + np.full(3, 3.5).tobytes())
 
 
 def _checkpoint(path, mask_byte=0, n_parts=1, any_movable=0, **rec):
     shape = (8, 8, 8)
     N = 8 * 8 * 8
     h = _CkptHeader()
-    h.magic = 0x37304B434C424C56
+    h.magic = 0x38304B434C424C56
     h.dims[:] = [8, 8, 8, 1, 1, 1]
     h.storage, h.n_parts, h.any_movable = 0, n_parts, any_movable
     h.params[:] = [1 / 3, 0.0, 1.0, 3 / 16, 0.0, 0.0, 0.0]
@@ -190,13 +192,17 @@ def test_load_rejects_inconsistent_particle_records_on_the_host(tmp_path, case):
     p = str(tmp_path / "bad.ckpt")
     if case == "mask_beyond_table":
         _checkpoint(p, mask_byte=64 + 1, n_parts=1)
+        why = "beyond the table"
     elif case == "zero_mass":
         _checkpoint(p, mass=0.0)
+        why = "invalid particle record"
     elif case == "nan_radius":
         _checkpoint(p, radius=float("nan"))
+        why = "invalid particle record"
     else:
         _checkpoint(p, any_movable=1, movable=0)
+        why = "movable flag"
     h = vlb._P()
     st = vlb.lib().vlb_load(p.encode(), None, ctypes.byref(h))
     assert st == vlb.VLB_EINVAL
-    assert "vlb_load" in vlb.vlb_last_error(None)
+    assert why in vlb.vlb_last_error(None)

@@ -62,12 +62,16 @@ def _duct_with_moving_sphere(storage):
     return L
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
-def test_checkpoint_restart_is_bitwise(tmp_path, storage):
+@pytest.mark.parametrize("storage,smoothing", [("f32", 0), ("f16", 0), ("bf16", 0), ("f32", 4)])
+def test_checkpoint_restart_is_bitwise(tmp_path, storage, smoothing):
+    """Save, continue, and load + continue give the same bits; with
+    smoothed conversions the sphere's previous position and the sample count
+    travel with the checkpoint."""
     path = str(tmp_path / f"ck_{storage}.vlb")
-    log(f"[lattice] checkpoint restart storage={storage}")
+    log(f"[lattice] checkpoint restart storage={storage} smoothing={smoothing}")
     L = _duct_with_moving_sphere(storage)
     L.set_rounding("stochastic", 77)
+    L.set_conversion_smoothing(smoothing)
     L.step(100)
     L.save(path)
     m_saved = L.mask()
