@@ -1,0 +1,203 @@
+"""The workloads at their configured lengths against the FP64 oracle.
+
+The oracle's results come from fixtures under tests/golden/ that
+tests/golden/make_config_fixtures.py writes by running only the oracle on the
+shared seeded inputs: the particle trajectory every 100 steps and the
+velocity and stress at a seeded sample of fluid cells at the end.  The GPU
+runs the same workload and is compared at the same cells and steps.
+FP32 storage must stay within 1e-5 relative on velocity and stress; 16-bit
+storage errors are printed as numbers.
+
+A random sample of a settling box lies mostly far from the sphere, where the
+velocity is 1e-9 of what it is at the sphere's surface; velocity errors
+there are measured against the flow's velocity scale, the largest speed of
+the sphere along its trajectory, and stress errors against the largest
+stress in the sample.  Particle positions, the integral of velocities that
+carry the 1e-7 relative error of FP32 forces over thousands of steps, agree
+to 1e-6 lattice units."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2009_12279_amd import inputs, vlb
+from parity import log
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+ETA = 1.0 / 3.0
+
+
+def _fixture(name):
+    path = os.path.join(GOLDEN, name + ".npz")
+    if not os.path.exists(path):
+        pytest.skip(f"fixture {name} not written yet (tests/golden/make_config_fixtures.py)")
+    return np.load(path)
+
+
+def _rel(a, b, scale=None):
+    """(L2 relative error, max error / max |b|), or with a given scale
+    (max error / scale, L2 error / (scale sqrt(size)))."""
+    if scale is not None:
+        return (float(np.linalg.norm(a - b) / (scale * np.sqrt(b.size))),
+                float(np.max(np.abs(a - b)) / scale))
+    return (float(np.linalg.norm(a - b) / np.linalg.norm(b)),
+            float(np.max(np.abs(a - b)) / np.max(np.abs(b))))
+
+
+def _fields(L, cells):
+    u = L.velocity().reshape(3, -1)[:, cells]
+    tau = L.stress().reshape(6, -1)[:, cells]
+    return u, tau
+
+
+def _duct(lam, storage="f32"):
+    shape = (64, 32, 32)
+    L = vlb.Lattice(shape, inputs.channel_mask(shape, wall_axes=(1, 2)), (1, 0, 0),
+                    storage=storage)
+    L.set_params(eta=ETA, beta=0.5, lambda_p=float(lam), magic=3 / 16, body_force=(1e-6, 0, 0))
+    L.add_sphere(center=(31.5, 15.5, 15.5), radius=4.0)
+    L.init_equilibrium()
+    return L
+
+
+@pytest.mark.parametrize("lam", [100, 1000, 5000])
+def test_fixed_sphere_duct_full_length(lam):
+    """Duct with a fixed sphere (the 64 x 32 x 32 copy of the 128 x 64 x 64
+    duct), lambda_p = 100, 1000, 5000, the full 10 000 steps."""
+    fx = _fixture(f"duct_lambda{lam}")
+    log(f"[config] duct lambda={lam} 10000 steps")
+    L = _duct(lam)
+    L.step(10000)
+    u, tau = _fields(L, fx["cells_10000"])
+    eu, et = _rel(u, fx["u_10000"]), _rel(tau, fx["tau_10000"])
+    log(f"[config]   u {eu}  tau {et}")
+    assert max(eu) < 1e-5 and max(et) < 1e-5
+    f_or = fx["trajectory"][-1, 10:13]
+    f_g = L.particle(0)["force"]
+    np.testing.assert_allclose(f_g, f_or, rtol=0, atol=1e-5 * np.abs(f_or).max())
+    L.close()
+
+
+def _settling(wi):
+    shape = (64, 64, 256)
+    r, F = 6.0, 0.004
+    lam1 = r / (F / (6 * np.pi * ETA * r))
+    L = vlb.Lattice(shape, inputs.channel_mask(shape, wall_axes=(0, 1, 2)), (0, 0, 0))
+    L.set_params(eta=ETA, beta=0.5 if wi > 0 else 0.0, lambda_p=max(1.0, wi * lam1),
+                 magic=3 / 16, body_force=(0, 0, 0))
+    L.add_sphere(center=(31.5, 31.5, 191.5), radius=r, density_ratio=1.5, movable=True,
+                 f_ext=(0.0, 0.0, -F))
+    L.set_check_interval(0)
+    L.init_equilibrium()
+    return L
+
+
+@pytest.mark.parametrize("name,wi,steps", [("settling_wi0", 0.0, 5000),
+                                           ("settling_wi0.25", 0.25, 5000),
+                                           ("settling_wi1", 1.0, 5000),
+                                           ("settling_wi1_long", 1.0, 50000)])
+def test_settling_sphere_trajectory_full_length(name, wi, steps):
+    """Sphere settling in the closed 64 x 64 x 256 box at Wi = 0, 0.25 and 1
+    (5000 steps) and at Wi = 1 over the full 50 000 steps: position and
+    velocity every 100 steps, the covered cells and the fields at the end."""
+    fx = _fixture(name)
+    if steps not in fx["ends"]:
+        pytest.skip(f"fixture {name} does not reach step {steps} yet")
+    traj = fx["trajectory"]
+    log(f"[config] {name} {steps} steps")
+    L = _settling(wi)
+    worst_z = worst_v = 0.0
+    vscale = np.abs(traj[:, 6]).max()
+    for k in range(steps // 100):
+        L.step(100)
+        p = L.particle(0)
+        assert traj[k, 0] == 100 * (k + 1)
+        worst_z = max(worst_z, float(np.max(np.abs(p["pos"] - traj[k, 1:4]))))
+        worst_v = max(worst_v, float(np.max(np.abs(p["vel"] - traj[k, 4:7]))) / vscale)
+    log(f"[config]   worst |dR| {worst_z:.3e}, worst |dv|/max|v_z| {worst_v:.3e}")
+    assert worst_z < 1e-6 and worst_v < 1e-5
+    covered = np.flatnonzero(L.mask().reshape(-1) >= 64)
+    np.testing.assert_array_equal(covered, fx[f"covered_{steps}"])
+    u, tau = _fields(L, fx[f"cells_{steps}"])
+    uo = fx[f"u_{steps}"]
+    eu = _rel(u, uo, max(np.abs(uo).max(), np.abs(traj[:steps // 100, 4:7]).max()))
+    log(f"[config]   u {eu} (sample L2 relative {_rel(u, uo)[0]:.3e})")
+    assert max(eu) < 1e-5
+    if wi > 0:
+        et = _rel(tau, fx[f"tau_{steps}"])
+        log(f"[config]   tau {et}")
+        assert max(et) < 1e-5
+    L.close()
+
+
+def test_box256_storage_errors_against_the_oracle():
+    """The 256^3 box with 64 fixed spheres after 100 and 1000 steps in FP32,
+    FP16 and BF16 storage, at 8192 sampled fluid cells: FP32 within 1e-5
+    relative, the 16-bit errors printed."""
+    fx = _fixture("box256")
+    shape = (256, 256, 256)
+    spheres = inputs.place_spheres(4, 0, shape, 64, 6.0, 6.0, min_gap=2.0, periodic=(1, 1, 1))
+    beta = float(inputs.Stream(4, 1).uniform(1, 0.1, 0.9)[0])
+    for storage in ("f32", "f16", "bf16"):
+        log(f"[config] box256 {storage}")
+        L = vlb.Lattice(shape, np.zeros(shape[::-1], np.uint8), (1, 1, 1), storage=storage)
+        L.set_params(eta=ETA, beta=beta, lambda_p=1000.0, magic=3 / 16, body_force=(1e-6, 0, 0))
+        for c, r in spheres:
+            L.add_sphere(center=c, radius=r)
+        L.set_check_interval(0)
+        L.init_equilibrium()
+        done = 0
+        for end in fx["ends"]:
+            L.step(int(end) - done)
+            done = int(end)
+            u, tau = _fields(L, fx[f"cells_{end}"])
+            eu, et = _rel(u, fx[f"u_{end}"]), _rel(tau, fx[f"tau_{end}"])
+            log(f"[config]   {storage} step {end}: u L2 {eu[0]:.3e} max {eu[1]:.3e}; "
+                f"tau L2 {et[0]:.3e} max {et[1]:.3e}")
+            if storage == "f32":
+                assert max(eu) < 1e-5 and max(et) < 1e-5
+            else:
+                assert max(eu) < 0.1 and max(et) < 0.1
+        L.close()
+
+
+def test_sphere_crossing_a_periodic_seam():
+    """A free sphere driven along x across the periodic seam x = 0 / n_x - 1
+    (covers and uncovers on both sides of the seam, the minimum image in the
+    surface velocity, the lever arm and the coverage test): trajectory,
+    masks and fields against the oracle."""
+    import oracle
+
+    shape = (32, 24, 24)
+    fext = (0.08, 0.0, 0.0)
+    sides = []
+    for side in ("gpu", "oracle"):
+        mk = vlb.Lattice if side == "gpu" else oracle.Lattice
+        L = mk(shape, np.zeros(shape[::-1], np.uint8), (1, 1, 1))
+        L.set_params(eta=ETA, beta=0.5, lambda_p=200.0, magic=3 / 16, body_force=(0, 0, 0))
+        L.add_sphere(center=(30.6, 11.5, 11.7), radius=4.0, density_ratio=3.0, movable=True,
+                     f_ext=fext)
+        L.set_counter_force(True)
+        L.init_equilibrium()
+        sides.append(L)
+    g, o = sides
+    log("[config] seam crossing 32x24x24, 1200 steps")
+    for n in range(12):
+        g.step(100)
+        o.step(100)
+        pg, po = g.particle(0), o.particle(0)
+        np.testing.assert_allclose(pg["pos"], po["pos"], rtol=0, atol=1e-6)
+        np.testing.assert_allclose(pg["vel"], po["vel"], rtol=0,
+                                   atol=1e-5 * np.abs(po["vel"]).max())
+        assert np.array_equal(g.mask(), o.mask()), n
+    x = o.particle(0)["pos"][0]
+    assert x < 10.0, x  # the centre has wrapped past the seam
+    fl = o.mask() == 0
+    for name, a, b in (("u", g.velocity(), o.velocity()), ("tau", g.stress(), o.stress())):
+        e = _rel(a[:, fl], b[:, fl])
+        log(f"[config]   {name} {e}")
+        assert max(e) < 1e-5
+    g.close()
+    o.close()
