@@ -265,12 +265,36 @@ def run_cpu_baseline(args):
         single = timed(args.cpu_steps_single)
         oracle.set_threads(0)
     L.close()
+    # the fixed-sphere duct, 128 x 64 x 64 with a sphere of radius 8
+    from paper_2009_12279_amd import inputs
+    dshape = (128, 64, 64)
+    D = oracle.Lattice(dshape, inputs.channel_mask(dshape, wall_axes=(1, 2)), (1, 0, 0))
+    D.set_params(eta=1.0 / 3.0, beta=0.5, lambda_p=1000.0, magic=3.0 / 16.0,
+                 body_force=(1e-6, 0.0, 0.0))
+    D.add_sphere((63.5, 31.5, 31.5), 8.0)
+    D.init_equilibrium()
+    ncell = dshape[0] * dshape[1] * dshape[2]
+
+    def dtimed(n):
+        D.step(1)
+        t0 = time.perf_counter()
+        D.step(n)
+        return ncell * n / (time.perf_counter() - t0) / 1e6
+
+    duct = dict(all_cores=round(dtimed(40), 3))
+    oracle.set_threads(1)
+    duct["single_thread"] = round(dtimed(10), 3)
+    oracle.set_threads(0)
+    D.close()
     return dict(value=all_cores, unit="MLUPS", cores=threads, kind="oracle",
                 sample=f"the same 256^3 workload, {args.cpu_steps} steps after 1 untimed step "
                        f"(FP64 oracle, OpenMP {threads} threads)",
                 single_thread=None if single is None else dict(
                     value=single, unit="MLUPS", cores=1,
-                    sample=f"{args.cpu_steps_single} steps after 1 untimed step, 1 thread"))
+                    sample=f"{args.cpu_steps_single} steps after 1 untimed step, 1 thread"),
+                duct_128x64x64=dict(duct, unit="MLUPS",
+                                    sample="fixed-sphere duct, r = 8, lambda_p = 1000: 40 steps "
+                                           f"on {threads} threads, 10 steps on 1"))
 
 
 def serving_requests(n, steps_scale):
@@ -324,7 +348,11 @@ def run_serving(args):
     # sequential baseline: one plain lattice after another
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for r in reqs:
+    last = t0
+    for i, r in enumerate(reqs):
+        if time.perf_counter() - last > 30.0:
+            last = time.perf_counter()
+            print(f"[serving] sequential {i}/{len(reqs)}", file=sys.stderr, flush=True)
         L = vlb.Lattice(r["shape"], r["mask"], r["periodic"])
         L.set_params(**r["params"])
         for c in r["spheres"]:
@@ -347,7 +375,12 @@ def run_serving(args):
             tickets = {}
             nxt = 0
             t0 = time.perf_counter()
+            last = t0
             while len(lat) < len(reqs):
+                if time.perf_counter() - last > 30.0:
+                    last = time.perf_counter()
+                    print(f"[serving] {len(lat)}/{len(reqs)} done, {nxt} submitted",
+                          file=sys.stderr, flush=True)
                 now = time.perf_counter() - t0
                 while nxt < len(reqs) and arrivals[nxt] <= now:
                     r = reqs[nxt]

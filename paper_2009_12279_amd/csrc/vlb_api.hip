@@ -907,6 +907,10 @@ hipError_t capture_steps(vlb_lattice *lat, const vlb::StepArgs &base, int par, i
         le = e;
     if (le == hipSuccess)
         le = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+    // upload now, so that the first replay of this executable does not pay
+    // for it inside a caller's timed loop
+    if (le == hipSuccess)
+        le = hipGraphUpload(*out, st);
     if (graph)
         (void)hipGraphDestroy(graph);
     return le;

@@ -133,6 +133,12 @@ struct BatchSolve {
     uint32_t first_block;
     uint32_t nblocks;
     uint32_t target;
+    // stress update: its block range, and 64 x 4 tiles marching through
+    // chunks of fv_zc planes (fv_tiled) or one cell per thread
+    uint32_t fv_tiled;
+    uint32_t fv_first_block;
+    uint32_t fv_nblocks;
+    uint32_t fv_zc;
     uint32_t pad;
 };
 
@@ -142,7 +148,14 @@ struct BatchTable {
     const BatchSolve *solves;     // [n_solves]
     const uint32_t *block_solve;  // [total_blocks]
     uint32_t *steps;              // [n_solves], advanced on the device
+    uint32_t fv_total_blocks;
+    const uint32_t *fv_block_solve;  // [fv_total_blocks], stress-update blocks
 };
+
+// Stress-update blocks of a served solve: tiles (64 x 4, chunks of *zc
+// planes) when it is at least 32 cells wide and 4 rows high, else one cell
+// per thread.
+uint32_t batch_fv_blocks(const Geom &g, bool *tiled, uint32_t *zc);
 
 // Host-side launchers (vlb_kernels.hip).
 // Counter-force: count the cells that are fluid now into *count, then
@@ -153,11 +166,12 @@ hipError_t launch_body_force(const Geom &g, const uint8_t *mask, const Particle 
                              double *g_out, hipStream_t s);
 hipError_t launch_lb_step(int storage, const StepArgs &a, hipStream_t s);
 // n_steps batched steps (stream-collide, stress update, counter advance per
-// step) over every solve of the table; grid of max_blocks blocks.
+// step) over every solve of the table: stream-collide on max_blocks blocks
+// of BLOCK threads, the stress update on fv_blocks blocks of 64 x 4.
 // Base step of graph replays: *step = value, or *step += value (add != 0).
 hipError_t launch_set_step(uint32_t *step, uint32_t value, int add, hipStream_t s);
-hipError_t launch_batch_step(const BatchTable *t, uint32_t max_blocks, int stochastic, int n_steps,
-                             hipStream_t s);
+hipError_t launch_batch_step(const BatchTable *t, uint32_t max_blocks, uint32_t fv_blocks,
+                             int stochastic, int n_steps, hipStream_t s);
 // tile_rows 4 or 8 selects the tiled kernel (64 x tile_rows tiles marching
 // through z_chunk planes, 0 = 16) where the lattice is large enough for it,
 // -4 or -8 the tiled kernel for any lattice; anything else the per-cell

@@ -69,6 +69,8 @@ struct Slot {
     vlb::StepArgs args[2]{};
     uint32_t target = 0;
     uint32_t nblocks = 0;
+    bool fv_tiled = false;              // stress update in tiles, else per cell
+    uint32_t fv_nblocks = 0, fv_zc = 0;
     uint64_t last_launch = 0;           // the replay that takes it to its target
 };
 
@@ -112,13 +114,14 @@ struct vlb_server {
     vlb::BatchSolve *d_solves = nullptr;
     uint32_t *d_block_solve = nullptr;
     uint32_t *d_steps = nullptr;
-    uint32_t table_capacity_blocks = 0;
+    uint32_t table_capacity_blocks = 0;  // of the block-to-solve array (both kernels)
     vlb::BatchTable *h_table = nullptr;
     vlb::BatchSolve *h_solves = nullptr;
     uint32_t *h_block_solve = nullptr;
     uint32_t *h_zero = nullptr;
     hipEvent_t tables_copied = nullptr;
     uint32_t total_blocks = 0;
+    uint32_t fv_total_blocks = 0;
     bool tables_dirty = false;
     bool admitted_since_launch = false;
     hipEvent_t io_done = nullptr;
@@ -130,9 +133,12 @@ struct vlb_server {
     struct GraphSet {
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
-        uint32_t blocks = 0;
-        std::vector<hipGraphNode_t> nodes;  // kernel nodes whose grid is the block count
+        uint32_t blocks = 0, fv_blocks = 0;
+        // kernel nodes whose grid is the block count: stream-collide (fv
+        // false) and stress update (fv true)
+        std::vector<hipGraphNode_t> nodes;
         std::vector<hipKernelNodeParams> params;
+        std::vector<bool> fv;
     } graphs[2];
     hipEvent_t launch_done[2] = {nullptr, nullptr};
     uint64_t n_launched = 0, n_completed = 0;
@@ -292,6 +298,7 @@ vlb_status admit(vlb_server *srv, Request &rq, bool &no_room)
     sl.bytes = bytes;
     sl.target = rq.steps;
     sl.nblocks = static_cast<uint32_t>((N + vlb::BLOCK - 1) / vlb::BLOCK);
+    sl.fv_nblocks = vlb::batch_fv_blocks(sl.g, &sl.fv_tiled, &sl.fv_zc);
     const uint64_t P = sl.g.plane;
     char *base = srv->arena + offset;
     sl.f[0] = reinterpret_cast<float *>(base);
@@ -334,13 +341,16 @@ vlb_status admit(vlb_server *srv, Request &rq, bool &no_room)
 vlb_status rebuild_tables(vlb_server *srv)
 {
     SCHK(srv, hipEventSynchronize(srv->tables_copied), "table staging");
-    uint32_t n_ids = 0, total = 0;
+    uint32_t n_ids = 0, total = 0, fv_total = 0;
     for (const Slot &sl : srv->slots) {
         n_ids = std::max(n_ids, sl.id + 1);
         total += sl.nblocks;
+        fv_total += sl.fv_nblocks;
     }
-    if (total > srv->table_capacity_blocks) {
-        const uint32_t cap = std::max<uint32_t>(total, 2 * srv->table_capacity_blocks);
+    // one array: the stream-collide blocks' solves, then the stress update's
+    if (total + fv_total > srv->table_capacity_blocks) {
+        const uint32_t cap =
+            std::max<uint32_t>(total + fv_total, 2 * srv->table_capacity_blocks);
         if (srv->d_block_solve)
             (void)hipFree(srv->d_block_solve);  // waits for the replays that use it
         if (srv->h_block_solve)
@@ -353,7 +363,7 @@ vlb_status rebuild_tables(vlb_server *srv)
         srv->table_capacity_blocks = cap;
     }
     std::memset(srv->h_solves, 0, n_ids * sizeof(vlb::BatchSolve));
-    uint32_t first = 0;
+    uint32_t first = 0, fv_first = 0;
     for (const Slot &sl : srv->slots) {
         vlb::BatchSolve &bs = srv->h_solves[sl.id];
         bs.args[0] = sl.args[0];
@@ -361,17 +371,27 @@ vlb_status rebuild_tables(vlb_server *srv)
         bs.first_block = first;
         bs.nblocks = sl.nblocks;
         bs.target = sl.target;
+        bs.fv_tiled = sl.fv_tiled ? 1u : 0u;
+        bs.fv_first_block = fv_first;
+        bs.fv_nblocks = sl.fv_nblocks;
+        bs.fv_zc = sl.fv_zc;
         for (uint32_t k = 0; k < sl.nblocks; ++k)
             srv->h_block_solve[first + k] = sl.id;
+        for (uint32_t k = 0; k < sl.fv_nblocks; ++k)
+            srv->h_block_solve[total + fv_first + k] = sl.id;
         first += sl.nblocks;
+        fv_first += sl.fv_nblocks;
     }
     srv->total_blocks = total;
+    srv->fv_total_blocks = fv_total;
     vlb::BatchTable &t = *srv->h_table;
     t.n_solves = n_ids;
     t.total_blocks = total;
     t.solves = srv->d_solves;
     t.block_solve = srv->d_block_solve;
     t.steps = srv->d_steps;
+    t.fv_total_blocks = fv_total;
+    t.fv_block_solve = srv->d_block_solve + total;
     for (uint32_t id : srv->new_ids)
         SCHK(srv, hipMemcpyAsync(srv->d_steps + id, srv->h_zero, sizeof(uint32_t),
                                  hipMemcpyHostToDevice, srv->stream),
@@ -381,9 +401,10 @@ vlb_status rebuild_tables(vlb_server *srv)
         SCHK(srv, hipMemcpyAsync(srv->d_solves, srv->h_solves, n_ids * sizeof(vlb::BatchSolve),
                                  hipMemcpyHostToDevice, srv->stream),
              "solve table");
-    if (total)
-        SCHK(srv, hipMemcpyAsync(srv->d_block_solve, srv->h_block_solve, total * sizeof(uint32_t),
-                                 hipMemcpyHostToDevice, srv->stream),
+    if (total + fv_total)
+        SCHK(srv, hipMemcpyAsync(srv->d_block_solve, srv->h_block_solve,
+                                 (total + fv_total) * sizeof(uint32_t), hipMemcpyHostToDevice,
+                                 srv->stream),
              "block table");
     SCHK(srv, hipMemcpyAsync(srv->d_table, srv->h_table, sizeof(vlb::BatchTable),
                              hipMemcpyHostToDevice, srv->stream),
@@ -407,19 +428,20 @@ void drop_graph(vlb_server::GraphSet &gs)
 // place rather than captured again.
 vlb_status ensure_graph(vlb_server *srv, vlb_server::GraphSet &gs)
 {
-    if (gs.exec && gs.blocks == srv->total_blocks)
+    if (gs.exec && gs.blocks == srv->total_blocks && gs.fv_blocks == srv->fv_total_blocks)
         return VLB_OK;
     if (gs.exec) {
         bool ok = true;
         for (size_t k = 0; k < gs.nodes.size() && ok; ++k) {
             hipKernelNodeParams p = gs.params[k];
-            p.gridDim.x = srv->total_blocks;
+            p.gridDim.x = gs.fv[k] ? srv->fv_total_blocks : srv->total_blocks;
             ok = hipGraphExecKernelNodeSetParams(gs.exec, gs.nodes[k], &p) == hipSuccess;
             if (ok)
                 gs.params[k] = p;
         }
         if (ok) {
             gs.blocks = srv->total_blocks;
+            gs.fv_blocks = srv->fv_total_blocks;
             srv->stats.graph_updates += 1;
             return VLB_OK;
         }
@@ -427,22 +449,24 @@ vlb_status ensure_graph(vlb_server *srv, vlb_server::GraphSet &gs)
         drop_graph(gs);
     }
     SCHK(srv, hipStreamBeginCapture(srv->cap, hipStreamCaptureModeThreadLocal), "capture");
-    hipError_t e = vlb::launch_batch_step(srv->d_table, srv->total_blocks, srv->stochastic,
-                                          srv->k_steps, srv->cap);
+    hipError_t e = vlb::launch_batch_step(srv->d_table, srv->total_blocks, srv->fv_total_blocks,
+                                          srv->stochastic, srv->k_steps, srv->cap);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(srv->cap, &g);
     SCHK(srv, e, "capture launch");
     SCHK(srv, e2, "end capture");
     gs.graph = g;
     SCHK(srv, hipGraphInstantiate(&gs.exec, g, nullptr, nullptr, 0), "instantiate");
-    // remember the per-cell kernel nodes (block size BLOCK; the counter
-    // advance runs with a different block size)
+    // remember the nodes whose grid follows the block counts: stream-collide
+    // (BLOCK x 1 threads) and the stress update (64 x 4); the counter advance
+    // runs with a block of its own size
     size_t count = 0;
     SCHK(srv, hipGraphGetNodes(g, nullptr, &count), "graph nodes");
     std::vector<hipGraphNode_t> nodes(count);
     SCHK(srv, hipGraphGetNodes(g, nodes.data(), &count), "graph nodes");
     gs.nodes.clear();
     gs.params.clear();
+    gs.fv.clear();
     for (hipGraphNode_t nd : nodes) {
         hipGraphNodeType ty;
         SCHK(srv, hipGraphNodeGetType(nd, &ty), "graph node type");
@@ -450,12 +474,16 @@ vlb_status ensure_graph(vlb_server *srv, vlb_server::GraphSet &gs)
             continue;
         hipKernelNodeParams p{};
         SCHK(srv, hipGraphKernelNodeGetParams(nd, &p), "graph node params");
-        if (p.blockDim.x == static_cast<unsigned>(vlb::BLOCK)) {
+        const bool lb = p.blockDim.x == static_cast<unsigned>(vlb::BLOCK) && p.blockDim.y == 1;
+        const bool fv = p.blockDim.x == 64u && p.blockDim.y == 4u;
+        if (lb || fv) {
             gs.nodes.push_back(nd);
             gs.params.push_back(p);
+            gs.fv.push_back(fv);
         }
     }
     gs.blocks = srv->total_blocks;
+    gs.fv_blocks = srv->fv_total_blocks;
     srv->stats.graph_captures += 1;
     return VLB_OK;
 }

@@ -33,11 +33,15 @@ def make_request(seed, shape, n_steps, n_spheres=1, wi=0.5):
                 n_steps=n_steps, seed=1000 + seed)
 
 
+# solves 32 or more cells wide take the tiled stress update (32: half the
+# tile's lanes past the row; 64 x 14 x 40: ragged y tiles and z chunks), the
+# narrower ones the per-cell one, in the same batch
 REQS = [
     (1, (16, 18, 12), 120, 1),
     (2, (24, 14, 20), 200, 2),
     (3, (20, 20, 20), 90, 0),
     (4, (32, 12, 8), 160, 1),
+    (5, (64, 14, 40), 80, 1),
 ]
 
 
@@ -73,7 +77,7 @@ def test_results_identical_alone_and_in_the_mix():
     log("[serving] mix of 4 requests, staggered submission")
     mixed, stats = serve(reqs)
     log(f"[serving]   stats {stats}")
-    assert stats["completed"] == 4 and stats["launches"] > 0
+    assert stats["completed"] == len(reqs) and stats["launches"] > 0
     for r in reqs:
         log(f"[serving] alone seed={r['seed']} shape={r['shape']}")
         alone, _ = serve([r], slots=1)
@@ -100,9 +104,13 @@ def test_result_buffer_grows_between_readouts():
             np.testing.assert_array_equal(a, b)
 
 
-def test_served_solve_equals_plain_lattice():
-    r = make_request(7, (18, 16, 14), 150, 1)
-    log("[serving] served vs plain lattice")
+@pytest.mark.parametrize("shape", [(18, 16, 14), (64, 16, 12), (128, 13, 37)])
+def test_served_solve_equals_plain_lattice(shape):
+    """Per-cell (18 wide) and tiled (64 and 128 wide; ragged y tiles and
+    z chunks) stress updates in the batch give the bits of the lattice's own
+    step."""
+    r = make_request(7, shape, 150, 1)
+    log(f"[serving] served vs plain lattice {shape}")
     out, _ = serve([r], slots=2, k=7)
     us, ts, _ = out[r["seed"]]
     L = vlb.Lattice(r["shape"], r["mask"], r["periodic"])
