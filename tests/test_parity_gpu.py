@@ -63,8 +63,13 @@ BRUTE = [
 
 
 @pytest.mark.parametrize("seed,shape,periodic,moving,sphere", BRUTE)
-@pytest.mark.parametrize("steps", [1, 30])
+@pytest.mark.parametrize("steps", [1, 30, 100])
 def test_brute_force_tiny_lattices(seed, shape, periodic, moving, sphere, steps):
+    """Random masks, walls, spheres and states after 1, 30 and 100 steps.
+    Errors are relative to the largest deviation of each field (populations
+    and density as deviations from rest): within 1e-6 for populations,
+    velocity and stress after 1 and 100 steps; the density deviation, a
+    difference of two nearly equal sums, within 1e-5."""
     case = random_case(seed, shape, periodic, moving, sphere)
     log(f"[parity] brute seed={seed} shape={shape} per={periodic} steps={steps}")
     g, o = build(case)
@@ -73,8 +78,8 @@ def test_brute_force_tiny_lattices(seed, shape, periodic, moving, sphere, steps)
     e = compare(g, o, case)
     log(f"[parity]   errors {e}")
     assert e["mask_equal"]
-    tol = 2e-6 if steps == 1 else 1e-5
     for k in ("f", "u", "tau", "rho"):
+        tol = 1e-5 if k == "rho" or steps == 30 else 1e-6
         assert e[k][0] < tol, (k, e[k])
     wo = o.wall_force()
     np.testing.assert_allclose(g.wall_force(), wo, rtol=0, atol=1e-5 * np.abs(wo).max() + 1e-12)
