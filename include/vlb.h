@@ -63,8 +63,8 @@ typedef enum vlb_status {
 } vlb_status;
 
 /* Population storage: deviations h_i = s * (f_i - w_i) from the lattice
- * weights w_i, with a power-of-two scale s (1 for FP32, 2^10 for FP16, 1 for
- * BF16).  The per-cell arithmetic runs in FP64 registers for FP32 storage and
+ * weights w_i, with a power-of-two scale s (1 for FP32, 2^10 for FP16 unless
+ * vlb_set_velocity_scale picks another, 1 for BF16).  The per-cell arithmetic runs in FP64 registers for FP32 storage and
  * in FP32 for FP16/BF16 storage; particle sums are FP64. */
 typedef enum vlb_storage { VLB_STORE_F32 = 0, VLB_STORE_F16 = 1, VLB_STORE_BF16 = 2 } vlb_storage;
 
@@ -324,6 +324,23 @@ vlb_status vlb_set_counter_force(vlb_lattice *lat, int32_t on);
 
 /* Rounding of stored values (default VLB_ROUND_STOCHASTIC, seed 0x2009). */
 vlb_status vlb_set_rounding(vlb_lattice *lat, vlb_rounding mode, uint32_t seed);
+
+/* Storage scale of FP16 populations from the largest flow speed expected
+ * (a storage choice of this library; the method itself is precision
+ * agnostic).  FP16 storage takes s = 2^k, the largest power of two up to
+ * 2^24 with s * max(u_max, 1e-4) <= 64: the deviations of a flow at that
+ * speed, at most about u_max, then sit three decades below FP16's largest
+ * value, and deviations as small as 2^-14 / s (2e-9 for u_max = 1e-3) are
+ * still normal FP16 numbers.  The state already stored is rescaled in place by the
+ * power-of-two ratio (exact for every value that stays a normal FP16 number
+ * at both scales).  FP32 and BF16 storage keep s = 1, since their exponent
+ * range needs no scale; for them the call only checks u_max.  VLB_EINVAL for
+ * a non-finite or non-positive u_max.  The scale is kept in checkpoints. */
+vlb_status vlb_set_velocity_scale(vlb_lattice *lat, double u_max);
+
+/* The storage scale s in use (1 for FP32 and BF16; 2^10 for FP16 unless
+ * vlb_set_velocity_scale chose another); 0 for a NULL lattice. */
+double vlb_storage_scale(const vlb_lattice *lat);
 double vlb_kernel_time_ms(const vlb_lattice *lat, int32_t which);
 
 /* ------------------------------------------------------------------------

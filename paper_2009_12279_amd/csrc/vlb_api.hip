@@ -113,6 +113,27 @@ size_t storage_bytes(int storage) { return storage == vlb::ST_F32 ? 4 : 2; }
 
 float default_scale(int storage) { return storage == vlb::ST_F16 ? 1024.f : 1.f; }
 
+// FP16 storage scale for a flow whose speed stays below u_max: the largest
+// 2^k, k <= 24, with 2^k * max(u_max, 1e-4) <= 64.
+float fp16_scale_for(double u_max)
+{
+    const double d = u_max > 1e-4 ? u_max : 1e-4;
+    int k = 0;
+    while (k < 24 && std::ldexp(d, k + 1) <= 64.0)
+        ++k;
+    return std::ldexp(1.f, k);
+}
+
+// A storage scale a checkpoint may carry: 1 for FP32 and BF16, a power of
+// two from 1 to 2^24 for FP16.
+bool valid_scale(int storage, float s)
+{
+    if (storage != vlb::ST_F16)
+        return s == 1.f;
+    int e = 0;
+    return s >= 1.f && s <= 16777216.f && std::frexp(s, &e) == 0.5f;
+}
+
 }  // namespace
 
 struct vlb_lattice {
@@ -1515,7 +1536,7 @@ vlb_status vlb_load(const char *path, void *stream, vlb_lattice **out)
     FileHeader h{};
     if (std::fread(&h, sizeof h, 1, fp) != 1 || h.magic != kMagic || h.n_parts < 0 ||
         h.n_parts > vlb::MAX_PARTICLES || h.storage < VLB_STORE_F32 || h.storage > VLB_STORE_BF16 ||
-        h.scale != default_scale(h.storage)) {
+        !valid_scale(h.storage, h.scale)) {
         std::fclose(fp);
         return fail(nullptr, VLB_EINVAL, "vlb_load: not a lattice checkpoint");
     }
@@ -1784,6 +1805,33 @@ vlb_status vlb_set_rounding(vlb_lattice *lat, vlb_rounding mode, uint32_t seed)
     lat->rounding = mode;
     lat->seed = seed;
     return VLB_OK;
+}
+
+vlb_status vlb_set_velocity_scale(vlb_lattice *lat, double u_max)
+{
+    if (!lat)
+        return VLB_EINVAL;
+    if (!(u_max > 0.0) || !std::isfinite(u_max))
+        return fail(lat, VLB_EINVAL, "vlb_set_velocity_scale: u_max must be finite and positive");
+    if (lat->storage != vlb::ST_F16)
+        return VLB_OK;
+    const float s = fp16_scale_for(u_max);
+    if (s == lat->scale)
+        return VLB_OK;
+    // the stored state: the current population buffer (the other one is
+    // rewritten whole by the next step before it is read)
+    HIPCHK(lat, vlb::launch_rescale_f16(lat->d_f[lat->cur], vlb::Q * lat->g.plane, s / lat->scale,
+                                        lat->stream),
+           "vlb_set_velocity_scale");
+    HIPCHK(lat, hipStreamSynchronize(lat->stream), "vlb_set_velocity_scale");
+    lat->scale = s;
+    lat->inv_scale = 1.f / s;
+    return VLB_OK;
+}
+
+double vlb_storage_scale(const vlb_lattice *lat)
+{
+    return lat ? static_cast<double>(lat->scale) : 0.0;
 }
 
 vlb_status vlb_set_timing(vlb_lattice *lat, int32_t on)

@@ -191,6 +191,8 @@ hipError_t launch_step_fused(int storage, const StepArgs &a, hipStream_t s, uint
                              bool force);
 hipError_t launch_init_equilibrium(int storage, const Geom &g, const uint8_t *mask,
                                    const double *u, void *f, float scale, hipStream_t s);
+// Multiply `count` FP16 values at f by the power of two `factor`.
+hipError_t launch_rescale_f16(void *f, uint64_t count, float factor, hipStream_t s);
 hipError_t launch_set_populations(int storage, const Geom &g, const uint8_t *mask,
                                   const double *f_in, void *f, float scale, hipStream_t s);
 hipError_t launch_set_stress(const Geom &g, const uint8_t *mask, const double *tau_in,

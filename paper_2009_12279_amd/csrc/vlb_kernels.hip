@@ -89,7 +89,8 @@ __device__ __forceinline__ void st_stream(T *p, T v)
 // st() rounds to nearest; st_sr() rounds stochastically with the 16-bit
 // uniform r16, which removes the systematic bias round-to-nearest leaves in
 // a slowly relaxing steady state.  The scale s is 1 for FP32 and BF16 (the
-// library never sets another), so their codecs skip the multiplications.
+// library never sets another), so their codecs skip the multiplications; FP16
+// takes a power of two chosen per lattice.
 
 template <int S>
 struct Store;
@@ -2742,6 +2743,28 @@ hipError_t launch_init_equilibrium(int storage, const Geom &g, const uint8_t *ma
                            0, s, g, mask, u, f, scale);
         return hipGetLastError();
     });
+}
+
+// FP16 deviations times a power of two (a change of storage scale): exact
+// wherever the value stays a normal FP16 number, rounded to nearest where it
+// enters or leaves the subnormal range.
+__global__ __launch_bounds__(BLOCK) void rescale_f16_kernel(__half *h, uint64_t count, float factor)
+{
+    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * BLOCK;
+    for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * BLOCK + threadIdx.x; i < count;
+         i += stride)
+        h[i] = __float2half_rn(__half2float(h[i]) * factor);
+}
+
+hipError_t launch_rescale_f16(void *f, uint64_t count, float factor, hipStream_t s)
+{
+    if (count == 0)
+        return hipSuccess;
+    const uint64_t need = (count + BLOCK - 1) / BLOCK;
+    const uint32_t blocks = static_cast<uint32_t>(need < 8192 ? need : 8192);
+    hipLaunchKernelGGL(rescale_f16_kernel, dim3(blocks), dim3(BLOCK), 0, s,
+                       static_cast<__half *>(f), count, factor);
+    return hipGetLastError();
 }
 
 hipError_t launch_set_populations(int storage, const Geom &g, const uint8_t *mask,

@@ -104,6 +104,8 @@ SIGNATURES = [
     ("vlb_set_timing", ctypes.c_int, [_P, ctypes.c_int32]),
     ("vlb_kernel_time_ms", ctypes.c_double, [_P, ctypes.c_int32]),
     ("vlb_set_rounding", ctypes.c_int, [_P, ctypes.c_int, ctypes.c_uint32]),
+    ("vlb_set_velocity_scale", ctypes.c_int, [_P, ctypes.c_double]),
+    ("vlb_storage_scale", ctypes.c_double, [_P]),
     ("vlb_set_counter_force", ctypes.c_int, [_P, ctypes.c_int32]),
     ("vlb_set_conversion_smoothing", ctypes.c_int, [_P, ctypes.c_int32]),
     ("vlb_set_giesekus", ctypes.c_int, [_P, ctypes.c_double]),
@@ -420,6 +422,14 @@ def vlb_set_rounding(h, mode="stochastic", seed=0x2009):
     return _check(lib().vlb_set_rounding(h, ROUNDING[mode], int(seed) & 0xFFFFFFFF), h)
 
 
+def vlb_set_velocity_scale(h, u_max):
+    return _check(lib().vlb_set_velocity_scale(h, float(u_max)), h)
+
+
+def vlb_storage_scale(h):
+    return float(lib().vlb_storage_scale(h))
+
+
 # ---- convenience wrapper ------------------------------------------------------
 
 class Lattice:
@@ -544,6 +554,14 @@ class Lattice:
 
     def set_counter_force(self, on=True):
         vlb_set_counter_force(self._h, on)
+
+    def set_velocity_scale(self, u_max):
+        """FP16 storage scale from the largest expected flow speed."""
+        vlb_set_velocity_scale(self._h, u_max)
+
+    @property
+    def storage_scale(self):
+        return vlb_storage_scale(self._h)
 
     def set_giesekus(self, alpha):
         vlb_set_giesekus(self._h, alpha)

@@ -161,15 +161,15 @@ def _particle_record(radius=2.0, mass=30.0, movable=0):
             + np.full(3, 3.5).tobytes())
 
 
-def _checkpoint(path, mask_byte=0, n_parts=1, any_movable=0, **rec):
+def _checkpoint(path, mask_byte=0, n_parts=1, any_movable=0, storage=0, scale=1.0, **rec):
     shape = (8, 8, 8)
     N = 8 * 8 * 8
     h = _CkptHeader()
     h.magic = 0x38304B434C424C56
     h.dims[:] = [8, 8, 8, 1, 1, 1]
-    h.storage, h.n_parts, h.any_movable = 0, n_parts, any_movable
+    h.storage, h.n_parts, h.any_movable = storage, n_parts, any_movable
     h.params[:] = [1 / 3, 0.0, 1.0, 3 / 16, 0.0, 0.0, 0.0]
-    h.scale, h.rounding = 1.0, 1
+    h.scale, h.rounding = scale, 1
     mask = np.zeros(N, np.uint8)
     mask[100] = mask_byte
     with open(path, "wb") as fp:
@@ -206,3 +206,16 @@ def test_load_rejects_inconsistent_particle_records_on_the_host(tmp_path, case):
     st = vlb.lib().vlb_load(p.encode(), None, ctypes.byref(h))
     assert st == vlb.VLB_EINVAL
     assert why in vlb.vlb_last_error(None)
+
+
+@pytest.mark.parametrize("storage,scale", [(1, 3.0), (1, 0.5), (1, 2.0 ** 25), (0, 2.0),
+                                           (2, 1024.0), (1, float("nan"))])
+def test_load_rejects_a_storage_scale_the_format_cannot_carry(tmp_path, storage, scale):
+    """FP16 checkpoints carry a power-of-two scale from 1 to 2^24, FP32 and
+    BF16 ones the scale 1; anything else is refused before any device work."""
+    p = str(tmp_path / "bad_scale.ckpt")
+    _checkpoint(p, storage=storage, scale=scale)
+    h = vlb._P()
+    st = vlb.lib().vlb_load(p.encode(), None, ctypes.byref(h))
+    assert st == vlb.VLB_EINVAL
+    assert "not a lattice checkpoint" in vlb.vlb_last_error(None)
