@@ -113,6 +113,15 @@ size_t storage_bytes(int storage) { return storage == vlb::ST_F32 ? 4 : 2; }
 
 float default_scale(int storage) { return storage == vlb::ST_F16 ? 1024.f : 1.f; }
 
+// Conversion in one block for every particle, even where their cells are
+// far apart (VLB_CONV_SERIAL=1): the reference order the per-particle blocks
+// must reproduce bit for bit.  Read when the step arguments are built.
+bool conv_serial()
+{
+    const char *e = std::getenv("VLB_CONV_SERIAL");
+    return e && e[0] == '1';
+}
+
 // FP16 storage scale for a flow whose speed stays below u_max: the largest
 // 2^k, k <= 24, with 2^k * max(u_max, 1e-4) <= 64.
 float fp16_scale_for(double u_max)
@@ -219,6 +228,7 @@ struct vlb_lattice {
         b.moving = (any_movable || moving_walls) ? 1 : 0;
         b.walls_move = moving_walls ? 1 : 0;
         b.smooth_ns = smooth_ns;
+        b.conv_serial = conv_serial() ? 1 : 0;
         return b;
     }
 };
@@ -590,9 +600,13 @@ vlb_status create_impl(const vlb_dims *dims, const uint8_t *mask, const double *
         return bail(e, "fluid count");
     if ((e = hipMalloc(&lat->d_g3, 3 * sizeof(double))) != hipSuccess)
         return bail(e, "body force");
-    if ((e = hipMalloc(&lat->d_counters, 4 * sizeof(int32_t))) != hipSuccess)
+    // conversion counts (covers, uncovers, dropped), one unused word, then a
+    // change flag per particle
+    constexpr size_t n_counters = 4 + vlb::MAX_PARTICLES;
+    if ((e = hipMalloc(&lat->d_counters, n_counters * sizeof(int32_t))) != hipSuccess)
         return bail(e, "counters");
-    if ((e = hipMemsetAsync(lat->d_counters, 0, 4 * sizeof(int32_t), lat->stream)) != hipSuccess)
+    if ((e = hipMemsetAsync(lat->d_counters, 0, n_counters * sizeof(int32_t), lat->stream)) !=
+        hipSuccess)
         return bail(e, "counters");
     if ((e = hipMemcpyAsync(lat->d_mask, mask, N, hipMemcpyHostToDevice, lat->stream)) != hipSuccess)
         return bail(e, "mask upload");

@@ -69,6 +69,9 @@ struct Bound {
     // overlap-fraction smoothing of conversions: sub-samples per axis of a
     // cell's overlap with a moving particle (0: binary conversion)
     int32_t smooth_ns = 0;
+    // conversion in one block, particle after particle, even where the
+    // particles' cells are far apart (VLB_CONV_SERIAL=1; the same bits)
+    int32_t conv_serial = 0;
 };
 
 // Map from the stored stress variable to the polymer stress.  Identity for

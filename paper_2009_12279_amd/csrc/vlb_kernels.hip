@@ -2100,10 +2100,13 @@ __global__ __launch_bounds__(BLOCK) void wall_force_kernel(Geom g, const uint8_t
 // Section 3.4: totals and symplectic Euler (velocity first, then position
 // with the new velocity).
 // ---------------------------------------------------------------------------
-// Fluid/solid conversion around movable particles (Section 3.4), one block.
-// The new owner of a cell is a pure function of its old mask byte and the
-// updated particle positions, so every phase is a gather and needs no
-// atomics; phases are separated by barriers.
+// Fluid/solid conversion around movable particles (Section 3.4).  The new
+// owner of a cell is a pure function of its old mask byte and the updated
+// particle positions, so every phase is a gather and needs no atomics; phases
+// are separated by barriers.  One block per movable particle when no
+// particle's cells come near another's (each block then runs every phase for
+// its particle alone, which gives the bits of the one-block order), else one
+// block for all of them, particle after particle within each phase.
 
 constexpr int CONV_THREADS = 1024;
 constexpr int CONV_CHECK_BLOCKS = 16;  // blocks per particle of the change check
@@ -2162,9 +2165,9 @@ __device__ int fluid_neighbours(const ConvCtx &c, const Nbr &nb)
     return nf;
 }
 
-// Does any cell change owner this step?  Many blocks per moving particle scan
-// its bounding box and raise flag[0]; the conversion kernel does nothing
-// unless it is raised (and clears it).
+// Does any cell change owner this step?  Many blocks per moving particle p
+// scan its bounding box and raise flag[p]; the conversion kernel does nothing
+// for p unless it is raised (and clears it).
 __global__ __launch_bounds__(BLOCK) void conversion_check_kernel(Geom g, const Particle *parts,
                                                                  const uint8_t *mask,
                                                                  int32_t *flag)
@@ -2188,7 +2191,7 @@ __global__ __launch_bounds__(BLOCK) void conversion_check_kernel(Geom g, const P
         }
     }
     if (__syncthreads_or(change) && threadIdx.x == 0)
-        atomicOr(flag, 1);
+        atomicOr(flag + p, 1);
 }
 
 // Fraction of the unit cell around (x, y, z) that a sphere of radius r at
@@ -2221,6 +2224,28 @@ __device__ double overlap_fraction(const Geom &g, const double Rc[3], double r, 
     return static_cast<double>(in) / static_cast<double>(ns * ns * ns);
 }
 
+// Do two (possibly wrapped) boxes share a cell?
+__device__ bool boxes_meet(const Geom &g, const Box &a, const Box &b)
+{
+    const int len[3] = {g.nx, g.ny, g.nz};
+    for (int k = 0; k < 3; ++k) {
+        if (a.ext[k] <= 0 || b.ext[k] <= 0)
+            return false;
+        bool meet;
+        if (g.per[k]) {
+            int ab = (b.lo[k] - a.lo[k]) % len[k], ba = (a.lo[k] - b.lo[k]) % len[k];
+            ab = ab < 0 ? ab + len[k] : ab;
+            ba = ba < 0 ? ba + len[k] : ba;
+            meet = ab < a.ext[k] || ba < b.ext[k];
+        } else {
+            meet = a.lo[k] < b.lo[k] + b.ext[k] && b.lo[k] < a.lo[k] + a.ext[k];
+        }
+        if (!meet)
+            return false;
+    }
+    return true;
+}
+
 // Is (x, y, z) inside the (possibly wrapped) box?
 __device__ __forceinline__ bool in_box(const Geom &g, const Box &bx, int x, int y, int z)
 {
@@ -2249,13 +2274,6 @@ __global__ __launch_bounds__(CONV_THREADS) void conversion_kernel(Geom g, Bound 
     T *f = static_cast<T *>(fv);
     __shared__ int go;
     if (threadIdx.x == 0) {
-        go = counters[3];
-        counters[3] = 0;
-    }
-    __syncthreads();
-    if (!go && b.smooth_ns <= 0)
-        return;
-    if (threadIdx.x == 0) {
         int k = 0;
         for (int p = 0; p < b.n_parts; ++p)
             if (parts[p].movable)
@@ -2263,7 +2281,39 @@ __global__ __launch_bounds__(CONV_THREADS) void conversion_kernel(Geom g, Bound 
         n_moving = k;
     }
     __syncthreads();
-    ConvCtx c{g, parts, b.n_parts, mask, moving, n_moving};
+    // A particle writes cells up to one beyond its margin-2 box (populations
+    // of uncovered cells' neighbours) and reads up to two beyond it, so blocks
+    // of different particles share no cell when no particle's box widened by
+    // 3 meets another's box.  Otherwise block 0 takes every particle in turn.
+    const int nm = n_moving;
+    bool clash = false;
+    for (int k = threadIdx.x; k < nm * nm; k += CONV_THREADS) {
+        const int i = k / nm, j = k - (k / nm) * nm;
+        if (i != j && boxes_meet(g, particle_box(g, parts[moving[i]], 5),
+                                 particle_box(g, parts[moving[j]], 2)))
+            clash = true;
+    }
+    const bool serial = __syncthreads_or(clash ? 1 : 0) != 0 || b.conv_serial != 0;
+    if (serial ? blockIdx.x != 0 : static_cast<int>(blockIdx.x) >= nm)
+        return;
+    const int q0 = serial ? 0 : static_cast<int>(blockIdx.x);
+    const int q1 = serial ? nm : q0 + 1;
+    if (threadIdx.x == 0) {
+        int any = 0;
+        for (int q = q0; q < q1; ++q) {
+            any |= counters[4 + moving[q]];
+            counters[4 + moving[q]] = 0;
+        }
+        go = any;
+    }
+    __syncthreads();
+    if (!go && b.smooth_ns <= 0)
+        return;
+    // With one block per particle no other movable sphere reaches the cells
+    // this block reads (each sphere lies inside its margin-2 box, and the
+    // boxes stay three cells apart), so the coverage tests need only this
+    // block's particle.
+    ConvCtx c{g, parts, b.n_parts, mask, moving + q0, q1 - q0};
     const uint64_t PL = g.plane;
     auto cell = [&](int x, int y, int z) {
         return static_cast<uint32_t>(x) + static_cast<uint32_t>(g.nx) * (y + static_cast<uint32_t>(g.ny) * z);
@@ -2277,7 +2327,7 @@ __global__ __launch_bounds__(CONV_THREADS) void conversion_kernel(Geom g, Bound 
     // fraction go to scratch planes 0 and 1; then, one stress component at a
     // time, every receiver gathers into plane 2 and every cell applies.
     if (b.smooth_ns > 0)
-        for (int q = 0; q < n_moving; ++q) {
+        for (int q = q0; q < q1; ++q) {
             const Particle P = parts[moving[q]];
             const Box bx = particle_box(g, P, 2);
             const uint32_t vol = static_cast<uint32_t>(bx.ext[0]) * bx.ext[1] * bx.ext[2];
@@ -2336,7 +2386,7 @@ __global__ __launch_bounds__(CONV_THREADS) void conversion_kernel(Geom g, Bound 
     // stress is shared among the D3Q19 neighbours that stay fluid (gathered
     // by each receiver).
     int covers = 0, dropped = 0;
-    for (int q = 0; q < n_moving; ++q) {
+    for (int q = q0; q < q1; ++q) {
         const int p = moving[q];
         const Particle P = parts[p];
         const uint8_t me = static_cast<uint8_t>(PART0 + p);
@@ -2398,7 +2448,7 @@ __global__ __launch_bounds__(CONV_THREADS) void conversion_kernel(Geom g, Bound 
         __syncthreads();
     }
     // Phase 2: covered cells hold no stress.
-    for (int q = 0; q < n_moving; ++q) {
+    for (int q = q0; q < q1; ++q) {
         const int p = moving[q];
         const Particle P = parts[p];
         const uint8_t me = static_cast<uint8_t>(PART0 + p);
@@ -2418,7 +2468,7 @@ __global__ __launch_bounds__(CONV_THREADS) void conversion_kernel(Geom g, Bound 
     // neighbours that stay fluid and the surface velocity; the particle pays
     // the created momentum; the stress is the neighbours' sum / (N_f + 1).
     int uncovers = 0;
-    for (int q = 0; q < n_moving; ++q) {
+    for (int q = q0; q < q1; ++q) {
         const int p = moving[q];
         const Particle P = parts[p];
         const uint8_t me = static_cast<uint8_t>(PART0 + p);
@@ -2482,7 +2532,7 @@ __global__ __launch_bounds__(CONV_THREADS) void conversion_kernel(Geom g, Bound 
         __syncthreads();
     }
     // Phase 4: the neighbours give up what the uncovered cells took.
-    for (int q = 0; q < n_moving; ++q) {
+    for (int q = q0; q < q1; ++q) {
         const int p = moving[q];
         const Particle P = parts[p];
         const uint8_t me = static_cast<uint8_t>(PART0 + p);
@@ -2515,7 +2565,7 @@ __global__ __launch_bounds__(CONV_THREADS) void conversion_kernel(Geom g, Bound 
         __syncthreads();
     }
     // Phase 5: the new mask.
-    for (int q = 0; q < n_moving; ++q) {
+    for (int q = q0; q < q1; ++q) {
         const int p = moving[q];
         const Particle P = parts[p];
         const uint8_t me = static_cast<uint8_t>(PART0 + p);
@@ -2899,14 +2949,15 @@ hipError_t launch_conversion(int storage, const Geom &g, const Bound &b, uint8_t
 {
     if (b.n_parts > 0) {
         hipLaunchKernelGGL(conversion_check_kernel, dim3(CONV_CHECK_BLOCKS, b.n_parts), dim3(BLOCK),
-                           0, s, g, b.parts, mask, counters + 3);
+                           0, s, g, b.parts, mask, counters + 4);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             return e;
     }
     return dispatch(storage, [&](auto st) {
-        hipLaunchKernelGGL(conversion_kernel<decltype(st)::value>, dim3(1), dim3(CONV_THREADS), 0,
-                           s, g, b, mask, f, tau, scale, inv_scale, counters, scratch);
+        const uint32_t blocks = b.n_parts > 1 ? static_cast<uint32_t>(b.n_parts) : 1u;
+        hipLaunchKernelGGL(conversion_kernel<decltype(st)::value>, dim3(blocks), dim3(CONV_THREADS),
+                           0, s, g, b, mask, f, tau, scale, inv_scale, counters, scratch);
         return hipGetLastError();
     });
 }
