@@ -195,6 +195,7 @@ struct vlb_lattice {
     }
     double *d_out = nullptr;
     int32_t *d_counters = nullptr;
+    uint8_t *d_owner = nullptr;  // new owner of each cell near a converting particle
     int n_walls = 0;
     std::vector<double> wall_h;
     std::vector<Particle> parts_h;  // host copy of static particle data
@@ -358,7 +359,7 @@ void free_all(vlb_lattice *lat)
             }
     void *ptrs[] = {lat->d_wall,   lat->d_parts, lat->d_partials, lat->d_out,
                     lat->d_counters, lat->d_pforce, lat->d_count, lat->d_g3,
-                    lat->d_wfield, lat->d_gfield, lat->d_step};
+                    lat->d_wfield, lat->d_gfield, lat->d_step, lat->d_owner};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -452,7 +453,7 @@ size_t vlb_required_bytes(const vlb_dims *dims, vlb_storage storage, int32_t n_p
     const uint64_t pops = 2ull * vlb::Q * P * storage_bytes(storage);
     const uint64_t tau = 2ull * 6 * P * sizeof(float);
     const uint64_t u = 3ull * P * sizeof(float);
-    const uint64_t mask = round_up(N, 256);
+    const uint64_t mask = 2 * round_up(N, 256);  // the mask and the conversion's owner map
     const uint64_t small = sizeof(Particle) * vlb::MAX_PARTICLES + 64 * 3 * sizeof(double) +
                            2048 * 8 * sizeof(double) + 4096 +
                            vlb::MAX_PARTICLES * vlb::PF_BLOCKS * 12 * sizeof(double);
@@ -608,6 +609,8 @@ vlb_status create_impl(const vlb_dims *dims, const uint8_t *mask, const double *
     if ((e = hipMemsetAsync(lat->d_counters, 0, n_counters * sizeof(int32_t), lat->stream)) !=
         hipSuccess)
         return bail(e, "counters");
+    if ((e = hipMalloc(&lat->d_owner, round_up(N, 256))) != hipSuccess)
+        return bail(e, "owner map");
     if ((e = hipMemcpyAsync(lat->d_mask, mask, N, hipMemcpyHostToDevice, lat->stream)) != hipSuccess)
         return bail(e, "mask upload");
     if ((e = hipMemcpyAsync(lat->d_wall, lat->wall_h.data(), 64 * 3 * sizeof(double),
@@ -910,7 +913,8 @@ hipError_t launch_step(vlb_lattice *lat, const vlb::StepArgs &a, bool counter, i
                                         lat->d_pforce, st, lat->stress_map());
         if (e == hipSuccess)
             e = vlb::launch_conversion(lat->storage, lat->g, a.b, lat->d_mask, a.fout, a.tout,
-                                       lat->scale, lat->inv_scale, lat->d_counters, lat->d_u, st);
+                                       lat->scale, lat->inv_scale, lat->d_counters, lat->d_u,
+                                       lat->d_owner, st);
         if (e == hipSuccess && counter)
             e = vlb::launch_body_force(lat->g, lat->d_mask, lat->d_parts, np,
                                        lat->params.body_force, lat->d_count, lat->d_g3, st);

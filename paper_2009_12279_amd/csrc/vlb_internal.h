@@ -233,9 +233,10 @@ hipError_t launch_wall_force(int storage, const Geom &g, const uint8_t *mask, co
                              double *out, hipStream_t s, const StressMap &sm = StressMap{});
 // Fluid/solid conversion around every movable particle.  scratch: 3 float
 // planes (stride g.plane) the smoothing may overwrite (the step's velocity
-// planes, dead by then).
+// planes, dead by then); owner: g.N bytes for the new owner of the cells
+// near the particles.
 hipError_t launch_conversion(int storage, const Geom &g, const Bound &b, uint8_t *mask, void *f,
                              float *tau, float scale, float inv_scale, int32_t *counters,
-                             float *scratch, hipStream_t s);
+                             float *scratch, uint8_t *owner, hipStream_t s);
 
 }  // namespace vlb

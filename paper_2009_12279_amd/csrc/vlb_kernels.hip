@@ -2118,6 +2118,7 @@ struct ConvCtx {
     const uint8_t *mask;
     const int *moving;  // indices of movable particles (LDS)
     int n_moving;
+    const uint8_t *owner = nullptr;  // new owner of every cell the phases look at
 };
 
 __device__ bool inside_sphere(const Geom &g, const Particle &P, int x, int y, int z)
@@ -2129,7 +2130,10 @@ __device__ bool inside_sphere(const Geom &g, const Particle &P, int x, int y, in
     return d2 < P.radius * P.radius;
 }
 
-__device__ uint8_t new_owner(const ConvCtx &c, uint32_t n, int x, int y, int z)
+// The owner of cell n after this step's moves: its particle while the
+// particle still covers it, the first movable particle that covers a fluid
+// cell, else the old mask byte.
+__device__ uint8_t compute_owner(const ConvCtx &c, uint32_t n, int x, int y, int z)
 {
     const uint8_t m = c.mask[n];
     if (m >= PART0) {
@@ -2146,6 +2150,13 @@ __device__ uint8_t new_owner(const ConvCtx &c, uint32_t n, int x, int y, int z)
         }
     }
     return m;
+}
+
+// The same from the owner map the conversion kernel fills first (one
+// coverage test per cell instead of one per look).
+__device__ __forceinline__ uint8_t new_owner(const ConvCtx &c, uint32_t n, int, int, int)
+{
+    return c.owner[n];
 }
 
 __device__ __forceinline__ bool stays_fluid(const ConvCtx &c, uint32_t n, int x, int y, int z)
@@ -2263,7 +2274,7 @@ template <int S>
 __global__ __launch_bounds__(CONV_THREADS) void conversion_kernel(Geom g, Bound b, uint8_t *mask,
                                                                   void *fv, float *tau, float scale,
                                                                   float inv_scale, int32_t *counters,
-                                                                  float *scratch)
+                                                                  float *scratch, uint8_t *owner)
 {
     using St = Store<S>;
     using T = typename St::T;
@@ -2287,6 +2298,8 @@ __global__ __launch_bounds__(CONV_THREADS) void conversion_kernel(Geom g, Bound 
     // 3 meets another's box.  Otherwise block 0 takes every particle in turn.
     const int nm = n_moving;
     bool clash = false;
+    // (the owner map below covers two cells beyond each box, which the
+    // widening by 3 keeps apart as well)
     for (int k = threadIdx.x; k < nm * nm; k += CONV_THREADS) {
         const int i = k / nm, j = k - (k / nm) * nm;
         if (i != j && boxes_meet(g, particle_box(g, parts[moving[i]], 5),
@@ -2318,6 +2331,21 @@ __global__ __launch_bounds__(CONV_THREADS) void conversion_kernel(Geom g, Bound 
     auto cell = [&](int x, int y, int z) {
         return static_cast<uint32_t>(x) + static_cast<uint32_t>(g.nx) * (y + static_cast<uint32_t>(g.ny) * z);
     };
+    // The owner map over every cell the phases look at: up to two cells
+    // beyond each particle's margin-2 box.  Boxes of this block's particles
+    // may overlap; their cells then get the same value twice.
+    for (int q = q0; q < q1; ++q) {
+        const Box bx = particle_box(g, parts[moving[q]], 4);
+        const uint32_t vol = static_cast<uint32_t>(bx.ext[0]) * bx.ext[1] * bx.ext[2];
+        for (uint32_t k = threadIdx.x; k < vol; k += CONV_THREADS) {
+            int x, y, z;
+            box_cell(g, bx, k, x, y, z);
+            const uint32_t n = cell(x, y, z);
+            owner[n] = compute_owner(c, n, x, y, z);
+        }
+    }
+    __syncthreads();
+    c.owner = owner;
 
     // Phase 0 (overlap-fraction smoothing, particle by particle): a cell
     // that is fluid, stays fluid and is overlapped more by the particle than
@@ -2945,7 +2973,7 @@ hipError_t launch_body_force(const Geom &g, const uint8_t *mask, const Particle 
 
 hipError_t launch_conversion(int storage, const Geom &g, const Bound &b, uint8_t *mask, void *f,
                              float *tau, float scale, float inv_scale, int32_t *counters,
-                             float *scratch, hipStream_t s)
+                             float *scratch, uint8_t *owner, hipStream_t s)
 {
     if (b.n_parts > 0) {
         hipLaunchKernelGGL(conversion_check_kernel, dim3(CONV_CHECK_BLOCKS, b.n_parts), dim3(BLOCK),
@@ -2957,7 +2985,7 @@ hipError_t launch_conversion(int storage, const Geom &g, const Bound &b, uint8_t
     return dispatch(storage, [&](auto st) {
         const uint32_t blocks = b.n_parts > 1 ? static_cast<uint32_t>(b.n_parts) : 1u;
         hipLaunchKernelGGL(conversion_kernel<decltype(st)::value>, dim3(blocks), dim3(CONV_THREADS),
-                           0, s, g, b, mask, f, tau, scale, inv_scale, counters, scratch);
+                           0, s, g, b, mask, f, tau, scale, inv_scale, counters, scratch, owner);
         return hipGetLastError();
     });
 }
