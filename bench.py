@@ -97,7 +97,28 @@ def build_workload(storage, steps_hint=0):
     return shape, spheres, params
 
 
-def run_gpu(args, law=None):
+SETTLE_S = 0.1
+
+
+def settle_gpu(seconds=SETTLE_S):
+    """Keep the GPU busy with device copies for `seconds` before the warm-up
+    steps: its clocks ramp up under load, and a fresh lattice's first 20
+    steps after 5 warm-up steps otherwise run about 5 % slower than the steady
+    state.  No step of the workload runs here."""
+    import torch
+
+    src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        for _ in range(10):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+    del src, dst
+
+
+def run_gpu(args, law=None, repeats=0):
     import torch
 
     from paper_2009_12279_amd import vlb
@@ -122,6 +143,7 @@ def run_gpu(args, law=None):
         lat.set_fene_p(100.0)
     fluid = int((lat.mask() == 0).sum())
 
+    settle_gpu()
     lat.step(args.warmup)
     torch.cuda.synchronize()
     # timed region: K steps, bracketed by device synchronisation
@@ -136,6 +158,14 @@ def run_gpu(args, law=None):
     gpu_ms = ev0.elapsed_time(ev1)
     ms_per_step = gpu_ms / args.steps
     mlups = N * args.steps / (gpu_ms / 1e3) / 1e6
+    # further repetitions of the same K steps, after the timed region
+    reps = []
+    for _ in range(repeats):
+        ev0.record(stream)
+        lat.step(args.steps)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        reps.append(ev0.elapsed_time(ev1) / args.steps)
 
     # per-kernel durations: HIP events recorded by the library on the same
     # stream around every launch, averaged over a second timed pass
@@ -153,7 +183,7 @@ def run_gpu(args, law=None):
     step_achieved = alg["step"] * N / (sum(k_ms.values()) * 1e-3) / 1e9
     lat.close()
     return dict(N=N, fluid=fluid, shape=shape, params=params, ms_per_step=ms_per_step, mlups=mlups,
-                wall_s=wall, kernels=k_ms, dominant=dom, per_kernel=per_kernel,
+                repeats=reps, wall_s=wall, kernels=k_ms, dominant=dom, per_kernel=per_kernel,
                 step_achieved=step_achieved, alg=alg, health=health)
 
 
@@ -162,6 +192,7 @@ def _time_lattice(lat, args, stream):
     times of a second timed pass."""
     import torch
 
+    settle_gpu()
     lat.step(args.warmup)
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -265,36 +296,60 @@ def run_cpu_baseline(args):
         single = timed(args.cpu_steps_single)
         oracle.set_threads(0)
     L.close()
-    # the fixed-sphere duct, 128 x 64 x 64 with a sphere of radius 8
     from paper_2009_12279_amd import inputs
-    dshape = (128, 64, 64)
-    D = oracle.Lattice(dshape, inputs.channel_mask(dshape, wall_axes=(1, 2)), (1, 0, 0))
-    D.set_params(eta=1.0 / 3.0, beta=0.5, lambda_p=1000.0, magic=3.0 / 16.0,
-                 body_force=(1e-6, 0.0, 0.0))
-    D.add_sphere((63.5, 31.5, 31.5), 8.0)
-    D.init_equilibrium()
-    ncell = dshape[0] * dshape[1] * dshape[2]
 
-    def dtimed(n):
-        D.step(1)
+    def duct_rates(dshape, r, n_all, n_single):
+        """The fixed-sphere duct (walls in y and z, periodic x, sphere at the
+        centre, lambda_p = 1000): n_all steps on every thread, n_single on 1."""
+        D = oracle.Lattice(dshape, inputs.channel_mask(dshape, wall_axes=(1, 2)), (1, 0, 0))
+        D.set_params(eta=1.0 / 3.0, beta=0.5, lambda_p=1000.0, magic=3.0 / 16.0,
+                     body_force=(1e-6, 0.0, 0.0))
+        D.add_sphere(tuple((n - 1) / 2.0 for n in dshape), r)
+        D.init_equilibrium()
+        ncell = dshape[0] * dshape[1] * dshape[2]
+
+        def dtimed(n):
+            D.step(1)
+            t0 = time.perf_counter()
+            D.step(n)
+            return ncell * n / (time.perf_counter() - t0) / 1e6
+
+        out = dict(all_cores=round(dtimed(n_all), 3))
+        oracle.set_threads(1)
+        out["single_thread"] = round(dtimed(n_single), 3)
+        oracle.set_threads(0)
+        D.close()
+        return dict(out, unit="MLUPS", sample=f"{n_all} steps on {threads} threads, "
+                                              f"{n_single} steps on 1, after 1 untimed step")
+
+    duct = duct_rates((128, 64, 64), 8.0, 40, 10)
+    duct_copy = duct_rates((64, 32, 32), 4.0, 200, 50)
+    # the serving list solved one after another by the oracle: the first 4
+    # requests, 10 steps each (each after 1 untimed step)
+    reqs = serving_requests(4, 1.0)
+    cells = 0
+    secs = 0.0
+    for r in reqs:
+        S = oracle.Lattice(r["shape"], r["mask"], r["periodic"])
+        S.set_params(**r["params"])
+        for c in r["spheres"]:
+            S.add_sphere(tuple(c[:3]), c[3])
+        S.init_equilibrium()
+        S.step(1)
         t0 = time.perf_counter()
-        D.step(n)
-        return ncell * n / (time.perf_counter() - t0) / 1e6
-
-    duct = dict(all_cores=round(dtimed(40), 3))
-    oracle.set_threads(1)
-    duct["single_thread"] = round(dtimed(10), 3)
-    oracle.set_threads(0)
-    D.close()
+        S.step(10)
+        secs += time.perf_counter() - t0
+        cells += int(np.prod(r["shape"])) * 10
+        S.close()
+    serving_seq = dict(all_cores=round(cells / secs / 1e6, 3), unit="MLUPS",
+                       sample=f"the first 4 serving requests, 10 steps each, {threads} threads")
     return dict(value=all_cores, unit="MLUPS", cores=threads, kind="oracle",
                 sample=f"the same 256^3 workload, {args.cpu_steps} steps after 1 untimed step "
                        f"(FP64 oracle, OpenMP {threads} threads)",
                 single_thread=None if single is None else dict(
                     value=single, unit="MLUPS", cores=1,
                     sample=f"{args.cpu_steps_single} steps after 1 untimed step, 1 thread"),
-                duct_128x64x64=dict(duct, unit="MLUPS",
-                                    sample="fixed-sphere duct, r = 8, lambda_p = 1000: 40 steps "
-                                           f"on {threads} threads, 10 steps on 1"))
+                duct_128x64x64=duct, duct_64x32x32=duct_copy, serving_sequential=serving_seq)
 
 
 def serving_requests(n, steps_scale):
@@ -457,7 +512,7 @@ def main():
               "(the multi-GPU slab decomposition is a design note, not built)", file=sys.stderr)
         sys.exit(2)
     rank = int(os.environ.get("RANK", "0"))
-    g = run_gpu(args)
+    g = run_gpu(args, repeats=5)
     if args.copy_calibration:
         import torch
         src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda:0")
@@ -532,6 +587,11 @@ def main():
                         f"beta={g['params']['beta']:.4f}",
             "cells": g["N"],
             "fluid_cells": g["fluid"],
+            "fluid_mflups": round(g["fluid"] / (g["ms_per_step"] * 1e-3) / 1e6, 1),
+            "repeats_ms_per_step": [round(x, 4) for x in g["repeats"]],
+            "repeats_median_ms_per_step": (round(float(np.median(g["repeats"])), 4)
+                                           if g["repeats"] else None),
+            "clock_settle_ms": round(SETTLE_S * 1e3),
             "storage": args.storage,
             "arithmetic": dtype,
             "parallelism": "single GPU",
