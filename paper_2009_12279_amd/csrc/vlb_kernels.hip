@@ -98,7 +98,11 @@ struct Store;
 template <>
 struct Store<ST_F32> {
     using T = float;
+#ifdef VLB_F32_REGS
+    using R = float;  // measurement build: FP32 registers for FP32 storage
+#else
     using R = double;  // register type of the per-cell arithmetic
+#endif
     static __device__ __forceinline__ float ld(const T *p, uint64_t i, float)
     {
         return p[i];
