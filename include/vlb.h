@@ -341,6 +341,14 @@ vlb_status vlb_set_velocity_scale(vlb_lattice *lat, double u_max);
 /* The storage scale s in use (1 for FP32 and BF16; 2^10 for FP16 unless
  * vlb_set_velocity_scale chose another); 0 for a NULL lattice. */
 double vlb_storage_scale(const vlb_lattice *lat);
+
+/* Control experiment for the storage layout (not part of the method): when
+ * on, every step rounds each stored population f_i = w_i + h_i to the nearest
+ * FP32 number right after stream-collide, which is what storing the raw
+ * populations in FP32 would keep of them, so the deviations carry rounding
+ * errors of the size of w_i's last place instead of their own.  FP32 storage
+ * only (VLB_EINVAL otherwise); off by default and not kept in checkpoints. */
+vlb_status vlb_set_raw_f32_control(vlb_lattice *lat, int32_t on);
 double vlb_kernel_time_ms(const vlb_lattice *lat, int32_t which);
 
 /* ------------------------------------------------------------------------

@@ -181,6 +181,7 @@ struct vlb_lattice {
     double L2 = 0.0;              // FENE-P extensibility (0: off)
     int extrap = 0;               // stress extrapolation into solid neighbours
     int smooth_ns = 0;            // overlap sub-samples per axis of smoothed conversions (0: off)
+    bool raw_f32 = false;         // raw-FP32 storage control (not kept in checkpoints)
     vlb::StressMap stress_map() const
     {
         vlb::StressMap m;
@@ -230,6 +231,7 @@ struct vlb_lattice {
         b.walls_move = moving_walls ? 1 : 0;
         b.smooth_ns = smooth_ns;
         b.conv_serial = conv_serial() ? 1 : 0;
+        b.raw_f32 = raw_f32 ? 1 : 0;
         return b;
     }
 };
@@ -902,6 +904,8 @@ hipError_t launch_step(vlb_lattice *lat, const vlb::StepArgs &a, bool counter, i
         *fused_out = fused;
     if (e == hipSuccess && !fused)
         e = vlb::launch_lb_step(lat->storage, a, st);
+    if (e == hipSuccess && a.b.raw_f32)
+        e = vlb::launch_raw_f32_control(lat->g, a.fout, st);
     rec(1);
     if (e == hipSuccess && lat->polymer && !fused)
         e = vlb::launch_fv_step(lat->storage, a, st, tile_rows, z_chunk);
@@ -1822,6 +1826,16 @@ vlb_status vlb_set_rounding(vlb_lattice *lat, vlb_rounding mode, uint32_t seed)
         return fail(lat, VLB_EINVAL, "vlb_set_rounding: unknown mode");
     lat->rounding = mode;
     lat->seed = seed;
+    return VLB_OK;
+}
+
+vlb_status vlb_set_raw_f32_control(vlb_lattice *lat, int32_t on)
+{
+    if (!lat)
+        return VLB_EINVAL;
+    if (on && lat->storage != vlb::ST_F32)
+        return fail(lat, VLB_EINVAL, "vlb_set_raw_f32_control: FP32 storage only");
+    lat->raw_f32 = on != 0;
     return VLB_OK;
 }
 

@@ -72,6 +72,9 @@ struct Bound {
     // conversion in one block, particle after particle, even where the
     // particles' cells are far apart (VLB_CONV_SERIAL=1; the same bits)
     int32_t conv_serial = 0;
+    // raw-FP32 storage control: after stream-collide, every population is
+    // rounded to the FP32 grid of f rather than of f - w (FP32 storage only)
+    int32_t raw_f32 = 0;
 };
 
 // Map from the stored stress variable to the polymer stress.  Identity for
@@ -168,6 +171,8 @@ hipError_t launch_body_force(const Geom &g, const uint8_t *mask, const Particle 
                              int n_parts, const double body_force[3], uint32_t *count,
                              double *g_out, hipStream_t s);
 hipError_t launch_lb_step(int storage, const StepArgs &a, hipStream_t s);
+// Round the FP32 deviations at f (Q planes) so that w_i + h_i is an FP32 number.
+hipError_t launch_raw_f32_control(const Geom &g, void *f, hipStream_t s);
 // n_steps batched steps (stream-collide, stress update, counter advance per
 // step) over every solve of the table: stream-collide on max_blocks blocks
 // of BLOCK threads, the stress update on fv_blocks blocks of 64 x 4.

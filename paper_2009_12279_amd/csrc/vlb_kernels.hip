@@ -2648,6 +2648,29 @@ hipError_t dispatch(int storage, Fn fn)
 // ---------------------------------------------------------------------------
 // launchers
 
+// Control experiment for the storage layout: the populations f_i = w_i + h_i
+// that FP32 deviation storage holds, rounded to the nearest FP32 number, as
+// storing raw populations in FP32 would keep them (the deviations then carry
+// the rounding error of numbers near w_i instead of their own).
+__global__ __launch_bounds__(BLOCK) void raw_f32_control_kernel(float *f, uint64_t plane, uint32_t N)
+{
+    const uint32_t n = blockIdx.x * BLOCK + threadIdx.x;
+    const int i = static_cast<int>(blockIdx.y);
+    if (n >= N)
+        return;
+    const double w = i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
+    float *p = f + i * plane + n;
+    const float raw = static_cast<float>(w + static_cast<double>(*p));
+    *p = static_cast<float>(static_cast<double>(raw) - w);
+}
+
+hipError_t launch_raw_f32_control(const Geom &g, void *f, hipStream_t s)
+{
+    hipLaunchKernelGGL(raw_f32_control_kernel, dim3(blocks_for(g.N), Q), dim3(BLOCK), 0, s,
+                       static_cast<float *>(f), g.plane, g.N);
+    return hipGetLastError();
+}
+
 hipError_t launch_lb_step(int storage, const StepArgs &a, hipStream_t s)
 {
     return dispatch(storage, [&](auto st) {

@@ -106,6 +106,7 @@ SIGNATURES = [
     ("vlb_set_rounding", ctypes.c_int, [_P, ctypes.c_int, ctypes.c_uint32]),
     ("vlb_set_velocity_scale", ctypes.c_int, [_P, ctypes.c_double]),
     ("vlb_storage_scale", ctypes.c_double, [_P]),
+    ("vlb_set_raw_f32_control", ctypes.c_int, [_P, ctypes.c_int32]),
     ("vlb_set_counter_force", ctypes.c_int, [_P, ctypes.c_int32]),
     ("vlb_set_conversion_smoothing", ctypes.c_int, [_P, ctypes.c_int32]),
     ("vlb_set_giesekus", ctypes.c_int, [_P, ctypes.c_double]),
@@ -430,6 +431,10 @@ def vlb_storage_scale(h):
     return float(lib().vlb_storage_scale(h))
 
 
+def vlb_set_raw_f32_control(h, on=True):
+    return _check(lib().vlb_set_raw_f32_control(h, 1 if on else 0), h)
+
+
 # ---- convenience wrapper ------------------------------------------------------
 
 class Lattice:
@@ -562,6 +567,10 @@ class Lattice:
     @property
     def storage_scale(self):
         return vlb_storage_scale(self._h)
+
+    def set_raw_f32_control(self, on=True):
+        """Control experiment: keep the populations on the FP32 grid of f."""
+        vlb_set_raw_f32_control(self._h, on)
 
     def set_giesekus(self, alpha):
         vlb_set_giesekus(self._h, alpha)

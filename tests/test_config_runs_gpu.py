@@ -135,14 +135,20 @@ def test_settling_sphere_trajectory_full_length(name, wi, steps):
 def test_box256_storage_errors_against_the_oracle():
     """The 256^3 box with 64 fixed spheres after 100 and 1000 steps in FP32,
     FP16 and BF16 storage, at 8192 sampled fluid cells: FP32 within 1e-5
-    relative, the 16-bit errors printed."""
+    relative, the 16-bit errors printed; and the raw-FP32 control (the
+    populations themselves on the FP32 grid, rounded to nearest), whose
+    errors are printed beside them."""
     fx = _fixture("box256")
     shape = (256, 256, 256)
     spheres = inputs.place_spheres(4, 0, shape, 64, 6.0, 6.0, min_gap=2.0, periodic=(1, 1, 1))
     beta = float(inputs.Stream(4, 1).uniform(1, 0.1, 0.9)[0])
-    for storage in ("f32", "f16", "bf16"):
+    for storage in ("f32", "f16", "bf16", "raw"):
         log(f"[config] box256 {storage}")
-        L = vlb.Lattice(shape, np.zeros(shape[::-1], np.uint8), (1, 1, 1), storage=storage)
+        L = vlb.Lattice(shape, np.zeros(shape[::-1], np.uint8), (1, 1, 1),
+                        storage="f32" if storage == "raw" else storage)
+        if storage == "raw":
+            L.set_raw_f32_control(True)
+            L.set_rounding("nearest")
         L.set_params(eta=ETA, beta=beta, lambda_p=1000.0, magic=3 / 16, body_force=(1e-6, 0, 0))
         for c, r in spheres:
             L.add_sphere(center=c, radius=r)
@@ -158,7 +164,7 @@ def test_box256_storage_errors_against_the_oracle():
                 f"tau L2 {et[0]:.3e} max {et[1]:.3e}")
             if storage == "f32":
                 assert max(eu) < 1e-5 and max(et) < 1e-5
-            else:
+            elif storage != "raw":
                 assert max(eu) < 0.1 and max(et) < 0.1
         L.close()
 

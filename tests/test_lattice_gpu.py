@@ -62,16 +62,22 @@ def _duct_with_moving_sphere(storage):
     return L
 
 
-@pytest.mark.parametrize("storage,smoothing", [("f32", 0), ("f16", 0), ("bf16", 0), ("f32", 4)])
-def test_checkpoint_restart_is_bitwise(tmp_path, storage, smoothing):
+@pytest.mark.parametrize("storage,smoothing,u_max", [("f32", 0, None), ("f16", 0, None),
+                                                     ("bf16", 0, None), ("f32", 4, None),
+                                                     ("f16", 0, 2e-3)])
+def test_checkpoint_restart_is_bitwise(tmp_path, storage, smoothing, u_max):
     """Save, continue, and load + continue give the same bits; with
     smoothed conversions the sphere's previous position and the sample count
-    travel with the checkpoint."""
+    travel with the checkpoint, and an FP16 scale chosen from the flow speed
+    travels with the populations."""
     path = str(tmp_path / f"ck_{storage}.vlb")
-    log(f"[lattice] checkpoint restart storage={storage} smoothing={smoothing}")
+    log(f"[lattice] checkpoint restart storage={storage} smoothing={smoothing} u_max={u_max}")
     L = _duct_with_moving_sphere(storage)
     L.set_rounding("stochastic", 77)
     L.set_conversion_smoothing(smoothing)
+    if u_max is not None:
+        L.set_velocity_scale(u_max)
+        assert L.storage_scale == 2.0 ** 14
     L.step(100)
     L.save(path)
     m_saved = L.mask()
@@ -80,6 +86,8 @@ def test_checkpoint_restart_is_bitwise(tmp_path, storage, smoothing):
     L.close()
     R = vlb.Lattice.load(path, (20, 18, 26))
     assert R.step_count == 100
+    if u_max is not None:
+        assert R.storage_scale == 2.0 ** 14
     R.step(200)
     got = (R.populations(), R.stress(), R.mask(), R.particle(0), R.step_count)
     R.close()

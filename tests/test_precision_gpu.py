@@ -176,3 +176,40 @@ def test_fp16_channel_with_scale_from_the_flow_speed(g):
         chosen = [v for k, v in errs.items() if k != 1024.0][0]
         assert chosen["u"][1] < 0.25 * errs[1024.0]["u"][1]
         assert chosen["tau"][1] < 0.25 * errs[1024.0]["tau"][1]
+
+
+def test_raw_f32_control_keeps_populations_on_the_fp32_grid():
+    """With the raw-FP32 control on, every stored population f = w + h sits on
+    the FP32 grid after a step (as raw FP32 storage would hold it); off, the
+    deviations do, and the populations generally do not.  Other storage
+    formats refuse the control."""
+    shape = (12, 10, 8)
+    mask = inputs.channel_mask(shape, wall_axes=(1,))
+    u0 = inputs.noise_field(4, 0, shape, 1e-3)
+    u0[:, mask != 0] = 0
+    log("[precision] raw-FP32 control on a small channel")
+    out = {}
+    for on in (False, True):
+        L = vlb.Lattice(shape, mask, (1, 0, 1))
+        L.set_params(eta=1 / 3, beta=0.5, lambda_p=100.0, magic=3 / 16, body_force=(1e-6, 0, 0))
+        L.set_check_interval(0)
+        L.set_raw_f32_control(on)
+        L.init_equilibrium(u0)
+        L.step(3)
+        f = L.populations()
+        fl = L.mask() == 0
+        out[on] = f[:, fl]
+        L.close()
+    # the stored deviation of a rounded population is itself rounded to FP32,
+    # which moves it off the grid by at most 2^-24 of the deviation (about
+    # 1e-11 here), far below the grid spacing near w (2e-9 to 3e-8)
+    def off_grid(f):
+        return np.abs(f - f.astype(np.float32).astype(np.float64)).max()
+    log(f"[precision]   distance from the FP32 grid: on {off_grid(out[True]):.2e}, "
+        f"off {off_grid(out[False]):.2e}")
+    assert off_grid(out[True]) < 1e-10 < off_grid(out[False])
+    for storage in ("f16", "bf16"):
+        M = vlb.Lattice(shape, mask, (1, 0, 1), storage=storage)
+        with pytest.raises(vlb.VlbError):
+            M.set_raw_f32_control(True)
+        M.close()
