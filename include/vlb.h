@@ -368,8 +368,9 @@ double vlb_kernel_time_ms(const vlb_lattice *lat, int32_t which);
  * host memory after that round's replays are issued.  Requests submitted while
  * others run join at the next pump.  Each solve computes exactly what a lone
  * vlb_lattice with the same mask, parameters and rounding seed computes:
- * results do not depend on what else is in the batch.  Walls in a request
- * mask are at rest; moving particles are not served.
+ * results do not depend on what else is in the batch.  Served solves are
+ * Oldroyd-B or Giesekus (FENE-P is not served); walls in a request mask are
+ * at rest; moving particles are not served.
  */
 typedef enum vlb_request_state {
     VLB_REQ_QUEUED = 0,
@@ -387,6 +388,8 @@ typedef struct vlb_request {
     const double *spheres;  /* n_spheres x {cx, cy, cz, r}: fixed spheres, copied     */
     int64_t n_steps;
     uint32_t seed;          /* stochastic-rounding seed (vlb_set_rounding)           */
+    double giesekus_alpha;  /* Giesekus mobility in [0, 1/2] (vlb_set_giesekus);
+                               0 for Oldroyd-B                                       */
 } vlb_request;
 
 typedef struct vlb_server_stats {

@@ -1595,15 +1595,22 @@ __global__ __launch_bounds__(FV_TX * 4) void fv_batch_kernel(const BatchTable *_
     const VLB_CONST_AS StepArgs &a = bs.args[step & 1u];
     const int tid = static_cast<int>(threadIdx.x + FV_TX * threadIdx.y);
     const uint32_t lb = b - bs.fv_first_block;
-    // served solves are Oldroyd-B
+    // served solves are Oldroyd-B or Giesekus (the law is uniform per block)
+    const bool gk = a.gk != 0.f;
     if (bs.fv_tiled) {
-        fv_tile_block<SR, LAW_OB, 4>(a, lb, bs.fv_zc, step, false, tid, lds);
+        if (gk)
+            fv_tile_block<SR, LAW_GIESEKUS, 4>(a, lb, bs.fv_zc, step, false, tid, lds);
+        else
+            fv_tile_block<SR, LAW_OB, 4>(a, lb, bs.fv_zc, step, false, tid, lds);
         return;
     }
     const uint32_t n = lb * (FV_TX * 4) + static_cast<uint32_t>(tid);
     if (n >= a.g.N)
         return;
-    fv_cell<SR, LAW_OB>(a, n, step);
+    if (gk)
+        fv_cell<SR, LAW_GIESEKUS>(a, n, step);
+    else
+        fv_cell<SR, LAW_OB>(a, n, step);
 }
 
 __global__ void set_step_kernel(uint32_t *step, uint32_t value, int add)

@@ -47,6 +47,7 @@ struct Request {
     vlb_dims dims{};
     std::vector<uint8_t> mask;
     vlb_params params{};
+    double alpha = 0.0;  // Giesekus mobility (0: Oldroyd-B)
     uint32_t steps = 0;
     uint32_t seed = 0;
     int state = VLB_REQ_QUEUED;
@@ -262,6 +263,7 @@ void make_args(vlb_server *srv, Slot &sl, const Request &rq)
         if (a.polymer) {
             a.eta_p_lam = rq.params.beta * rq.params.eta / rq.params.lambda_p;
             a.inv_lam = 1.0 / rq.params.lambda_p;
+            a.gk = static_cast<float>(rq.alpha / (rq.params.beta * rq.params.eta));
         }
         a.scale = 1.f;
         a.inv_scale = 1.f;
@@ -774,6 +776,8 @@ vlb_status vlb_server_submit(vlb_server *srv, const vlb_request *req, uint64_t *
     double wp, wm;
     if (!params_ok(req->params, wp, wm))
         return sfail(srv, VLB_EINVAL, "vlb_server_submit: invalid parameters");
+    if (!(req->giesekus_alpha >= 0.0 && req->giesekus_alpha <= 0.5))
+        return sfail(srv, VLB_EINVAL, "vlb_server_submit: Giesekus alpha must lie in [0, 1/2]");
     if (footprint(d) > srv->budget)
         return sfail(srv, VLB_EBUSY, "vlb_server_submit: request exceeds the memory budget");
     Request rq;
@@ -850,6 +854,7 @@ vlb_status vlb_server_submit(vlb_server *srv, const vlb_request *req, uint64_t *
                 }
     }
     rq.params = req->params;
+    rq.alpha = req->giesekus_alpha;
     rq.steps = static_cast<uint32_t>(req->n_steps);
     rq.seed = req->seed;
     rq.submitted = clock_type::now();

@@ -47,7 +47,8 @@ class vlb_params(ctypes.Structure):
 class vlb_request(ctypes.Structure):
     _fields_ = [("dims", vlb_dims), ("mask", ctypes.c_char_p), ("params", vlb_params),
                 ("n_spheres", ctypes.c_int32), ("spheres", ctypes.POINTER(ctypes.c_double)),
-                ("n_steps", ctypes.c_int64), ("seed", ctypes.c_uint32)]
+                ("n_steps", ctypes.c_int64), ("seed", ctypes.c_uint32),
+                ("giesekus_alpha", ctypes.c_double)]
 
 
 class vlb_server_stats(ctypes.Structure):
@@ -638,7 +639,7 @@ def vlb_server_set_rounding(srv, mode="stochastic"):
 
 
 def vlb_server_submit(srv, shape, mask, periodic=(1, 1, 1), params=None, spheres=(), n_steps=1,
-                      seed=0x2009):
+                      seed=0x2009, giesekus_alpha=0.0):
     nx, ny, nz = shape
     m = np.ascontiguousarray(mask, dtype=np.uint8)
     if m.shape != (nz, ny, nx):
@@ -660,6 +661,7 @@ def vlb_server_submit(srv, shape, mask, periodic=(1, 1, 1), params=None, spheres
     req.spheres = _dp(sp) if sp.shape[0] else None
     req.n_steps = int(n_steps)
     req.seed = int(seed) & 0xFFFFFFFF
+    req.giesekus_alpha = float(giesekus_alpha)
     ticket = ctypes.c_uint64()
     _scheck(lib().vlb_server_submit(srv, ctypes.byref(req), ctypes.byref(ticket)), srv)
     return ticket.value

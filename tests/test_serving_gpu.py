@@ -45,6 +45,12 @@ REQS = [
 ]
 
 
+def submit(srv, r):
+    return vlb.vlb_server_submit(srv, **{k: r[k] for k in (
+        "shape", "mask", "periodic", "params", "spheres", "n_steps", "seed", "giesekus_alpha")
+        if k in r})
+
+
 def serve(reqs, budget=4 * GB, slots=16, k=10, stagger=True):
     srv = vlb.vlb_server_create(budget, slots, k)
     try:
@@ -52,8 +58,7 @@ def serve(reqs, budget=4 * GB, slots=16, k=10, stagger=True):
         pending = list(reqs)
         # submit the first one, then the others while it runs
         first = pending.pop(0)
-        tickets[first["seed"]] = (vlb.vlb_server_submit(srv, **{k2: first[k2] for k2 in (
-            "shape", "mask", "periodic", "params", "spheres", "n_steps", "seed")}), first)
+        tickets[first["seed"]] = (submit(srv, first), first)
         out = {}
         rounds = 0
         while len(out) < len(reqs):
@@ -61,8 +66,7 @@ def serve(reqs, budget=4 * GB, slots=16, k=10, stagger=True):
             rounds += 1
             if pending and (not stagger or rounds % 2 == 0):
                 r = pending.pop(0)
-                tickets[r["seed"]] = (vlb.vlb_server_submit(srv, **{k2: r[k2] for k2 in (
-                    "shape", "mask", "periodic", "params", "spheres", "n_steps", "seed")}), r)
+                tickets[r["seed"]] = (submit(srv, r), r)
             for seed, (t, r) in tickets.items():
                 if seed not in out and vlb.vlb_server_poll(srv, t) == "done":
                     out[seed] = vlb.vlb_server_result(srv, t, r["shape"])
@@ -74,6 +78,9 @@ def serve(reqs, budget=4 * GB, slots=16, k=10, stagger=True):
 
 def test_results_identical_alone_and_in_the_mix():
     reqs = [make_request(*r) for r in REQS]
+    # two Giesekus solves (per-cell and tiled) among the Oldroyd-B ones
+    reqs[1]["giesekus_alpha"] = 0.25
+    reqs[4]["giesekus_alpha"] = 0.4
     log("[serving] mix of 4 requests, staggered submission")
     mixed, stats = serve(reqs)
     log(f"[serving]   stats {stats}")
@@ -104,17 +111,22 @@ def test_result_buffer_grows_between_readouts():
             np.testing.assert_array_equal(a, b)
 
 
-@pytest.mark.parametrize("shape", [(18, 16, 14), (64, 16, 12), (128, 13, 37)])
-def test_served_solve_equals_plain_lattice(shape):
+@pytest.mark.parametrize("shape,alpha", [((18, 16, 14), 0.0), ((64, 16, 12), 0.0),
+                                         ((128, 13, 37), 0.0), ((18, 16, 14), 0.3),
+                                         ((64, 16, 12), 0.3)])
+def test_served_solve_equals_plain_lattice(shape, alpha):
     """Per-cell (18 wide) and tiled (64 and 128 wide; ragged y tiles and
     z chunks) stress updates in the batch give the bits of the lattice's own
-    step."""
+    step, for Oldroyd-B and for the Giesekus law."""
     r = make_request(7, shape, 150, 1)
-    log(f"[serving] served vs plain lattice {shape}")
+    r["giesekus_alpha"] = alpha
+    log(f"[serving] served vs plain lattice {shape} alpha={alpha}")
     out, _ = serve([r], slots=2, k=7)
     us, ts, _ = out[r["seed"]]
     L = vlb.Lattice(r["shape"], r["mask"], r["periodic"])
     L.set_params(**r["params"])
+    if alpha:
+        L.set_giesekus(alpha)
     for (cx, cy, cz, rad) in r["spheres"]:
         L.add_sphere(center=(cx, cy, cz), radius=rad)
     L.set_rounding("stochastic", r["seed"])
@@ -193,3 +205,16 @@ def test_served_solve_matches_oracle():
     et = np.max(np.abs(ts[:, fl] - to[:, fl])) / np.max(np.abs(to[:, fl]))
     log(f"[serving] vs oracle: u {eu:.2e} tau {et:.2e}")
     assert eu < 1e-5 and et < 1e-5
+
+
+def test_submit_refuses_a_giesekus_alpha_outside_its_range():
+    r = make_request(40, (12, 10, 8), 10, 0)
+    srv = vlb.vlb_server_create(GB, 2, 5)
+    try:
+        for bad in (-0.1, 0.7, float("nan")):
+            r["giesekus_alpha"] = bad
+            with pytest.raises(vlb.VlbError) as ei:
+                submit(srv, r)
+            assert ei.value.status == vlb.VLB_EINVAL
+    finally:
+        vlb.vlb_server_destroy(srv)
