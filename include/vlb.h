@@ -369,8 +369,9 @@ double vlb_kernel_time_ms(const vlb_lattice *lat, int32_t which);
  * others run join at the next pump.  Each solve computes exactly what a lone
  * vlb_lattice with the same mask, parameters and rounding seed computes:
  * results do not depend on what else is in the batch.  Served solves are
- * Oldroyd-B or Giesekus (FENE-P is not served); walls in a request mask are
- * at rest; moving particles are not served.
+ * Oldroyd-B or Giesekus (FENE-P is not served); walls in a request mask move
+ * with the request's wall velocities (at rest by default); fixed spheres are
+ * solid cells at rest; moving particles are not served.
  */
 typedef enum vlb_request_state {
     VLB_REQ_QUEUED = 0,
@@ -382,7 +383,7 @@ typedef enum vlb_request_state {
 
 typedef struct vlb_request {
     vlb_dims dims;
-    const uint8_t *mask;    /* N bytes: 0 fluid, 1..63 solid at rest; copied        */
+    const uint8_t *mask;    /* N bytes: 0 fluid, 1..63 solid (wall id); copied      */
     vlb_params params;
     int32_t n_spheres;
     const double *spheres;  /* n_spheres x {cx, cy, cz, r}: fixed spheres, copied     */
@@ -390,6 +391,8 @@ typedef struct vlb_request {
     uint32_t seed;          /* stochastic-rounding seed (vlb_set_rounding)           */
     double giesekus_alpha;  /* Giesekus mobility in [0, 1/2] (vlb_set_giesekus);
                                0 for Oldroyd-B                                       */
+    int32_t n_walls;        /* 0..63: walls with ids 1..n_walls move; copied          */
+    const double *wall_velocity; /* n_walls x 3: their velocities, as in vlb_create    */
 } vlb_request;
 
 typedef struct vlb_server_stats {

@@ -48,6 +48,7 @@ struct Request {
     std::vector<uint8_t> mask;
     vlb_params params{};
     double alpha = 0.0;  // Giesekus mobility (0: Oldroyd-B)
+    std::vector<double> walls;  // n_walls x 3 wall velocities
     uint32_t steps = 0;
     uint32_t seed = 0;
     int state = VLB_REQ_QUEUED;
@@ -67,6 +68,7 @@ struct Slot {
     float *f[2] = {nullptr, nullptr};
     float *tau[2] = {nullptr, nullptr};
     float *u = nullptr;
+    double *walls = nullptr;            // 63 x 3 wall velocities (device)
     vlb::StepArgs args[2]{};
     uint32_t target = 0;
     uint32_t nblocks = 0;
@@ -81,11 +83,14 @@ struct Quarantined {
     uint64_t offset, bytes, free_after;
 };
 
+// wall-velocity table of a solve: ids 1..63, three doubles each
+constexpr uint64_t kWallBytes = 64 * 3 * sizeof(double);
+
 uint64_t footprint(const vlb_dims &d)
 {
     const uint64_t N = static_cast<uint64_t>(d.nx) * d.ny * d.nz;
     const uint64_t P = round_up(N, kAlign);
-    return 2 * vlb::Q * P * 4 + 2 * 6 * P * 4 + 3 * P * 4 + round_up(N, kAlign);
+    return 2 * vlb::Q * P * 4 + 2 * 6 * P * 4 + 3 * P * 4 + round_up(N, kAlign) + kWallBytes;
 }
 
 }  // namespace
@@ -234,11 +239,15 @@ void make_args(vlb_server *srv, Slot &sl, const Request &rq)
         vlb::StepArgs &a = sl.args[par];
         a = vlb::StepArgs{};
         a.g = sl.g;
-        a.b.wall_vel = nullptr;
-        a.b.n_walls = 0;
+        bool walls_move = false;
+        for (double v : rq.walls)
+            walls_move = walls_move || v != 0.0;
+        a.b.wall_vel = sl.walls;
+        a.b.n_walls = static_cast<int32_t>(rq.walls.size() / 3);
         a.b.parts = nullptr;
         a.b.n_parts = 0;
-        a.b.moving = 0;
+        a.b.moving = walls_move ? 1 : 0;
+        a.b.walls_move = walls_move ? 1 : 0;
         a.mask = sl.mask;
         a.fin = sl.f[par];
         a.fout = sl.f[par ^ 1];
@@ -309,6 +318,7 @@ vlb_status admit(vlb_server *srv, Request &rq, bool &no_room)
     sl.tau[1] = sl.tau[0] + 6 * P;
     sl.u = sl.tau[1] + 6 * P;
     sl.mask = reinterpret_cast<uint8_t *>(sl.u + 3 * P);
+    sl.walls = reinterpret_cast<double *>(sl.mask + round_up(N, kAlign));
     const uint64_t K = static_cast<uint64_t>(srv->k_steps);
     sl.last_launch = srv->n_launched + (sl.target + K - 1) / K - 1;  // unused for target 0
     hipError_t e = hipMemcpyAsync(sl.mask, rq.mask.data(), N, hipMemcpyHostToDevice, srv->io);
@@ -319,6 +329,11 @@ vlb_status admit(vlb_server *srv, Request &rq, bool &no_room)
     }
     if (e == hipSuccess)
         e = hipMemsetAsync(sl.u, 0, 3 * P * 4, srv->io);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(sl.walls, 0, kWallBytes, srv->io);
+    if (e == hipSuccess && !rq.walls.empty())
+        e = hipMemcpyAsync(sl.walls, rq.walls.data(), rq.walls.size() * sizeof(double),
+                           hipMemcpyHostToDevice, srv->io);
     if (e == hipSuccess)
         e = vlb::launch_init_equilibrium(vlb::ST_F32, sl.g, sl.mask, nullptr, sl.f[0], 1.f, srv->io);
     if (e != hipSuccess) {
@@ -778,6 +793,11 @@ vlb_status vlb_server_submit(vlb_server *srv, const vlb_request *req, uint64_t *
         return sfail(srv, VLB_EINVAL, "vlb_server_submit: invalid parameters");
     if (!(req->giesekus_alpha >= 0.0 && req->giesekus_alpha <= 0.5))
         return sfail(srv, VLB_EINVAL, "vlb_server_submit: Giesekus alpha must lie in [0, 1/2]");
+    if (req->n_walls < 0 || req->n_walls > 63 || (req->n_walls > 0 && !req->wall_velocity))
+        return sfail(srv, VLB_EINVAL, "vlb_server_submit: n_walls must lie in 0..63 with velocities");
+    for (int i = 0; i < 3 * req->n_walls; ++i)
+        if (!std::isfinite(req->wall_velocity[i]))
+            return sfail(srv, VLB_EINVAL, "vlb_server_submit: non-finite wall velocity");
     if (footprint(d) > srv->budget)
         return sfail(srv, VLB_EBUSY, "vlb_server_submit: request exceeds the memory budget");
     Request rq;
@@ -855,6 +875,8 @@ vlb_status vlb_server_submit(vlb_server *srv, const vlb_request *req, uint64_t *
     }
     rq.params = req->params;
     rq.alpha = req->giesekus_alpha;
+    if (req->n_walls > 0)
+        rq.walls.assign(req->wall_velocity, req->wall_velocity + 3 * req->n_walls);
     rq.steps = static_cast<uint32_t>(req->n_steps);
     rq.seed = req->seed;
     rq.submitted = clock_type::now();

@@ -48,7 +48,8 @@ class vlb_request(ctypes.Structure):
     _fields_ = [("dims", vlb_dims), ("mask", ctypes.c_char_p), ("params", vlb_params),
                 ("n_spheres", ctypes.c_int32), ("spheres", ctypes.POINTER(ctypes.c_double)),
                 ("n_steps", ctypes.c_int64), ("seed", ctypes.c_uint32),
-                ("giesekus_alpha", ctypes.c_double)]
+                ("giesekus_alpha", ctypes.c_double), ("n_walls", ctypes.c_int32),
+                ("wall_velocity", ctypes.POINTER(ctypes.c_double))]
 
 
 class vlb_server_stats(ctypes.Structure):
@@ -639,7 +640,7 @@ def vlb_server_set_rounding(srv, mode="stochastic"):
 
 
 def vlb_server_submit(srv, shape, mask, periodic=(1, 1, 1), params=None, spheres=(), n_steps=1,
-                      seed=0x2009, giesekus_alpha=0.0):
+                      seed=0x2009, giesekus_alpha=0.0, wall_velocity=None):
     nx, ny, nz = shape
     m = np.ascontiguousarray(mask, dtype=np.uint8)
     if m.shape != (nz, ny, nx):
@@ -662,6 +663,11 @@ def vlb_server_submit(srv, shape, mask, periodic=(1, 1, 1), params=None, spheres
     req.n_steps = int(n_steps)
     req.seed = int(seed) & 0xFFFFFFFF
     req.giesekus_alpha = float(giesekus_alpha)
+    wv = None
+    if wall_velocity is not None and len(wall_velocity):
+        wv = np.ascontiguousarray(np.asarray(wall_velocity, dtype=np.float64).reshape(-1, 3))
+        req.n_walls = wv.shape[0]
+        req.wall_velocity = _dp(wv)
     ticket = ctypes.c_uint64()
     _scheck(lib().vlb_server_submit(srv, ctypes.byref(req), ctypes.byref(ticket)), srv)
     return ticket.value

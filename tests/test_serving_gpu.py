@@ -218,3 +218,46 @@ def test_submit_refuses_a_giesekus_alpha_outside_its_range():
             assert ei.value.status == vlb.VLB_EINVAL
     finally:
         vlb.vlb_server_destroy(srv)
+
+
+@pytest.mark.parametrize("shape", [(20, 18, 14), (64, 18, 20)])
+def test_served_solve_with_a_moving_wall_equals_plain_lattice(shape):
+    """A channel whose top wall (id 2) slides in x and z, served per cell
+    (20 wide) and tiled (64 wide), alone and beside a solve with walls at
+    rest: the bits of a plain lattice created with the same wall velocities."""
+    nx, ny, nz = shape
+    mask = inputs.channel_mask(shape, wall_axes=(1,), top_id=2)
+    walls = [[0.0, 0.0, 0.0], [3e-3, 0.0, -1e-3]]
+    r = dict(shape=shape, mask=mask, periodic=(1, 0, 1),
+             params=dict(eta=1 / 3, beta=0.4, lambda_p=80.0, magic=3 / 16, body_force=(0, 0, 0)),
+             spheres=[[nx / 2 - 0.3, ny / 2 + 0.2, nz / 2, 3.0]], n_steps=120, seed=4242)
+    other = make_request(8, (16, 18, 12), 90, 1)
+    log(f"[serving] moving lid {shape}")
+    srv = vlb.vlb_server_create(GB, 4, 10)
+    try:
+        t = vlb.vlb_server_submit(srv, shape, mask, (1, 0, 1), r["params"], r["spheres"],
+                                  r["n_steps"], r["seed"], wall_velocity=walls)
+        t2 = submit(srv, other)
+        for _ in range(1000):
+            vlb.vlb_server_pump(srv, wait=True)
+            if vlb.vlb_server_poll(srv, t) == "done" and vlb.vlb_server_poll(srv, t2) == "done":
+                break
+        us, ts, _ = vlb.vlb_server_result(srv, t, shape)
+        with pytest.raises(vlb.VlbError) as ei:
+            vlb.vlb_server_submit(srv, shape, mask, (1, 0, 1), r["params"], (), 10, 1,
+                                  wall_velocity=[[np.nan, 0, 0]])
+        assert ei.value.status == vlb.VLB_EINVAL
+    finally:
+        vlb.vlb_server_destroy(srv)
+    L = vlb.Lattice(shape, mask, (1, 0, 1), walls)
+    L.set_params(**r["params"])
+    L.add_sphere(center=tuple(r["spheres"][0][:3]), radius=r["spheres"][0][3])
+    L.set_rounding("stochastic", r["seed"])
+    L.set_check_interval(0)
+    L.init_equilibrium()
+    L.step(r["n_steps"])
+    np.testing.assert_array_equal(L.velocity(), us)
+    np.testing.assert_array_equal(L.stress(), ts)
+    # the lid drags the fluid next to it
+    assert us[0, :, ny - 2, :].mean() > 0
+    L.close()
