@@ -527,6 +527,7 @@ vlb_status create_impl(const vlb_dims *dims, const uint8_t *mask, const double *
         lat->g.per[a] = dims->periodic[a] ? 1 : 0;
     lat->g.N = static_cast<uint32_t>(N);
     lat->g.plane = round_up(N, kPlaneAlign) + plane_pad();
+    vlb::set_divisors(lat->g);
     lat->storage = storage;
     lat->scale = default_scale(storage);
     lat->inv_scale = 1.f / lat->scale;

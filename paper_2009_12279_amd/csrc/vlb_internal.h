@@ -54,7 +54,31 @@ struct Geom {
     int32_t per[3];
     uint32_t N;        // cells
     uint64_t plane;    // elements between consecutive planes of a field
+    // division of a cell index by nx and by ny (set_divisors): multiplier and
+    // the two shifts (low and second byte)
+    uint32_t mx = 0, my = 0, shx = 0, shy = 0;
 };
+
+// Constants of the unsigned division by an invariant divisor d, 1 <= d < 2^31
+// (Granlund and Montgomery, "Division by invariant integers using
+// multiplication", 1994): with l = ceil(log2 d), m = floor(2^32 (2^l - d) / d)
+// + 1, s1 = min(l, 1), s2 = max(l - 1, 0), every 32-bit n has
+// n / d = (t + ((n - t) >> s1)) >> s2, t = (m n) >> 32.
+inline void divisor_constants(uint32_t d, uint32_t &m, uint32_t &sh)
+{
+    int l = 0;
+    while ((uint64_t(1) << l) < d)
+        ++l;
+    m = static_cast<uint32_t>(((uint64_t(1) << 32) * ((uint64_t(1) << l) - d)) / d + 1);
+    const int s1 = l < 1 ? l : 1, s2 = l > 1 ? l - 1 : 0;
+    sh = static_cast<uint32_t>(s1) | (static_cast<uint32_t>(s2) << 8);
+}
+
+inline void set_divisors(Geom &g)
+{
+    divisor_constants(static_cast<uint32_t>(g.nx), g.mx, g.shx);
+    divisor_constants(static_cast<uint32_t>(g.ny), g.my, g.shy);
+}
 
 struct Bound {
     const double *wall_vel;  // [n_walls][3]

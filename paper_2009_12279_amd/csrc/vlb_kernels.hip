@@ -262,12 +262,20 @@ struct Nbr {
     }
 };
 
+// n / d from the constants of divisor_constants
+__device__ __forceinline__ uint32_t div_by(uint32_t n, uint32_t m, uint32_t sh)
+{
+    const uint32_t t = __umulhi(m, n);
+    return (t + ((n - t) >> (sh & 0xffu))) >> (sh >> 8);
+}
+
 __device__ __forceinline__ void coords(const Geom &g, uint32_t n, int &x, int &y, int &z)
 {
-    x = static_cast<int>(n % static_cast<uint32_t>(g.nx));
-    const uint32_t t = n / static_cast<uint32_t>(g.nx);
-    y = static_cast<int>(t % static_cast<uint32_t>(g.ny));
-    z = static_cast<int>(t / static_cast<uint32_t>(g.ny));
+    const uint32_t t = div_by(n, g.mx, g.shx);
+    x = static_cast<int>(n - t * static_cast<uint32_t>(g.nx));
+    const uint32_t q = div_by(t, g.my, g.shy);
+    y = static_cast<int>(t - q * static_cast<uint32_t>(g.ny));
+    z = static_cast<int>(q);
 }
 
 // displacement from the particle centre to a cell, minimum image on periodic axes
@@ -482,6 +490,10 @@ __device__ __forceinline__ Geom geom_copy(const G &g)
     r.per[2] = g.per[2];
     r.N = g.N;
     r.plane = g.plane;
+    r.mx = g.mx;
+    r.my = g.my;
+    r.shx = g.shx;
+    r.shy = g.shy;
     return r;
 }
 template <class B>
@@ -1297,7 +1309,7 @@ __device__ __forceinline__ void fv_tile_block(const A &a, uint32_t b, uint32_t z
         const bool more = z + 1 < z1;
         float NN[FV_NV];
         if (more)
-            fv_load(a, own_xy + wrap_coord(z + 2, nz) * nxy, NN);
+            fv_load(a, own_xy + static_cast<uint32_t>(z + 2 < nz ? z + 2 : z + 2 - nz) * nxy, NN);
         __syncthreads();
         if (in_tile && C[9] == 0.f) {
             const float u0[3] = {C[0], C[1], C[2]};

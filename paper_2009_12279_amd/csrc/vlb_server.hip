@@ -305,6 +305,7 @@ vlb_status admit(vlb_server *srv, Request &rq, bool &no_room)
         sl.g.per[a] = rq.dims.periodic[a] ? 1 : 0;
     sl.g.N = static_cast<uint32_t>(N);
     sl.g.plane = round_up(N, kAlign);
+    vlb::set_divisors(sl.g);
     sl.offset = offset;
     sl.bytes = bytes;
     sl.target = rq.steps;
