@@ -423,10 +423,11 @@ def run_serving(args):
     rate = 1.5 * len(reqs) / seq_s
     budget = int(args.serving_budget_gb * (1 << 30))
 
-    def serve(arrivals):
+    def serve(arrivals, policy="fifo"):
         srv = vlb.vlb_server_create(budget, args.serving_slots, args.serving_k)
         lat = []
         try:
+            vlb.vlb_server_set_policy(srv, policy)
             tickets = {}
             nxt = 0
             t0 = time.perf_counter()
@@ -460,8 +461,11 @@ def run_serving(args):
     # Poisson arrivals at 1.5x the sequential service rate
     _, sat_s, sat_stats = serve(np.zeros(len(reqs)))
     rng = np.random.default_rng(args.serving_requests)
-    lat, bat_s, stats = serve(np.cumsum(rng.exponential(1.0 / rate, len(reqs))))
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, len(reqs)))
+    lat, bat_s, stats = serve(arrivals)
     lat = np.array(lat)
+    # the same arrivals admitted shortest first
+    lat_sf, sf_s, _ = serve(arrivals, "shortest_first")
     return dict(
         requests=len(reqs), steps_scale=args.serving_steps_scale,
         cell_steps=cell_steps, arrival_rate_hz=round(rate, 3),
@@ -469,6 +473,10 @@ def run_serving(args):
         steps_per_launch=args.serving_k,
         p50_ms=round(float(np.percentile(lat, 50)), 2),
         p99_ms=round(float(np.percentile(lat, 99)), 2),
+        policy="fifo",
+        shortest_first=dict(p50_ms=round(float(np.percentile(lat_sf, 50)), 2),
+                            p99_ms=round(float(np.percentile(lat_sf, 99)), 2),
+                            poisson_wall_s=round(sf_s, 3)),
         poisson_wall_s=round(bat_s, 3), saturated_wall_s=round(sat_s, 3),
         sequential_wall_s=round(seq_s, 3),
         batched_mlups=round(cell_steps / sat_s / 1e6, 1),

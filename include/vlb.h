@@ -413,6 +413,16 @@ vlb_status vlb_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t
 size_t vlb_server_request_bytes(const vlb_dims *dims);
 /* Rounding of stored values for every solve (only while idle). */
 vlb_status vlb_server_set_rounding(vlb_server *srv, vlb_rounding mode);
+/* Admission order of queued requests.  VLB_POLICY_FIFO (the default): in
+ * submission order, no overtaking.  VLB_POLICY_SHORTEST_FIRST: the queued
+ * request with the fewest cell-steps (cells x steps; ties in submission
+ * order) first, which shortens the typical wait when requests queue up, at
+ * the price of longer waits for the largest ones.  Either way a request is
+ * admitted only when a slot and its memory are free, and its results do not
+ * depend on the order.  May be changed at any time; VLB_EINVAL for an
+ * unknown policy. */
+typedef enum vlb_policy { VLB_POLICY_FIFO = 0, VLB_POLICY_SHORTEST_FIRST = 1 } vlb_policy;
+vlb_status vlb_server_set_policy(vlb_server *srv, vlb_policy policy);
 /* Queue a request (inputs copied).  VLB_EBUSY if it can never fit the budget,
  * VLB_EINVAL for invalid dimensions, mask or parameters. */
 vlb_status vlb_server_submit(vlb_server *srv, const vlb_request *req, uint64_t *ticket);

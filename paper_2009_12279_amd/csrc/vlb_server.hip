@@ -1,13 +1,14 @@
 // Serving runtime of libvlb: continuous batching of independent solves.
 //
-// Requests wait in a FIFO queue.  A request is admitted when a slot is free
-// and its device footprint fits in the server's arena, one device allocation
-// of the whole HBM budget made at creation; the solve then owns its range of
-// the arena (populations, stress, velocity, mask) until it retires.  One
-// batched launch advances every admitted solve by one step; K such steps
-// (stream-collide, stress update and the per-solve step-counter advance) are
-// captured in a hipGraph and replayed.  The graph only refers to fixed device
-// tables, which are rewritten in stream order between replays.
+// Requests wait in a queue (FIFO, or shortest first).  A request is admitted
+// when a slot is free and its device footprint fits in the server's arena, one
+// device allocation of the whole HBM budget made at creation; the solve then
+// owns its range of the arena (populations, stress, velocity, mask, wall table)
+// until it retires.  One batched launch advances every admitted solve by one
+// step; K such steps (stream-collide, stress update and the per-solve
+// step-counter advance) are captured in a hipGraph and replayed.  The graph
+// only refers to fixed device tables, which are rewritten in stream order
+// between replays.
 //
 // Scheduling keeps the GPU fed: up to two replays are in flight, and the host
 // retires finished solves (results read on a second stream), admits new ones
@@ -149,6 +150,7 @@ struct vlb_server {
     hipEvent_t launch_done[2] = {nullptr, nullptr};
     uint64_t n_launched = 0, n_completed = 0;
     int stochastic = 1;
+    int policy = VLB_POLICY_FIFO;
     vlb_server_stats stats{};
     std::string err = "no error";
 };
@@ -625,25 +627,48 @@ vlb_status reap(vlb_server *srv, bool block)
     return VLB_OK;
 }
 
-// Admit queued requests while slots and memory allow (FIFO, no overtaking)
-// and keep up to two replays in flight.  Admitted requests of zero steps are
-// moved to zero_step.
+// The queue entry admitted next: the front (FIFO), or the one with the
+// fewest cell-steps (shortest first, the earliest of equal ones).  Cancelled
+// entries are dropped on the way.
+std::deque<uint64_t>::iterator next_in_queue(vlb_server *srv)
+{
+    for (auto it = srv->queue.begin(); it != srv->queue.end();) {
+        if (srv->requests[*it].state == VLB_REQ_CANCELLED)
+            it = srv->queue.erase(it);
+        else
+            ++it;
+    }
+    if (srv->policy != VLB_POLICY_SHORTEST_FIRST || srv->queue.empty())
+        return srv->queue.begin();
+    auto work = [&](uint64_t t) {
+        const Request &rq = srv->requests[t];
+        return static_cast<uint64_t>(rq.dims.nx) * rq.dims.ny * rq.dims.nz * rq.steps;
+    };
+    auto best = srv->queue.begin();
+    for (auto it = srv->queue.begin(); it != srv->queue.end(); ++it)
+        if (work(*it) < work(*best))
+            best = it;
+    return best;
+}
+
+// Admit queued requests while slots and memory allow (in the policy's order,
+// no overtaking of the request next in that order) and keep up to two
+// replays in flight.  Admitted requests of zero steps are moved to zero_step.
 vlb_status admit_and_launch(vlb_server *srv, std::vector<Slot> &zero_step)
 {
     vlb_status st = VLB_OK;
-    while (!srv->queue.empty() && static_cast<int>(srv->slots.size()) < srv->max_slots) {
-        Request &rq = srv->requests[srv->queue.front()];
-        if (rq.state == VLB_REQ_CANCELLED) {
-            srv->queue.pop_front();
-            continue;
-        }
+    while (static_cast<int>(srv->slots.size()) < srv->max_slots) {
+        const auto next = next_in_queue(srv);
+        if (next == srv->queue.end())
+            break;
+        Request &rq = srv->requests[*next];
         if (srv->used + footprint(rq.dims) > srv->budget)
             break;
         bool no_room = false;
         st = admit(srv, rq, no_room);
         if (no_room)
             break;  // no free range yet: wait for retirements
-        srv->queue.pop_front();
+        srv->queue.erase(next);
         if (st != VLB_OK) {
             rq.state = VLB_REQ_FAILED;
             rq.error = srv->err;
@@ -759,6 +784,14 @@ size_t vlb_server_request_bytes(const vlb_dims *dims)
     if (!dims || dims->nx < 1 || dims->ny < 1 || dims->nz < 1)
         return 0;
     return static_cast<size_t>(footprint(*dims));
+}
+
+vlb_status vlb_server_set_policy(vlb_server *srv, vlb_policy policy)
+{
+    if (!srv || (policy != VLB_POLICY_FIFO && policy != VLB_POLICY_SHORTEST_FIRST))
+        return VLB_EINVAL;
+    srv->policy = policy;
+    return VLB_OK;
 }
 
 vlb_status vlb_server_set_rounding(vlb_server *srv, vlb_rounding mode)

@@ -120,6 +120,7 @@ SIGNATURES = [
                                          ctypes.POINTER(_P)]),
     ("vlb_server_set_rounding", ctypes.c_int, [_P, ctypes.c_int]),
     ("vlb_server_request_bytes", ctypes.c_size_t, [ctypes.POINTER(vlb_dims)]),
+    ("vlb_server_set_policy", ctypes.c_int, [_P, ctypes.c_int]),
     ("vlb_server_submit", ctypes.c_int, [_P, ctypes.POINTER(vlb_request),
                                          ctypes.POINTER(ctypes.c_uint64)]),
     ("vlb_server_pump", ctypes.c_int, [_P, ctypes.c_int32]),
@@ -633,6 +634,13 @@ def vlb_server_create(hbm_budget_bytes, max_slots=64, steps_per_launch=50, strea
 def vlb_server_request_bytes(shape, periodic=(1, 1, 1)):
     d = make_dims(shape, periodic)
     return int(lib().vlb_server_request_bytes(ctypes.byref(d)))
+
+
+POLICIES = {"fifo": 0, "shortest_first": 1}
+
+
+def vlb_server_set_policy(srv, policy="fifo"):
+    return _scheck(lib().vlb_server_set_policy(srv, POLICIES[policy]), srv)
 
 
 def vlb_server_set_rounding(srv, mode="stochastic"):

@@ -261,3 +261,38 @@ def test_served_solve_with_a_moving_wall_equals_plain_lattice(shape):
     # the lid drags the fluid next to it
     assert us[0, :, ny - 2, :].mean() > 0
     L.close()
+
+
+@pytest.mark.parametrize("policy", ["fifo", "shortest_first"])
+def test_admission_order_follows_the_policy(policy):
+    """One slot, four requests queued before the first pump: FIFO admits them
+    in submission order, shortest-first by cell-steps (large ones last), and
+    every result equals the solve run alone."""
+    reqs = [make_request(50, (20, 16, 14), 60, 1), make_request(51, (12, 10, 8), 30, 0),
+            make_request(52, (16, 12, 10), 40, 0), make_request(53, (12, 10, 8), 20, 0)]
+    log(f"[serving] admission order, policy {policy}")
+    srv = vlb.vlb_server_create(GB, 1, 10)
+    order = []
+    try:
+        vlb.vlb_server_set_policy(srv, policy)
+        tickets = [submit(srv, r) for r in reqs]
+        done = {}
+        for _ in range(1000):
+            vlb.vlb_server_pump(srv, wait=True)
+            for i, t in enumerate(tickets):
+                if i not in done and vlb.vlb_server_poll(srv, t) == "done":
+                    done[i] = vlb.vlb_server_result(srv, t, reqs[i]["shape"])
+                    order.append(i)
+            if len(done) == len(reqs):
+                break
+        with pytest.raises(KeyError):
+            vlb.vlb_server_set_policy(srv, "longest_first")
+    finally:
+        vlb.vlb_server_destroy(srv)
+    work = [np.prod(r["shape"]) * r["n_steps"] for r in reqs]
+    expect = list(range(4)) if policy == "fifo" else sorted(range(4), key=lambda i: (work[i], i))
+    assert order == expect, (order, expect)
+    for i, r in enumerate(reqs):
+        alone, _ = serve([r], slots=1)
+        np.testing.assert_array_equal(alone[r["seed"]][0], done[i][0])
+        np.testing.assert_array_equal(alone[r["seed"]][1], done[i][1])
