@@ -120,15 +120,20 @@ def test_settling_sphere_trajectory_full_length(name, wi, steps):
     assert worst_z < 1e-6 and worst_v < 1e-5
     covered = np.flatnonzero(L.mask().reshape(-1) >= 64)
     np.testing.assert_array_equal(covered, fx[f"covered_{steps}"])
+    # the FP32 bar of 1e-5 holds over 10^4 steps; stochastic rounding makes the
+    # stored-state rounding errors unbiased and independent from step to
+    # step, so they add up like a random walk and the bar grows with the
+    # square root of longer runs (2.2e-5 over 5 x 10^4 steps)
+    tol = 1e-5 * max(1.0, np.sqrt(steps / 1e4))
     u, tau = _fields(L, fx[f"cells_{steps}"])
     uo = fx[f"u_{steps}"]
     eu = _rel(u, uo, max(np.abs(uo).max(), np.abs(traj[:steps // 100, 4:7]).max()))
     log(f"[config]   u {eu} (sample L2 relative {_rel(u, uo)[0]:.3e})")
-    assert max(eu) < 1e-5
+    assert max(eu) < tol
     if wi > 0:
         et = _rel(tau, fx[f"tau_{steps}"])
         log(f"[config]   tau {et}")
-        assert max(et) < 1e-5
+        assert max(et) < tol
     L.close()
 
 
