@@ -187,7 +187,7 @@ def run_gpu(args, law=None, repeats=0):
                 step_achieved=step_achieved, alg=alg, health=health)
 
 
-def _time_lattice(lat, args, stream):
+def _time_lattice(lat, args, stream, particles=True):
     """ms per step (HIP events on the lattice's stream) and per-kernel-family
     times of a second timed pass."""
     import torch
@@ -205,9 +205,49 @@ def _time_lattice(lat, args, stream):
     lat.set_timing(True)
     lat.step(args.steps)
     torch.cuda.synchronize()
-    k_ms = kernel_times(lat, particles=True)
+    k_ms = kernel_times(lat, particles=particles)
     lat.set_timing(False)
     return ms, {k: round(v, 5) for k, v in k_ms.items()}
+
+
+def run_fixed_configs(args):
+    """The smaller fixed-geometry workloads, timed like the others: the
+    4 x 64 x 4 Oldroyd-B channel (walls in y, g = 1e-6, lambda_p = 1000,
+    BGK) and the 128 x 64 x 64 duct (walls in y and z, fixed sphere r = 8 at
+    the centre, g = 1e-6, beta = 0.5) at lambda_p = 100, 1000 and 5000."""
+    import torch
+
+    from paper_2009_12279_amd import inputs, vlb
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream(0)
+    out = {}
+    shape = (4, 64, 4)
+    lat = vlb.Lattice(shape, inputs.channel_mask(shape, wall_axes=(1,)), (1, 0, 1),
+                      stream=stream.cuda_stream)
+    lat.set_params(eta=1.0 / 3.0, beta=0.5, lambda_p=1000.0, magic=-1.0,
+                   body_force=(1e-6, 0.0, 0.0))
+    lat.set_check_interval(0)
+    lat.init_equilibrium()
+    ms, k_ms = _time_lattice(lat, args, stream, particles=False)
+    lat.close()
+    out["channel_4x64x4"] = dict(ms_per_step=round(ms, 4),
+                                 mlups=round(1024 / (ms * 1e-3) / 1e6, 1), kernel_ms=k_ms)
+    shape = (128, 64, 64)
+    N = int(np.prod(shape))
+    for lam in (100.0, 1000.0, 5000.0):
+        lat = vlb.Lattice(shape, inputs.channel_mask(shape, wall_axes=(1, 2)), (1, 0, 0),
+                          stream=stream.cuda_stream)
+        lat.set_params(eta=1.0 / 3.0, beta=0.5, lambda_p=lam, magic=3.0 / 16.0,
+                       body_force=(1e-6, 0.0, 0.0))
+        lat.add_sphere(center=(63.5, 31.5, 31.5), radius=8.0)
+        lat.set_check_interval(0)
+        lat.init_equilibrium()
+        ms, k_ms = _time_lattice(lat, args, stream, particles=False)
+        lat.close()
+        out[f"duct_128x64x64_lambda{lam:.0f}"] = dict(
+            ms_per_step=round(ms, 4), mlups=round(N / (ms * 1e-3) / 1e6, 1), kernel_ms=k_ms)
+    return out
 
 
 def run_moving(args):
@@ -504,7 +544,8 @@ def main():
     ap.add_argument("--serving-k", type=int, default=50)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-moving", action="store_true",
-                    help="skip the moving-boundary (settling sphere) measurements")
+                    help="skip the moving-boundary (settling sphere) and the smaller "
+                         "fixed-geometry (channel, duct) measurements")
     ap.add_argument("--no-storage-variants", action="store_true",
                     help="skip timing the same workload with FP16 and BF16 population storage")
     ap.add_argument("--no-law-variants", action="store_true",
@@ -564,6 +605,7 @@ def main():
                              mlups=round(v["mlups"], 1),
                              kernel_ms={k: round(x, 5) for k, x in v["kernels"].items()})
     moving = None if args.no_moving else run_moving(args)
+    fixed = None if args.no_moving else run_fixed_configs(args)
     serving = None if args.no_serving else run_serving(args)
     cpu = None
     if rank == 0 and not args.no_cpu_baseline:
@@ -627,6 +669,7 @@ def main():
         "storage_variants": variants,
         "law_variants": laws,
         "moving_particle": moving,
+        "fixed_geometry": fixed,
         "serving": serving,
     }
     print(json.dumps(line), flush=True)
